@@ -1,0 +1,209 @@
+/*
+ * cagra.h -- C ABI of the MI355X (gfx950) CSR-segmenting library.
+ *
+ * Implements the pull-direction edge traversal of "Making Caches Work for
+ * Graph Analytics" (arXiv 1608.01362): CSR segmenting preprocessing
+ * (Section 3.1), per-segment gather into sequential buffers (Section 3.2),
+ * the cache-aware merge (Section 3.3), and the PageRank / label-propagation
+ * iterations built from them (Section 4 programming abstraction; Section 6
+ * applications).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the parameter name starts with host_.
+ *   - The caller owns all memory; the library never allocates or frees device
+ *     memory. Sizes of caller buffers are given by the *_bytes helpers.
+ *   - Work is enqueued on `stream` and is asynchronous, except where a function
+ *     states that it synchronizes the stream.
+ *   - Every argument is validated on the host before any HIP call; invalid
+ *     arguments return a negative status and enqueue nothing. A description of
+ *     the last error on the calling thread is available from cagra_last_error().
+ *   - All results are deterministic: repeated calls on the same inputs produce
+ *     bit-identical outputs.
+ *   - Graphs are in-edge CSR ("CSC"): the sources of the edges u->v are
+ *     in_sources[in_offsets[v] .. in_offsets[v+1]), strictly ascending, with no
+ *     self-loops and no duplicates; E < 2^31.
+ */
+#ifndef CAGRA_H
+#define CAGRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CAGRA_ABI_VERSION 1
+
+typedef enum {
+    CAGRA_OK = 0,
+    CAGRA_E_INVALID = -1,   /* null pointer, bad size, unknown enum value */
+    CAGRA_E_OVERFLOW = -2,  /* a count would not fit in int32 */
+    CAGRA_E_CAPACITY = -3,  /* parameter beyond a kernel capacity (LDS bytes, segment count) */
+    CAGRA_E_BUFFER = -4,    /* workspace too small or misaligned */
+    CAGRA_E_HIP = -5        /* a HIP runtime call or kernel launch failed */
+} cagra_status;
+
+/* Element types of vertex values gathered by the segment processing step. */
+enum { CAGRA_F32 = 0, CAGRA_BF16 = 1, CAGRA_I32 = 2 };
+
+/* Combine operators (the paper's user-supplied Merge, Section 4). */
+enum {
+    CAGRA_SUM_F32 = 0,       /* float sum, identity 0 */
+    CAGRA_MIN_I32 = 1,       /* int32 minimum, identity INT32_MAX */
+    CAGRA_SUM_F32_COMP = 2   /* float sum with Neumaier compensation (merge only) */
+};
+
+/* Vertices staged per segment: a segment is processed out of LDS when
+   N * element bytes <= CAGRA_LDS_BYTES, otherwise its gathers go through the
+   cache hierarchy (L2 / Infinity Cache sized segments). */
+#define CAGRA_LDS_BYTES 163840
+/* Waves (64 lanes) that share one staged segment in the gather kernel. */
+#define CAGRA_TILE_WAVES 16
+
+typedef struct {
+    int32_t V;                  /* vertices */
+    int64_t E;                  /* edges, < 2^31 */
+    const int32_t *in_offsets;  /* [V+1] */
+    const int32_t *in_sources;  /* [E] */
+    const int32_t *out_degree;  /* [V] out-degree of each vertex (for PageRank) */
+} cagra_graph;
+
+/*
+ * Segmented graph (Section 3.1). Subgraph s holds the in-edges whose source is
+ * in [s*N, min((s+1)*N, V)); its rows are the distinct destinations of those
+ * edges in ascending order, and a row's edges keep ascending source order.
+ * All subgraphs are concatenated, s ascending. Q = total number of rows.
+ *
+ *   seg_row_begin[k+1]   first row of subgraph s; seg_row_begin[k] = Q
+ *   row_ptr[Q+1]         first edge of each row; row_ptr[Q] = E
+ *   row_dst[Q]           global destination of each row (the paper's idxMap)
+ *   edge_src[E]          local source index u - s*N; bit 31 is set on the first
+ *                        edge of every row (mask with 0x7fffffff for the index)
+ *   block_ptr[(nb+1)*k]  merge block index: block_ptr[b*k + s] = first row of
+ *                        subgraph s whose destination is >= b*B (Section 3.3's
+ *                        block starts; block b of subgraph s ends at
+ *                        block_ptr[(b+1)*k + s])
+ *   tile_edge[ntiles+1]  gather work units: tile t covers edges
+ *                        [tile_edge[t], tile_edge[t+1]), starts and ends on row
+ *                        boundaries and lies within subgraph tile_seg[t]
+ *   tile_seg[ntiles]
+ *   tile_span_row[ntiles*CAGRA_TILE_WAVES]  for each tile, the first row that
+ *                        starts at or after each wave's share of the tile
+ *
+ * edge_src must be 16-byte aligned. All arrays are caller-allocated device
+ * memory of the sizes the query call reports.
+ */
+typedef struct {
+    /* parameters (set by the caller before the query call) */
+    int32_t N;            /* vertices per segment, >= 1 */
+    int32_t B;            /* merge block size in vertices, 1 <= B <= cagra_max_merge_block() */
+    int32_t tile_edges;   /* nominal edges per gather tile, >= 64 */
+    /* sizes (filled by the query call) */
+    int32_t V, k, nb, ntiles;
+    int64_t E, Q;
+    size_t build_workspace_bytes;
+    /* device arrays */
+    int32_t *seg_row_begin;
+    int32_t *row_ptr;
+    int32_t *row_dst;
+    int32_t *edge_src;
+    int32_t *block_ptr;
+    int32_t *tile_edge;
+    int32_t *tile_seg;
+    int32_t *tile_span_row;
+} cagra_segments;
+
+int cagra_abi_version(void);
+const char *cagra_status_string(int status);
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char *cagra_last_error(void);
+/* Largest merge block B accepted (LDS capacity of the merge kernel). */
+int32_t cagra_max_merge_block(void);
+
+/* Device workspace needed by the query call of cagra_build_segments. */
+size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
+
+/*
+ * Section 3.1 preprocessing on the GPU. Two calls:
+ *  1. Query: seg->N, seg->B, seg->tile_edges set, seg->row_dst == NULL,
+ *     workspace >= cagra_query_workspace_bytes(). Counts rows and per-segment
+ *     edges, SYNCHRONIZES the stream, and fills seg->{V,E,k,nb,Q,ntiles,
+ *     build_workspace_bytes}.
+ *  2. Build: every array of *seg allocated at the reported sizes, workspace >=
+ *     seg->build_workspace_bytes. Fills all arrays; asynchronous.
+ * Requirements: k = ceil(V/N) <= 32768; CSC as described at the top of this file.
+ */
+cagra_status cagra_build_segments(const cagra_graph *g, cagra_segments *seg, void *workspace,
+                                  size_t workspace_bytes, hipStream_t stream);
+
+/* Device workspace needed by the per-iteration calls below (FP64 partial sums). */
+size_t cagra_iter_workspace_bytes(const cagra_segments *seg);
+
+/*
+ * Segment processing (Section 3.2) on its own: for every row r of every
+ * subgraph s, partial[r] = op over the row's edges of values[s*N + local src].
+ *   op CAGRA_SUM_F32: values are CAGRA_F32 or CAGRA_BF16 (value_type), partial is float[Q]
+ *   op CAGRA_MIN_I32: values are CAGRA_I32, partial is int32[Q]
+ * Segments with N * element bytes <= CAGRA_LDS_BYTES are staged in LDS.
+ */
+cagra_status cagra_segment_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                                  void *partial, hipStream_t stream);
+
+/*
+ * Cache-aware merge (Section 3.3): out[v] = op over subgraphs s (ascending
+ * within fixed groups of subgraphs) of the buffer entries whose row_dst is v;
+ * vertices without entries get the identity. op CAGRA_SUM_F32 or
+ * CAGRA_SUM_F32_COMP (partial/out float) or CAGRA_MIN_I32 (int32).
+ */
+cagra_status cagra_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out,
+                         hipStream_t stream);
+
+/*
+ * PageRank start: contrib_out[v] = rank[v] / out_degree[v] (0 where the
+ * out-degree is 0) stored as contrib_type (CAGRA_F32 or CAGRA_BF16, round to
+ * nearest even); scalars_out[0] = dangling mass sum_{out_degree=0} rank (FP64),
+ * scalars_out[1] = 0, scalars_out[2] = sum of rank (FP64), scalars_out[3] = 0.
+ */
+cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
+                                 double *scalars_out, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream);
+
+/*
+ * One PageRank iteration through segmenting (Section 4 PageRank: EdgeMap with
+ * a summing EdgeUpdate and Merge, then VertexMap), normalized with teleport and
+ * uniform redistribution of the dangling mass:
+ *   rank_out[v] = (1-d)/V + d * ( sum_{u->v} contrib_in[u] + scalars_in[0]/V )
+ *   contrib_out[v] = rank_out[v] / out_degree[v] (0 if out_degree is 0)
+ *   scalars_out[0] = dangling mass of rank_out, scalars_out[1] = ||rank_out - rank_in||_1,
+ *   scalars_out[2] = sum of rank_out, scalars_out[3] = 0   (all FP64)
+ * partial is float[Q] scratch for the per-subgraph buffers. The merge adds the
+ * FP32 buffer values exactly (each rounded to a multiple of 2^-56 and summed
+ * as int64), so its result does not depend on the order of the additions;
+ * buffer sums must stay below 64 in magnitude (true for rank vectors that sum
+ * to at most 1). contrib_in is read with contrib_type, contrib_out written with
+ * it. scalars_in must not alias scalars_out. Requires
+ * 8*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES.
+ */
+cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                 int32_t contrib_type, const float *rank_in,
+                                 const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
+                                 void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream);
+
+/*
+ * One synchronous min-label propagation step on a segmented undirected graph
+ * (both edge directions present):
+ *   labels_out[v] = min(labels_in[v], min over in-neighbours u of labels_in[u])
+ * partial is int32[Q] scratch; *changed_out (device int32) = number of v whose
+ * label changed.
+ */
+cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,
+                                  int32_t *labels_out, int32_t *changed_out, void *workspace,
+                                  size_t workspace_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAGRA_H */

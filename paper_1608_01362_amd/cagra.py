@@ -1,0 +1,320 @@
+"""ctypes binding of libcagra.so (include/cagra.h), plus the iteration driver.
+
+Argument marshalling only: every step of the segmented traversal runs in the
+library's HIP kernels. PyTorch provides device memory and the stream. The
+library is required: importing works without it, but every call raises if
+libcagra.so is missing (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcagra.so")
+
+# enums of include/cagra.h
+OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_BUFFER, E_HIP = 0, -1, -2, -3, -4, -5
+F32, BF16, I32 = 0, 1, 2
+SUM_F32, MIN_I32, SUM_F32_COMP = 0, 1, 2
+LDS_BYTES = 163840
+TILE_WAVES = 16
+
+_c_i32, _c_i64, _c_size, _c_vp, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
+
+
+class CGraph(ctypes.Structure):
+    _fields_ = [("V", _c_i32), ("E", _c_i64), ("in_offsets", _c_vp), ("in_sources", _c_vp), ("out_degree", _c_vp)]
+
+
+class CSegments(ctypes.Structure):
+    _fields_ = [("N", _c_i32), ("B", _c_i32), ("tile_edges", _c_i32),
+                ("V", _c_i32), ("k", _c_i32), ("nb", _c_i32), ("ntiles", _c_i32),
+                ("E", _c_i64), ("Q", _c_i64), ("build_workspace_bytes", _c_size),
+                ("seg_row_begin", _c_vp), ("row_ptr", _c_vp), ("row_dst", _c_vp), ("edge_src", _c_vp),
+                ("block_ptr", _c_vp), ("tile_edge", _c_vp), ("tile_seg", _c_vp), ("tile_span_row", _c_vp)]
+
+
+EXPORTS = [
+    "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
+    "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
+    "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
+    "cagra_labelprop_iter",
+]
+
+
+class CagraError(RuntimeError):
+    def __init__(self, status: int, fn: str, detail: str):
+        super().__init__(f"{fn} -> {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcagra.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        GP, SP, st = ctypes.POINTER(CGraph), ctypes.POINTER(CSegments), _c_vp
+        sig = {
+            "cagra_abi_version": ([], ctypes.c_int),
+            "cagra_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "cagra_last_error": ([], ctypes.c_char_p),
+            "cagra_max_merge_block": ([], _c_i32),
+            "cagra_query_workspace_bytes": ([_c_i32, _c_i64, _c_i32], _c_size),
+            "cagra_build_segments": ([GP, SP, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_iter_workspace_bytes": ([SP], _c_size),
+            "cagra_segment_gather": ([SP, _c_i32, _c_i32, _c_vp, _c_vp, st], ctypes.c_int),
+            "cagra_merge": ([SP, _c_i32, _c_vp, _c_vp, st], ctypes.c_int),
+            "cagra_pagerank_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_pagerank_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                     _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, fn: str):
+    if status != OK:
+        raise CagraError(status, fn, lib().cagra_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the segmented traversal runs only on the GPU")
+    return torch.device("cuda")
+
+
+# --------------------------------------------------------------------------- graph and segments
+
+@dataclass
+class DeviceGraph:
+    V: int
+    E: int
+    in_offsets: object
+    in_sources: object
+    out_degree: object
+    c: CGraph = field(default=None)
+
+    @staticmethod
+    def from_host(g) -> "DeviceGraph":
+        """Upload a graphgen.Graph (numpy int32 CSC) to device memory."""
+        import torch
+        dev = _dev()
+        off = torch.from_numpy(np.ascontiguousarray(g.in_offsets)).to(dev)
+        src = torch.from_numpy(np.ascontiguousarray(g.in_sources)).to(dev) if g.E else \
+            torch.zeros(1, dtype=torch.int32, device=dev)
+        od = torch.from_numpy(np.ascontiguousarray(g.out_degree)).to(dev)
+        dg = DeviceGraph(g.V, g.E, off, src, od)
+        dg.c = CGraph(g.V, g.E, off.data_ptr(), src.data_ptr(), od.data_ptr())
+        return dg
+
+
+@dataclass
+class Segments:
+    c: CSegments
+    arrays: dict
+
+    @property
+    def Q(self):
+        return int(self.c.Q)
+
+    @property
+    def k(self):
+        return int(self.c.k)
+
+    @property
+    def q(self):
+        return self.c.Q / self.c.V
+
+    def host(self) -> dict:
+        return {k: v.cpu().numpy() for k, v in self.arrays.items()}
+
+
+def default_tile_edges(N: int, value_bytes: int = 4) -> int:
+    # enough edges per tile that staging a segment once costs well under its edge bytes
+    return 65536
+
+
+def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = None, stream=None) -> Segments:
+    """Section 3.1 preprocessing on the GPU (query call, then build call)."""
+    import torch
+    dev = _dev()
+    L = lib()
+    c = CSegments()
+    c.N, c.B, c.tile_edges = N, B, tile_edges or default_tile_edges(N)
+    st = _stream(stream)
+    qbytes = L.cagra_query_workspace_bytes(dg.V, dg.E, N)
+    if qbytes == 0:
+        _check(E_INVALID, "cagra_query_workspace_bytes")
+    qws = torch.empty(qbytes, dtype=torch.uint8, device=dev)
+    _check(L.cagra_build_segments(ctypes.byref(dg.c), ctypes.byref(c), _ptr(qws), qbytes, st),
+           "cagra_build_segments(query)")
+    del qws
+    i32 = torch.int32
+    k, nb, Q, E, nt = c.k, c.nb, c.Q, c.E, c.ntiles
+    arrays = {
+        "seg_row_begin": torch.empty(k + 1, dtype=i32, device=dev),
+        "row_ptr": torch.empty(Q + 1, dtype=i32, device=dev),
+        "row_dst": torch.empty(max(Q, 1), dtype=i32, device=dev),
+        "edge_src": torch.empty(max(E, 4), dtype=i32, device=dev),
+        "block_ptr": torch.empty((nb + 1) * k, dtype=i32, device=dev),
+        "tile_edge": torch.empty(nt + 1, dtype=i32, device=dev),
+        "tile_seg": torch.empty(max(nt, 1), dtype=i32, device=dev),
+        "tile_span_row": torch.empty(max(nt, 1) * TILE_WAVES, dtype=i32, device=dev),
+    }
+    for name, t in arrays.items():
+        setattr(c, name, t.data_ptr())
+    ws = torch.empty(c.build_workspace_bytes, dtype=torch.uint8, device=dev)
+    _check(L.cagra_build_segments(ctypes.byref(dg.c), ctypes.byref(c), _ptr(ws), c.build_workspace_bytes, st),
+           "cagra_build_segments(build)")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    del ws
+    arrays["row_dst"] = arrays["row_dst"][:Q]
+    arrays["edge_src"] = arrays["edge_src"][:E]
+    arrays["tile_seg"] = arrays["tile_seg"][:nt]
+    arrays["tile_span_row"] = arrays["tile_span_row"][:nt * TILE_WAVES]
+    return Segments(c, arrays)
+
+
+# --------------------------------------------------------------------------- single calls
+
+def iter_workspace(seg: Segments):
+    import torch
+    n = lib().cagra_iter_workspace_bytes(ctypes.byref(seg.c))
+    return torch.empty(n, dtype=torch.uint8, device=_dev())
+
+
+def segment_gather(seg: Segments, op: int, value_type: int, values, partial, stream=None):
+    _check(lib().cagra_segment_gather(ctypes.byref(seg.c), op, value_type, _ptr(values), _ptr(partial),
+                                      _stream(stream)), "cagra_segment_gather")
+
+
+def merge(seg: Segments, op: int, partial, out, stream=None):
+    _check(lib().cagra_merge(ctypes.byref(seg.c), op, _ptr(partial), _ptr(out), _stream(stream)), "cagra_merge")
+
+
+def pagerank_init(dg: DeviceGraph, contrib_type: int, rank, contrib_out, scalars_out, workspace, stream=None):
+    _check(lib().cagra_pagerank_init(ctypes.byref(dg.c), contrib_type, _ptr(rank), _ptr(contrib_out),
+                                     _ptr(scalars_out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "cagra_pagerank_init")
+
+
+def pagerank_iter(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, contrib_in,
+                  scalars_in, partial, rank_out, contrib_out, scalars_out, workspace, stream=None):
+    _check(lib().cagra_pagerank_iter(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, contrib_type,
+                                     _ptr(rank_in), _ptr(contrib_in), _ptr(scalars_in), _ptr(partial),
+                                     _ptr(rank_out), _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace),
+                                     workspace.numel(), _stream(stream)), "cagra_pagerank_iter")
+
+
+def labelprop_iter(seg: Segments, labels_in, partial, labels_out, changed_out, workspace, stream=None):
+    _check(lib().cagra_labelprop_iter(ctypes.byref(seg.c), _ptr(labels_in), _ptr(partial), _ptr(labels_out),
+                                      _ptr(changed_out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "cagra_labelprop_iter")
+
+
+# --------------------------------------------------------------------------- iteration driver
+
+class PageRankState:
+    """Device buffers for the PageRank power iteration (double-buffered)."""
+
+    def __init__(self, dg: DeviceGraph, seg: Segments, contrib_type: int = F32):
+        import torch
+        dev = _dev()
+        V = dg.V
+        self.dg, self.seg, self.contrib_type = dg, seg, contrib_type
+        cdt = torch.float32 if contrib_type == F32 else torch.int16
+        self.rank = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.contrib = [torch.empty(V, dtype=cdt, device=dev) for _ in range(2)]
+        self.scalars = [torch.zeros(4, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.partial = torch.empty(max(seg.Q, 1), dtype=torch.float32, device=dev)
+        self.ws = iter_workspace(seg)
+        self.cur = 0
+
+    def start(self, rank0=None, stream=None):
+        """rank0: device float32 [V] start vector (None: uniform 1/V)."""
+        if rank0 is None:
+            self.rank[0].fill_(1.0 / self.dg.V)
+        else:
+            self.rank[0].copy_(rank0)
+        self.cur = 0
+        pagerank_init(self.dg, self.contrib_type, self.rank[0], self.contrib[0], self.scalars[0], self.ws, stream)
+
+    def step(self, damping: float = 0.85, stream=None):
+        a, b = self.cur, 1 - self.cur
+        pagerank_iter(self.dg, self.seg, damping, self.contrib_type, self.rank[a], self.contrib[a],
+                      self.scalars[a], self.partial, self.rank[b], self.contrib[b], self.scalars[b], self.ws,
+                      stream)
+        self.cur = b
+
+    @property
+    def rank_now(self):
+        return self.rank[self.cur]
+
+    @property
+    def scalars_now(self):
+        return self.scalars[self.cur]
+
+
+def pagerank(dg: DeviceGraph, seg: Segments, iters: int = 20, damping: float = 0.85, contrib_type: int = F32,
+             tol: float = 0.0, rank0=None, check_every: int = 1):
+    """Power iteration; fixed `iters` steps, or stop at the first L1 residual < tol
+    (read back every `check_every` steps). Returns (rank tensor, residual list, steps)."""
+    stt = PageRankState(dg, seg, contrib_type)
+    stt.start(rank0)
+    res = []
+    steps = 0
+    for t in range(iters):
+        stt.step(damping)
+        steps += 1
+        if tol > 0 and (steps % check_every == 0):
+            r = float(stt.scalars_now[1].item())
+            res.append(r)
+            if r < tol:
+                break
+    if tol <= 0:
+        res = None
+    return stt.rank_now.clone(), res, steps
+
+
+def labelprop(seg: Segments, max_iters: int = 1 << 20):
+    """Min-label propagation to the fixed point; returns (labels tensor, iterations
+    including the final one without changes)."""
+    import torch
+    dev = _dev()
+    V = seg.c.V
+    lab = [torch.arange(V, dtype=torch.int32, device=dev), torch.empty(V, dtype=torch.int32, device=dev)]
+    partial = torch.empty(max(seg.Q, 1), dtype=torch.int32, device=dev)
+    changed = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = iter_workspace(seg)
+    cur, it = 0, 0
+    while it < max_iters:
+        labelprop_iter(seg, lab[cur], partial, lab[1 - cur], changed, ws)
+        cur = 1 - cur
+        it += 1
+        if int(changed.item()) == 0:
+            break
+    return lab[cur], it

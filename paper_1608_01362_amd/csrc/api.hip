@@ -1,0 +1,214 @@
+// C ABI entry points: host-side validation, then kernel launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace cagra {
+
+static thread_local char g_last_error[512] = "";
+
+cagra_status fail(cagra_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+// defined in builder.hip / gather.hip / merge.hip
+size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N);
+cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
+cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
+bool gather_staged(int32_t N, int32_t value_type);
+cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                           void *partial, hipStream_t st);
+size_t merge_ordered_lds_bytes(int32_t B, int32_t op);
+size_t merge_fused_lds_total(int32_t B, int32_t k, int acc_bytes);
+cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st);
+int32_t init_blocks(int32_t V);
+cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
+                            double *scalars_out, double *blk, hipStream_t st);
+cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
+                             const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
+                             void *contrib_out, double *scalars_out, double *blk, hipStream_t st);
+cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
+                             int32_t *labels_out, int32_t *changed_out, int32_t *blk, hipStream_t st);
+
+static constexpr int32_t kMaxSegments = 32768;
+static constexpr int32_t kMaxMergeBlock = 16384;
+
+static cagra_status check_graph(const cagra_graph *g, bool need_outdeg) {
+    if (!g) return fail(CAGRA_E_INVALID, "graph is NULL");
+    if (g->V < 1) return fail(CAGRA_E_INVALID, "V must be >= 1 (got %d)", g->V);
+    if (g->E < 0) return fail(CAGRA_E_INVALID, "E must be >= 0");
+    if (g->E > (int64_t)INT32_MAX - 1) return fail(CAGRA_E_OVERFLOW, "E=%lld does not fit int32", (long long)g->E);
+    if (!g->in_offsets) return fail(CAGRA_E_INVALID, "in_offsets is NULL");
+    if (g->E > 0 && !g->in_sources) return fail(CAGRA_E_INVALID, "in_sources is NULL");
+    if (need_outdeg && !g->out_degree) return fail(CAGRA_E_INVALID, "out_degree is NULL");
+    return CAGRA_OK;
+}
+
+static cagra_status check_params(const cagra_segments *seg, int32_t V) {
+    if (!seg) return fail(CAGRA_E_INVALID, "segments is NULL");
+    if (seg->N < 1) return fail(CAGRA_E_INVALID, "N must be >= 1 (got %d)", seg->N);
+    if (seg->B < 1 || seg->B > kMaxMergeBlock)
+        return fail(CAGRA_E_INVALID, "B must be in [1, %d] (got %d)", kMaxMergeBlock, seg->B);
+    if (seg->tile_edges < 64) return fail(CAGRA_E_INVALID, "tile_edges must be >= 64 (got %d)", seg->tile_edges);
+    int64_t k = ceil_div(V, seg->N);
+    if (k > kMaxSegments) return fail(CAGRA_E_CAPACITY, "k=%lld segments exceeds %d", (long long)k, kMaxSegments);
+    return CAGRA_OK;
+}
+
+// A segments struct filled by a successful build (sizes consistent, arrays present).
+static cagra_status check_built(const cagra_segments *seg) {
+    if (!seg) return fail(CAGRA_E_INVALID, "segments is NULL");
+    if (seg->V < 1 || seg->N < 1 || seg->B < 1 || seg->k != (int32_t)ceil_div(seg->V, seg->N) ||
+        seg->nb != (int32_t)ceil_div(seg->V, seg->B) || seg->Q < 0 || seg->Q > seg->E || seg->ntiles < 0)
+        return fail(CAGRA_E_INVALID, "segments sizes are inconsistent (not built?)");
+    if (!seg->seg_row_begin || !seg->row_ptr || !seg->row_dst || !seg->edge_src || !seg->block_ptr ||
+        !seg->tile_edge || !seg->tile_seg || !seg->tile_span_row)
+        return fail(CAGRA_E_INVALID, "a segments array is NULL");
+    if (((uintptr_t)seg->edge_src & 15) != 0) return fail(CAGRA_E_INVALID, "edge_src must be 16-byte aligned");
+    return CAGRA_OK;
+}
+
+static size_t iter_ws_bytes(int32_t V, int32_t nb) {
+    int64_t n = nb > init_blocks(V) ? nb : init_blocks(V);
+    return (size_t)n * 4 * sizeof(double) + 256;
+}
+
+}  // namespace cagra
+
+using namespace cagra;
+
+extern "C" {
+
+int cagra_abi_version(void) { return CAGRA_ABI_VERSION; }
+
+const char *cagra_status_string(int status) {
+    switch (status) {
+        case CAGRA_OK: return "CAGRA_OK";
+        case CAGRA_E_INVALID: return "CAGRA_E_INVALID";
+        case CAGRA_E_OVERFLOW: return "CAGRA_E_OVERFLOW";
+        case CAGRA_E_CAPACITY: return "CAGRA_E_CAPACITY";
+        case CAGRA_E_BUFFER: return "CAGRA_E_BUFFER";
+        case CAGRA_E_HIP: return "CAGRA_E_HIP";
+        default: return "CAGRA_E_UNKNOWN";
+    }
+}
+
+const char *cagra_last_error(void) { return g_last_error; }
+
+int32_t cagra_max_merge_block(void) { return kMaxMergeBlock; }
+
+size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
+    if (V < 1 || N < 1 || E < 0) return 0;
+    return query_workspace_bytes(V, E, N);
+}
+
+cagra_status cagra_build_segments(const cagra_graph *g, cagra_segments *seg, void *workspace,
+                                  size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, false)) != CAGRA_OK) return s;
+    if ((s = check_params(seg, g->V)) != CAGRA_OK) return s;
+    if (seg->row_dst == nullptr) {
+        size_t need = query_workspace_bytes(g->V, g->E, seg->N);
+        if (!workspace || workspace_bytes < need)
+            return fail(CAGRA_E_BUFFER, "query workspace needs %zu bytes (got %zu)", need, workspace_bytes);
+        return query_segments(g, seg, workspace, workspace_bytes, stream);
+    }
+    if (seg->V != g->V || seg->E != g->E)
+        return fail(CAGRA_E_INVALID, "segments were queried for a different graph");
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (!workspace || workspace_bytes < seg->build_workspace_bytes)
+        return fail(CAGRA_E_BUFFER, "build workspace needs %zu bytes (got %zu)", seg->build_workspace_bytes,
+                    workspace_bytes);
+    return build_segments(g, seg, workspace, workspace_bytes, stream);
+}
+
+size_t cagra_iter_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->V < 1) return 0;
+    return iter_ws_bytes(seg->V, seg->nb);
+}
+
+cagra_status cagra_segment_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                                  void *partial, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (!(op == CAGRA_SUM_F32 && (value_type == CAGRA_F32 || value_type == CAGRA_BF16)) &&
+        !(op == CAGRA_MIN_I32 && value_type == CAGRA_I32))
+        return fail(CAGRA_E_INVALID, "unsupported gather op %d with value type %d", op, value_type);
+    if (!values || (seg->Q > 0 && !partial)) return fail(CAGRA_E_INVALID, "values or partial is NULL");
+    return launch_gather(seg, op, value_type, values, partial, stream);
+}
+
+cagra_status cagra_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (op != CAGRA_SUM_F32 && op != CAGRA_SUM_F32_COMP && op != CAGRA_MIN_I32)
+        return fail(CAGRA_E_INVALID, "unknown merge op %d", op);
+    if (!out || (seg->Q > 0 && !partial)) return fail(CAGRA_E_INVALID, "partial or out is NULL");
+    if (merge_ordered_lds_bytes(seg->B, op) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "merge block B=%d too large for op %d", seg->B, op);
+    return launch_merge(seg, op, partial, out, stream);
+}
+
+cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
+                                 double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if (contrib_type != CAGRA_F32 && contrib_type != CAGRA_BF16)
+        return fail(CAGRA_E_INVALID, "contrib_type must be CAGRA_F32 or CAGRA_BF16");
+    if (!rank || !contrib_out || !scalars_out) return fail(CAGRA_E_INVALID, "rank, contrib_out or scalars_out is NULL");
+    size_t need = (size_t)init_blocks(g->V) * 4 * sizeof(double) + 256;
+    if (!workspace || workspace_bytes < need)
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
+    return launch_pr_init(g, contrib_type, rank, contrib_out, scalars_out, (double *)workspace, stream);
+}
+
+cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                 int32_t contrib_type, const float *rank_in,
+                                 const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
+                                 void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (!(damping >= 0.0 && damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
+    if (contrib_type != CAGRA_F32 && contrib_type != CAGRA_BF16)
+        return fail(CAGRA_E_INVALID, "contrib_type must be CAGRA_F32 or CAGRA_BF16");
+    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
+        (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    if (!workspace || workspace_bytes < iter_ws_bytes(seg->V, seg->nb))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg->V, seg->nb),
+                    workspace_bytes);
+    if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
+    return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
+                           scalars_out, (double *)workspace, stream);
+}
+
+cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,
+                                  int32_t *labels_out, int32_t *changed_out, void *workspace,
+                                  size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (!labels_in || !labels_out || !changed_out || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (merge_fused_lds_total(seg->B, seg->k, 4) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    if (!workspace || workspace_bytes < iter_ws_bytes(seg->V, seg->nb))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg->V, seg->nb),
+                    workspace_bytes);
+    if ((s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, labels_in, partial, stream)) != CAGRA_OK) return s;
+    return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, (int32_t *)workspace, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,555 @@
+// CSR segmenting preprocessing on the GPU (Section 3.1 of the paper).
+//
+// The CSC row of a destination v lists its sources in ascending order, so the
+// in-edges of v that fall in one segment (source / N) form a contiguous run.
+// Every run is one row (s, v) of subgraph s. The builder
+//   1. flags run starts and labels every edge with its run and destination
+//      (two device-wide scans),
+//   2. stable-sorts the runs by segment id with a chunked counting sort (the
+//      runs arrive in (v, s) order; segment-major order with v ascending inside
+//      each segment is the paper's "sortByDestination" per subgraph),
+//   3. scatters the edges into the concatenated subgraph CSRs,
+//   4. builds the merge block index (Section 3.3) and the gather tile table.
+// Everything is integer work; the result is unique and bit-identical run to run.
+#include <limits.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace cagra {
+
+// ------------------------------------------------------------------ scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+struct ScanAdd {
+    static __device__ __forceinline__ int32_t id() { return 0; }
+    static __device__ __forceinline__ int32_t op(int32_t a, int32_t b) { return a + b; }
+};
+struct ScanMax {
+    static __device__ __forceinline__ int32_t id() { return INT_MIN; }
+    static __device__ __forceinline__ int32_t op(int32_t a, int32_t b) { return a > b ? a : b; }
+};
+
+template <class Op>
+__device__ int32_t block_reduce_i32(int32_t v, int32_t *lds) {
+    for (int d = 32; d >= 1; d >>= 1) v = Op::op(v, __shfl_down(v, d, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x / 64] = v;
+    __syncthreads();
+    int32_t r = Op::id();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kScanThreads / 64; ++i) r = Op::op(r, lds[i]);
+    return r;
+}
+
+template <class Op>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
+                                                              int32_t *__restrict__ sums) {
+    __shared__ int32_t lds[kScanThreads / 64];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t acc = Op::id();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t j = base + i * kScanThreads + threadIdx.x;
+        if (j < n) acc = Op::op(acc, in[j]);
+    }
+    int32_t tot = block_reduce_i32<Op>(acc, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ int pad_idx(int p) { return p + (p >> 5); }
+
+// Scans one tile of 4096 items; `offsets` (exclusive prefix of earlier tiles)
+// may be null for a single tile. Safe in place (in == out).
+template <class Op>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *in, int32_t *out, int64_t n,
+                                                             const int32_t *__restrict__ offsets, int inclusive) {
+    __shared__ int32_t tile[kScanTile + kScanTile / 32];
+    __shared__ int32_t wsum[kScanThreads / 64];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int p = i * kScanThreads + threadIdx.x;
+        int64_t j = base + p;
+        tile[pad_idx(p)] = j < n ? in[j] : Op::id();
+    }
+    __syncthreads();
+    int32_t vals[kScanItems];
+    int32_t run = Op::id();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        vals[i] = tile[pad_idx(threadIdx.x * kScanItems + i)];
+        run = Op::op(run, vals[i]);
+    }
+    // exclusive scan of per-thread totals
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t incl = run;
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl = Op::op(o, incl);
+    }
+    if (lane == 63) wsum[w] = incl;
+    int32_t excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = Op::id();
+    __syncthreads();
+    int32_t prefix = offsets ? offsets[blockIdx.x] : Op::id();
+    for (int i = 0; i < w; ++i) prefix = Op::op(prefix, wsum[i]);
+    prefix = Op::op(prefix, excl);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int32_t nxt = Op::op(prefix, vals[i]);
+        tile[pad_idx(threadIdx.x * kScanItems + i)] = inclusive ? nxt : prefix;
+        prefix = nxt;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int p = i * kScanThreads + threadIdx.x;
+        int64_t j = base + p;
+        if (j < n) out[j] = tile[pad_idx(p)];
+    }
+}
+
+// Workspace bytes the scan temporaries of one scan of n items take (same
+// arena rules as scan_i32 below).
+static size_t scan_ws_bytes(int64_t n) {
+    ArenaSize a;
+    while (n > kScanTile) {
+        n = ceil_div(n, kScanTile);
+        a.take<int32_t>(n + 64);
+    }
+    return a.used + 256;
+}
+
+template <class Op>
+static cagra_status scan_i32_rec(const int32_t *in, int32_t *out, int64_t n, bool inclusive, Arena &ar,
+                                 hipStream_t st) {
+    if (n <= 0) return CAGRA_OK;
+    int64_t nblk = ceil_div(n, kScanTile);
+    if (nblk == 1) {
+        k_scan_apply<Op><<<1, kScanThreads, 0, st>>>(in, out, n, nullptr, inclusive ? 1 : 0);
+        CAGRA_LAUNCH_CHECK();
+        return CAGRA_OK;
+    }
+    int32_t *sums = ar.take<int32_t>(nblk + 64);
+    if (!sums) return fail(CAGRA_E_BUFFER, "builder workspace too small (scan temporaries)");
+    k_scan_reduce<Op><<<(unsigned)nblk, kScanThreads, 0, st>>>(in, n, sums);
+    CAGRA_LAUNCH_CHECK();
+    cagra_status s = scan_i32_rec<Op>(sums, sums, nblk, false, ar, st);
+    if (s != CAGRA_OK) return s;
+    k_scan_apply<Op><<<(unsigned)nblk, kScanThreads, 0, st>>>(in, out, n, sums, inclusive ? 1 : 0);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// Temporaries are released after the scan: later work on the same stream may
+// reuse them, as it runs only after the scan's kernels.
+template <class Op>
+static cagra_status scan_i32(const int32_t *in, int32_t *out, int64_t n, bool inclusive, Arena &ar, hipStream_t st) {
+    size_t mark = ar.used;
+    cagra_status s = scan_i32_rec<Op>(in, out, n, inclusive, ar, st);
+    ar.used = mark;
+    return s;
+}
+
+// ------------------------------------------------------------------ builder kernels
+
+static inline unsigned grid_for(int64_t n, int nt) {
+    int64_t g = ceil_div(n, nt);
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// mark[off[v]] = v + 1 for every non-empty row (mark pre-filled with 0)
+__global__ void k_mark_rows(const int32_t *__restrict__ off, int32_t V, int32_t *__restrict__ mark) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) {
+        int32_t a = off[v], b = off[v + 1];
+        if (b > a) mark[a] = (int32_t)v + 1;
+    }
+}
+
+__device__ __forceinline__ bool is_run_start(const int32_t *src, const int32_t *mark, int64_t e, int32_t N) {
+    if (e == 0 || mark[e] != 0) return true;
+    return (src[e] / N) != (src[e - 1] / N);
+}
+
+// Query pass: per-segment edge counts and the number of runs (rows).
+__global__ __launch_bounds__(256) void k_count(const int32_t *__restrict__ src, const int32_t *__restrict__ mark,
+                                               int64_t E, int32_t N, int32_t k, int use_lds,
+                                               int32_t *__restrict__ seg_edges, unsigned long long *runs) {
+    extern __shared__ int32_t hist[];
+    if (use_lds) {
+        for (int s = threadIdx.x; s < k; s += blockDim.x) hist[s] = 0;
+        __syncthreads();
+    }
+    unsigned long long nr = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = src[e] / N;
+        if (use_lds) atomicAdd(&hist[s], 1);
+        else atomicAdd(&seg_edges[s], 1);
+        nr += is_run_start(src, mark, e, N) ? 1 : 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) nr += __shfl_down(nr, d, 64);
+    if ((threadIdx.x & 63) == 0 && nr) atomicAdd(runs, nr);
+    if (use_lds) {
+        __syncthreads();
+        for (int s = threadIdx.x; s < k; s += blockDim.x)
+            if (hist[s]) atomicAdd(&seg_edges[s], hist[s]);
+    }
+}
+
+__global__ void k_flags(const int32_t *__restrict__ src, const int32_t *__restrict__ mark, int64_t E, int32_t N,
+                        int32_t *__restrict__ flag) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) flag[e] = is_run_start(src, mark, e, N) ? 1 : 0;
+}
+
+// runincl[e] = 1 + run index of edge e; dstp1[e] = 1 + destination of edge e.
+__global__ void k_runs(const int32_t *__restrict__ src, const int32_t *__restrict__ dstp1,
+                       const int32_t *__restrict__ runincl, int64_t E, int32_t N, int32_t *__restrict__ run_first,
+                       int32_t *__restrict__ run_seg, int32_t *__restrict__ run_dst) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t ri = runincl[e];
+    if (e == 0 || runincl[e - 1] != ri) {
+        int32_t r = ri - 1;
+        run_first[r] = (int32_t)e;
+        run_seg[r] = src[e] / N;
+        run_dst[r] = dstp1[e] - 1;
+    }
+    if (e == E - 1) run_first[ri] = (int32_t)E;
+}
+
+// counts[s*nchunks + c] = number of runs of segment s in chunk c.
+__global__ __launch_bounds__(256) void k_sort_count(const int32_t *__restrict__ key, int64_t Q, int32_t C, int32_t k,
+                                                    int32_t nchunks, int32_t *__restrict__ counts) {
+    extern __shared__ int32_t hist[];
+    for (int s = threadIdx.x; s < k; s += blockDim.x) hist[s] = 0;
+    __syncthreads();
+    int64_t c = blockIdx.x;
+    int64_t lo = c * C, hi = lo + C < Q ? lo + C : Q;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&hist[key[j]], 1);
+    __syncthreads();
+    for (int s = threadIdx.x; s < k; s += blockDim.x) counts[(int64_t)s * nchunks + c] = hist[s];
+}
+
+// Stable ranks: one wave walks its chunk in order, 64 items per round; lanes
+// with equal keys are matched with one ballot per key bit.
+__global__ __launch_bounds__(64) void k_sort_rank(const int32_t *__restrict__ key, int64_t Q, int32_t C, int32_t k,
+                                                  int32_t nchunks, int32_t nbits,
+                                                  const int32_t *__restrict__ offsets, int32_t *__restrict__ pos) {
+    extern __shared__ int32_t cnt[];
+    int64_t c = blockIdx.x;
+    for (int s = threadIdx.x; s < k; s += 64) cnt[s] = offsets[(int64_t)s * nchunks + c];
+    __syncthreads();
+    int64_t lo = c * C, hi = lo + C < Q ? lo + C : Q;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t j0 = lo; j0 < hi; j0 += 64) {
+        int64_t j = j0 + threadIdx.x;
+        bool valid = j < hi;
+        int32_t kk = valid ? key[j] : 0;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            bool bit = (kk >> b) & 1;
+            uint64_t bb = __ballot(valid && bit);
+            m &= bit ? bb : ~bb;
+        }
+        int32_t base = valid ? cnt[kk] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            pos[j] = base + __popcll(m & lt);
+            if ((m & lt) == 0) cnt[kk] = base + __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ void k_seg_begin(const int32_t *__restrict__ offsets, int32_t k, int32_t nchunks, int64_t Q,
+                            int32_t *__restrict__ seg_row_begin) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < k) seg_row_begin[s] = offsets[s * nchunks];
+    if (s == k) seg_row_begin[k] = (int32_t)Q;
+}
+
+__global__ void k_rows(const int32_t *__restrict__ run_first, const int32_t *__restrict__ run_dst,
+                       const int32_t *__restrict__ pos, int64_t Q, int32_t *__restrict__ row_dst,
+                       int32_t *__restrict__ row_len) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < Q) {
+        int32_t p = pos[r];
+        row_dst[p] = run_dst[r];
+        row_len[p] = run_first[r + 1] - run_first[r];
+    }
+    if (r == Q) row_len[Q] = 0;
+}
+
+__global__ void k_edges(const int32_t *__restrict__ src, const int32_t *__restrict__ runincl,
+                        const int32_t *__restrict__ run_first, const int32_t *__restrict__ pos,
+                        const int32_t *__restrict__ row_ptr, int64_t E, int32_t N, int32_t *__restrict__ edge_src) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t r = runincl[e] - 1;
+    int32_t off = (int32_t)e - run_first[r];
+    int32_t u = src[e];
+    int32_t local = u - (u / N) * N;
+    edge_src[row_ptr[pos[r]] + off] = off == 0 ? (int32_t)((uint32_t)local | 0x80000000u) : local;
+}
+
+// First index in [lo, hi) with a[i] >= x (hi if none).
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *a, int32_t lo, int32_t hi, int64_t x) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_block_ptr(const int32_t *__restrict__ row_dst, const int32_t *__restrict__ seg_row_begin,
+                            int32_t k, int32_t nb, int32_t B, int32_t *__restrict__ block_ptr) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)(nb + 1) * k) return;
+    int64_t b = id / k;
+    int32_t s = (int32_t)(id - b * k);
+    block_ptr[id] = lower_bound_i32(row_dst, seg_row_begin[s], seg_row_begin[s + 1], b * (int64_t)B);
+}
+
+__global__ void k_tile_count(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ seg_row_begin,
+                             int32_t k, int32_t T, int32_t *__restrict__ tcount) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < k) {
+        int64_t es = row_ptr[seg_row_begin[s]], ee = row_ptr[seg_row_begin[s + 1]];
+        tcount[s] = (int32_t)ceil_div(ee - es, T);
+    } else if (s == k) {
+        tcount[k] = 0;
+    }
+}
+
+__global__ void k_tiles(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ seg_row_begin,
+                        const int32_t *__restrict__ tile_base, int32_t k, int32_t T, int32_t ntiles, int64_t E,
+                        int32_t *__restrict__ tile_edge, int32_t *__restrict__ tile_seg) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    if (t == ntiles) {
+        tile_edge[ntiles] = (int32_t)E;
+        return;
+    }
+    // segment s with tile_base[s] <= t < tile_base[s+1]
+    int32_t lo = 0, hi = k;  // find last s with tile_base[s] <= t
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (tile_base[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    int32_t s = lo;
+    while (s + 1 < k && tile_base[s + 1] <= t) ++s;  // skip segments without tiles
+    int64_t j = t - tile_base[s];
+    int32_t r0 = seg_row_begin[s], r1 = seg_row_begin[s + 1];
+    int64_t nominal = (int64_t)row_ptr[r0] + j * T;
+    int32_t r = lower_bound_i32(row_ptr, r0, r1, nominal);
+    tile_edge[t] = row_ptr[r];  // row_ptr[r1] is the end of the segment
+    tile_seg[t] = s;
+}
+
+__global__ void k_spans(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ seg_row_begin,
+                        const int32_t *__restrict__ tile_edge, const int32_t *__restrict__ tile_seg, int32_t ntiles,
+                        int32_t *__restrict__ span_row) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ntiles * CAGRA_TILE_WAVES) return;
+    int64_t t = id / CAGRA_TILE_WAVES;
+    int32_t w = (int32_t)(id - t * CAGRA_TILE_WAVES);
+    int64_t lo = tile_edge[t], hi = tile_edge[t + 1];
+    int64_t sl = ceil_div(hi - lo, CAGRA_TILE_WAVES);
+    int64_t b = lo + w * sl;
+    if (b > hi) b = hi;
+    int32_t s = tile_seg[t];
+    span_row[id] = lower_bound_i32(row_ptr, seg_row_begin[s], seg_row_begin[s + 1], b);
+}
+
+// ------------------------------------------------------------------ host orchestration
+
+static int32_t sort_chunk(int32_t k) {
+    int64_t c = 64LL * k;
+    if (c < 4096) c = 4096;
+    if (c > (1 << 22)) c = 1 << 22;
+    return (int32_t)c;
+}
+
+static int nbits_for(int32_t k) {
+    int b = 1;
+    while ((1LL << b) < k) ++b;
+    return b;
+}
+
+size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
+    int64_t k = ceil_div(V, N);
+    ArenaSize a;
+    a.take<int32_t>(E);                  // mark
+    a.take<int32_t>(k);                  // per-segment edges
+    a.take<unsigned long long>(1);       // run count
+    return a.used + 256;
+}
+
+// Layout of the build workspace (mirrors build_segments below).
+static size_t build_workspace_size(int64_t E, int64_t Q, int32_t k) {
+    int32_t C = sort_chunk(k);
+    int64_t nchunks = ceil_div(Q, C);
+    ArenaSize a;
+    a.take<int32_t>(E);           // mark / dstp1
+    a.take<int32_t>(E);           // flags / runincl
+    a.take<int32_t>(Q + 1);       // run_first
+    a.take<int32_t>(Q);           // run_seg
+    a.take<int32_t>(Q);           // run_dst
+    a.take<int32_t>(Q);           // pos
+    a.take<int32_t>(k * nchunks); // sort counts
+    a.take<int32_t>(k + 1);       // tile counts
+    int64_t mx = E;
+    if (k * nchunks > mx) mx = k * nchunks;
+    if (Q + 1 > mx) mx = Q + 1;
+    return a.used + scan_ws_bytes(mx) + 256;
+}
+
+static cagra_status allow_big_lds_impl();
+static cagra_status allow_big_lds() { return allow_big_lds_impl(); }
+
+cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st) {
+    const int32_t V = g->V, N = seg->N;
+    const int64_t E = g->E;
+    const int32_t k = (int32_t)ceil_div(V, N);
+    Arena ar{(char *)ws, ws_bytes, 0};
+    int32_t *mark = ar.take<int32_t>(E);
+    int32_t *seg_edges = ar.take<int32_t>(k);
+    unsigned long long *runs = ar.take<unsigned long long>(1);
+    if (!mark || !seg_edges || !runs) return fail(CAGRA_E_BUFFER, "query workspace smaller than %zu bytes",
+                                                  query_workspace_bytes(V, E, N));
+    int64_t Q = 0;
+    std::vector<int32_t> host_edges(k, 0);
+    if (E > 0) {
+        if (cagra_status a = allow_big_lds()) return a;
+        k_fill_i32<<<grid_for(E, 256), 256, 0, st>>>(mark, E, 0);
+        CAGRA_LAUNCH_CHECK();
+        k_fill_i32<<<grid_for(k, 256), 256, 0, st>>>(seg_edges, k, 0);
+        CAGRA_LAUNCH_CHECK();
+        CAGRA_HIP_CHECK(hipMemsetAsync(runs, 0, sizeof(unsigned long long), st));
+        k_mark_rows<<<grid_for(V, 256), 256, 0, st>>>(g->in_offsets, V, mark);
+        CAGRA_LAUNCH_CHECK();
+        int use_lds = k <= 16384 ? 1 : 0;
+        unsigned grid = grid_for(E, 256 * 64);
+        if (grid > 4096) grid = 4096;
+        k_count<<<grid, 256, use_lds ? k * sizeof(int32_t) : 0, st>>>(g->in_sources, mark, E, N, k, use_lds,
+                                                                      seg_edges, runs);
+        CAGRA_LAUNCH_CHECK();
+        unsigned long long hr = 0;
+        CAGRA_HIP_CHECK(hipMemcpyAsync(&hr, runs, sizeof(hr), hipMemcpyDeviceToHost, st));
+        CAGRA_HIP_CHECK(hipMemcpyAsync(host_edges.data(), seg_edges, (size_t)k * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, st));
+        CAGRA_HIP_CHECK(hipStreamSynchronize(st));
+        Q = (int64_t)hr;
+    }
+    int64_t ntiles = 0;
+    for (int32_t s = 0; s < k; ++s) ntiles += ceil_div(host_edges[s], seg->tile_edges);
+    if (ntiles * CAGRA_TILE_WAVES > INT32_MAX) return fail(CAGRA_E_OVERFLOW, "too many gather tiles");
+    seg->V = V;
+    seg->E = E;
+    seg->k = k;
+    seg->nb = (int32_t)ceil_div(V, seg->B);
+    seg->Q = Q;
+    seg->ntiles = (int32_t)ntiles;
+    seg->build_workspace_bytes = build_workspace_size(E, Q, k);
+    return CAGRA_OK;
+}
+
+static cagra_status allow_big_lds_impl() {
+    static bool done = false;
+    if (!done) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_count)) return a_;
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_sort_count)) return a_;
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_sort_rank)) return a_;
+        done = true;
+    }
+    return CAGRA_OK;
+}
+
+cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (cagra_status a = allow_big_lds()) return a;
+    const int32_t V = g->V, N = seg->N, B = seg->B, T = seg->tile_edges, k = seg->k, nb = seg->nb;
+    const int64_t E = g->E, Q = seg->Q;
+    const int32_t ntiles = seg->ntiles;
+    const int32_t C = sort_chunk(k);
+    const int64_t nchunks = ceil_div(Q, C);
+    Arena ar{(char *)ws, ws_bytes, 0};
+    int32_t *mark = ar.take<int32_t>(E);
+    int32_t *flag = ar.take<int32_t>(E);
+    int32_t *run_first = ar.take<int32_t>(Q + 1);
+    int32_t *run_seg = ar.take<int32_t>(Q);
+    int32_t *run_dst = ar.take<int32_t>(Q);
+    int32_t *pos = ar.take<int32_t>(Q);
+    int32_t *counts = ar.take<int32_t>(k * nchunks);
+    int32_t *tcount = ar.take<int32_t>(k + 1);
+    if (!mark || !flag || !run_first || !run_seg || !run_dst || !pos || !counts || !tcount)
+        return fail(CAGRA_E_BUFFER, "build workspace smaller than %zu bytes", seg->build_workspace_bytes);
+    cagra_status s;
+    if (E == 0) {
+        k_fill_i32<<<grid_for(k + 1, 256), 256, 0, st>>>(seg->seg_row_begin, k + 1, 0);
+        CAGRA_LAUNCH_CHECK();
+        k_fill_i32<<<1, 64, 0, st>>>(seg->row_ptr, 1, 0);
+        CAGRA_LAUNCH_CHECK();
+        k_fill_i32<<<grid_for((int64_t)(nb + 1) * k, 256), 256, 0, st>>>(seg->block_ptr, (int64_t)(nb + 1) * k, 0);
+        CAGRA_LAUNCH_CHECK();
+        k_fill_i32<<<1, 64, 0, st>>>(seg->tile_edge, 1, 0);
+        CAGRA_LAUNCH_CHECK();
+        return CAGRA_OK;
+    }
+    // 1. run starts, destinations, run ids
+    k_fill_i32<<<grid_for(E, 256), 256, 0, st>>>(mark, E, 0);
+    CAGRA_LAUNCH_CHECK();
+    k_mark_rows<<<grid_for(V, 256), 256, 0, st>>>(g->in_offsets, V, mark);
+    CAGRA_LAUNCH_CHECK();
+    k_flags<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, mark, E, N, flag);
+    CAGRA_LAUNCH_CHECK();
+    if ((s = scan_i32<ScanMax>(mark, mark, E, true, ar, st)) != CAGRA_OK) return s;
+    if ((s = scan_i32<ScanAdd>(flag, flag, E, true, ar, st)) != CAGRA_OK) return s;
+    k_runs<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, mark, flag, E, N, run_first, run_seg, run_dst);
+    CAGRA_LAUNCH_CHECK();
+    // 2. stable counting sort of runs by segment
+    size_t lds_k = (size_t)k * sizeof(int32_t);
+    k_sort_count<<<(unsigned)nchunks, 256, lds_k, st>>>(run_seg, Q, C, k, (int32_t)nchunks, counts);
+    CAGRA_LAUNCH_CHECK();
+    if ((s = scan_i32<ScanAdd>(counts, counts, k * nchunks, false, ar, st)) != CAGRA_OK) return s;
+    k_sort_rank<<<(unsigned)nchunks, 64, lds_k, st>>>(run_seg, Q, C, k, (int32_t)nchunks, nbits_for(k), counts, pos);
+    CAGRA_LAUNCH_CHECK();
+    k_seg_begin<<<grid_for(k + 1, 256), 256, 0, st>>>(counts, k, (int32_t)nchunks, Q, seg->seg_row_begin);
+    CAGRA_LAUNCH_CHECK();
+    // 3. rows and edges
+    k_rows<<<grid_for(Q + 1, 256), 256, 0, st>>>(run_first, run_dst, pos, Q, seg->row_dst, seg->row_ptr);
+    CAGRA_LAUNCH_CHECK();
+    if ((s = scan_i32<ScanAdd>(seg->row_ptr, seg->row_ptr, Q + 1, false, ar, st)) != CAGRA_OK) return s;
+    k_edges<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N, seg->edge_src);
+    CAGRA_LAUNCH_CHECK();
+    // 4. merge block index and gather tiles
+    k_block_ptr<<<grid_for((int64_t)(nb + 1) * k, 256), 256, 0, st>>>(seg->row_dst, seg->seg_row_begin, k, nb, B,
+                                                                       seg->block_ptr);
+    CAGRA_LAUNCH_CHECK();
+    k_tile_count<<<grid_for(k + 1, 256), 256, 0, st>>>(seg->row_ptr, seg->seg_row_begin, k, T, tcount);
+    CAGRA_LAUNCH_CHECK();
+    if ((s = scan_i32<ScanAdd>(tcount, tcount, k + 1, false, ar, st)) != CAGRA_OK) return s;
+    k_tiles<<<grid_for(ntiles + 1, 256), 256, 0, st>>>(seg->row_ptr, seg->seg_row_begin, tcount, k, T, ntiles, E,
+                                                       seg->tile_edge, seg->tile_seg);
+    CAGRA_LAUNCH_CHECK();
+    if (ntiles > 0) {
+        k_spans<<<grid_for((int64_t)ntiles * CAGRA_TILE_WAVES, 256), 256, 0, st>>>(
+            seg->row_ptr, seg->seg_row_begin, seg->tile_edge, seg->tile_seg, ntiles, seg->tile_span_row);
+        CAGRA_LAUNCH_CHECK();
+    }
+    return CAGRA_OK;
+}
+
+}  // namespace cagra

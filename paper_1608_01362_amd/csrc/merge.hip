@@ -1,0 +1,403 @@
+// Cache-aware merge (Section 3.3) and the per-vertex update that follows it
+// (Section 4, VertexMap of the PageRank program).
+//
+// Destinations are cut into blocks of B vertices whose accumulators live in
+// LDS. For block b, subgraph s contributes the buffer entries
+// [block_ptr[b*k+s], block_ptr[(b+1)*k+s]); every read of the buffers and of
+// row_dst is sequential, and every random update hits LDS.
+//
+// Two schedules:
+//  * k_merge_ordered: the paper's order exactly -- subgraphs in ascending
+//    order, one wave per block, lanes over the entries of one subgraph's range
+//    (distinct destinations, so no conflicts). Used by cagra_merge for float
+//    sums (plain or Neumaier-compensated) and int minimum.
+//  * k_merge_pr / k_merge_lp: all 16 waves of the workgroup stream the block's
+//    entries at once (flattened over subgraphs), updating shared LDS
+//    accumulators with atomics whose result does not depend on their order:
+//    int32 minimum for labels, and for PageRank an int64 fixed-point sum
+//    (each FP32 buffer value scaled by 2^56 and rounded), which adds the buffer
+//    values exactly. The epilogue then applies the vertex update.
+#include <math.h>
+
+#include "common.h"
+
+namespace cagra {
+
+constexpr int kMergeThreads = 1024;
+constexpr double kFixScale = 72057594037927936.0;      // 2^56
+constexpr double kFixInv = 1.0 / 72057594037927936.0;  // 2^-56
+
+// Dynamic LDS of the fused merges; kFusedStaticLds covers their static arrays.
+constexpr size_t kFusedStaticLds = 256;
+size_t merge_fused_lds_bytes(int32_t B, int32_t k, int acc_bytes) {
+    return align_up((size_t)B * acc_bytes, 16) + (size_t)(2 * (int64_t)k + 2) * sizeof(int32_t) + 64;
+}
+size_t merge_fused_lds_total(int32_t B, int32_t k, int acc_bytes) {
+    return merge_fused_lds_bytes(B, k, acc_bytes) + kFusedStaticLds;
+}
+
+// ---------------------------------------------------------------- ordered (paper) merge
+
+template <class Op, bool COMP>
+__global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict__ row_dst,
+                                                      const int32_t *__restrict__ block_ptr,
+                                                      const typename Op::T *__restrict__ partial, int32_t V,
+                                                      int32_t k, int32_t B, int32_t nb,
+                                                      typename Op::T *__restrict__ out) {
+    using T = typename Op::T;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T *acc = reinterpret_cast<T *>(smem);
+    T *cmp = acc + B;  // Neumaier compensation terms (COMP only)
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int64_t vb = (int64_t)b * B;
+    int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    const int lane = threadIdx.x;
+    for (int i = lane; i < nv; i += 64) {
+        acc[i] = Op::identity();
+        if (COMP) cmp[i] = Op::identity();
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t s = 0; s < k; ++s) {
+        const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
+        for (int32_t i = lo + lane; i < hi; i += 64) {
+            const int32_t d = (int32_t)(row_dst[i] - vb);
+            const T x = partial[i];
+            if (COMP) {
+                // Neumaier (1974) compensated summation
+                float sacc = acc[d];
+                float tsum = sacc + x;
+                if (fabsf(sacc) >= fabsf(x)) cmp[d] += (sacc - tsum) + x;
+                else cmp[d] += (x - tsum) + sacc;
+                acc[d] = tsum;
+            } else {
+                acc[d] = Op::apply(acc[d], x);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int i = lane; i < nv; i += 64) out[vb + i] = COMP ? (T)(acc[i] + cmp[i]) : acc[i];
+}
+
+template <class Op, bool COMP>
+static cagra_status launch_ordered(const cagra_segments *seg, const void *partial, void *out, hipStream_t st) {
+    using T = typename Op::T;
+    auto kern = k_merge_ordered<Op, COMP>;
+    size_t lds = (size_t)seg->B * sizeof(T) * (COMP ? 2 : 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
+        attr_set = true;
+    }
+    kern<<<seg->nb, 64, lds, st>>>(seg->row_dst, seg->block_ptr, (const T *)partial, seg->V, seg->k, seg->B, seg->nb,
+                                   (T *)out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+size_t merge_ordered_lds_bytes(int32_t B, int32_t op) {
+    return (size_t)B * 4 * (op == CAGRA_SUM_F32_COMP ? 2 : 1);
+}
+
+cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st) {
+    if (seg->nb == 0) return CAGRA_OK;
+    switch (op) {
+        case CAGRA_SUM_F32: return launch_ordered<OpSum, false>(seg, partial, out, st);
+        case CAGRA_SUM_F32_COMP: return launch_ordered<OpSum, true>(seg, partial, out, st);
+        case CAGRA_MIN_I32: return launch_ordered<OpMin, false>(seg, partial, out, st);
+        default: return fail(CAGRA_E_INVALID, "unknown merge op %d", op);
+    }
+}
+
+// ---------------------------------------------------------------- fused merges
+
+// In-place exclusive scan of a[0..n) in LDS by the whole 1024-thread block;
+// returns the total (all threads). `tmp` holds 16 ints.
+__device__ int32_t block_excl_scan_lds(int32_t *a, int32_t n, int32_t *tmp) {
+    const int per = (n + kMergeThreads - 1) / kMergeThreads;
+    const int lo = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) sum += a[lo + i];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t incl = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[w] = incl;
+    __syncthreads();
+    int32_t pre = incl - sum;
+    for (int i = 0; i < w; ++i) pre += tmp[i];
+    int32_t total = 0;
+    for (int i = 0; i < kMergeThreads / 64; ++i) total += tmp[i];
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) {
+            int32_t x = a[lo + i];
+            a[lo + i] = pre;
+            pre += x;
+        }
+    __syncthreads();
+    return total;
+}
+
+// Loads the block's range bounds per subgraph into LDS and turns the lengths
+// into an exclusive prefix; returns the block's entry count.
+__device__ int32_t load_block_ranges(const int32_t *__restrict__ block_ptr, int b, int32_t k, int32_t *lo_s,
+                                     int32_t *pre, int32_t *tmp) {
+    for (int s = threadIdx.x; s < k; s += kMergeThreads) {
+        int32_t a = block_ptr[(int64_t)b * k + s], e = block_ptr[(int64_t)(b + 1) * k + s];
+        lo_s[s] = a;
+        pre[s] = e - a;
+    }
+    __syncthreads();
+    int32_t P = block_excl_scan_lds(pre, k, tmp);
+    if (threadIdx.x == 0) pre[k] = P;
+    __syncthreads();
+    return P;
+}
+
+// Entry index of flattened position f: subgraph = last s with pre[s] <= f.
+__device__ __forceinline__ int32_t flat_to_entry(const int32_t *pre, const int32_t *lo_s, int32_t k, int32_t f) {
+    int32_t lo = 0, hi = k;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= f) lo = mid;
+        else hi = mid;
+    }
+    return lo_s[lo] + (f - pre[lo]);
+}
+
+constexpr int kUnroll = 4;
+
+template <bool BF16OUT>
+__global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
+    const int32_t *__restrict__ row_dst, const int32_t *__restrict__ block_ptr, const float *__restrict__ partial,
+    int32_t V, int32_t k, int32_t B, int32_t nb, const float *__restrict__ rank_in,
+    const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
+    float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
+    int32_t *pre = lo_s + k;
+    __shared__ int32_t tmp[16];
+    __shared__ double red[16];
+
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
+    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+
+    for (int32_t f0 = threadIdx.x; f0 < P; f0 += kMergeThreads * kUnroll) {
+        int32_t d[kUnroll];
+        float x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + u * kMergeThreads;
+            if (f < P) {
+                const int32_t i = flat_to_entry(pre, lo_s, k, f);
+                d[u] = __builtin_nontemporal_load(row_dst + i) - (int32_t)vb;
+                x[u] = __builtin_nontemporal_load(partial + i);
+            } else {
+                d[u] = -1;
+                x[u] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (d[u] >= 0) atomicAdd(&acc[d[u]], (unsigned long long)llrint((double)x[u] * kFixScale));
+    }
+    __syncthreads();
+
+    const double dd = damping;
+    const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
+    double dang = 0.0, res = 0.0, mass = 0.0;
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
+        const int64_t v = vb + i;
+        const double sum = (double)(long long)acc[i] * kFixInv;
+        const float r = (float)(base + dd * sum);
+        rank_out[v] = r;
+        const int32_t od = outdeg[v];
+        const float c = od > 0 ? r / (float)od : 0.0f;
+        if (BF16OUT) reinterpret_cast<uint16_t *>(contrib_out)[v] = f32_to_bf16(c);
+        else reinterpret_cast<float *>(contrib_out)[v] = c;
+        if (od == 0) dang += (double)r;
+        res += fabs((double)r - (double)rank_in[v]);
+        mass += (double)r;
+    }
+    dang = block_sum_f64<kMergeThreads>(dang, red);
+    res = block_sum_f64<kMergeThreads>(res, red);
+    mass = block_sum_f64<kMergeThreads>(mass, red);
+    if (threadIdx.x == 0) {
+        blk[(int64_t)b * 4 + 0] = dang;
+        blk[(int64_t)b * 4 + 1] = res;
+        blk[(int64_t)b * 4 + 2] = mass;
+        blk[(int64_t)b * 4 + 3] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
+    const int32_t *__restrict__ row_dst, const int32_t *__restrict__ block_ptr, const int32_t *__restrict__ partial,
+    int32_t V, int32_t k, int32_t B, int32_t nb, const int32_t *__restrict__ labels_in,
+    int32_t *__restrict__ labels_out, int32_t *__restrict__ blk_changed) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    int32_t *acc = reinterpret_cast<int32_t *>(smem);
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
+    int32_t *pre = lo_s + k;
+    __shared__ int32_t tmp[16];
+    __shared__ int32_t cnt[16];
+
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
+    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+
+    for (int32_t f0 = threadIdx.x; f0 < P; f0 += kMergeThreads * kUnroll) {
+        int32_t d[kUnroll], x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + u * kMergeThreads;
+            if (f < P) {
+                const int32_t i = flat_to_entry(pre, lo_s, k, f);
+                d[u] = __builtin_nontemporal_load(row_dst + i) - (int32_t)vb;
+                x[u] = __builtin_nontemporal_load(partial + i);
+            } else {
+                d[u] = -1;
+                x[u] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (d[u] >= 0) atomicMin(&acc[d[u]], x[u]);
+    }
+    __syncthreads();
+    int32_t changed = 0;
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
+        const int32_t l = acc[i];
+        labels_out[vb + i] = l;
+        changed += (l != labels_in[vb + i]) ? 1 : 0;
+    }
+    for (int dd = 32; dd >= 1; dd >>= 1) changed += __shfl_down(changed, dd, 64);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int i = 0; i < kMergeThreads / 64; ++i) tot += cnt[i];
+        blk_changed[b] = tot;
+    }
+}
+
+// PageRank start vector: contributions, dangling mass and total mass.
+constexpr int kInitSpan = 16384;  // vertices per init block
+
+template <bool BF16OUT>
+__global__ __launch_bounds__(256) void k_pr_init(const float *__restrict__ rank, const int32_t *__restrict__ outdeg,
+                                                 int32_t V, void *__restrict__ contrib_out,
+                                                 double *__restrict__ blk) {
+    __shared__ double red[4];
+    const int64_t lo = (int64_t)blockIdx.x * kInitSpan;
+    const int64_t hi = lo + kInitSpan < V ? lo + kInitSpan : V;
+    double dang = 0.0, mass = 0.0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
+        const float r = rank[v];
+        const int32_t od = outdeg[v];
+        const float c = od > 0 ? r / (float)od : 0.0f;
+        if (BF16OUT) reinterpret_cast<uint16_t *>(contrib_out)[v] = f32_to_bf16(c);
+        else reinterpret_cast<float *>(contrib_out)[v] = c;
+        if (od == 0) dang += (double)r;
+        mass += (double)r;
+    }
+    dang = block_sum_f64<256>(dang, red);
+    mass = block_sum_f64<256>(mass, red);
+    if (threadIdx.x == 0) {
+        blk[(int64_t)blockIdx.x * 4 + 0] = dang;
+        blk[(int64_t)blockIdx.x * 4 + 1] = 0.0;
+        blk[(int64_t)blockIdx.x * 4 + 2] = mass;
+        blk[(int64_t)blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
+// Fixed-order FP64 reduction of n rows of 4 partial sums.
+__global__ __launch_bounds__(256) void k_reduce4(const double *__restrict__ blk, int32_t n,
+                                                 double *__restrict__ out) {
+    __shared__ double red[4];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t j = threadIdx.x; j < n; j += 256)
+        for (int c = 0; c < 4; ++c) a[c] += blk[(int64_t)j * 4 + c];
+    for (int c = 0; c < 4; ++c) {
+        double t = block_sum_f64<256>(a[c], red);
+        if (threadIdx.x == 0) out[c] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_i32(const int32_t *__restrict__ blk, int32_t n,
+                                                    int32_t *__restrict__ out) {
+    __shared__ int32_t red[4];
+    int32_t a = 0;
+    for (int32_t j = threadIdx.x; j < n; j += 256) a += blk[j];
+    for (int d = 32; d >= 1; d >>= 1) a += __shfl_down(a, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+int32_t init_blocks(int32_t V) { return (int32_t)ceil_div(V, kInitSpan); }
+
+cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
+                            double *scalars_out, double *blk, hipStream_t st) {
+    const int32_t nblk = init_blocks(g->V);
+    if (contrib_type == CAGRA_BF16) k_pr_init<true><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
+    else k_pr_init<false><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_reduce4<<<1, 256, 0, st>>>(blk, nblk, scalars_out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
+                             const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
+                             void *contrib_out, double *scalars_out, double *blk, hipStream_t st) {
+    const size_t lds = merge_fused_lds_bytes(seg->B, seg->k, 8);
+    if (contrib_type == CAGRA_BF16) {
+        static bool attr = false;
+        if (!attr) {
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<true>)) return a_;
+            attr = true;
+        }
+        k_merge_pr<true><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k,
+                                                              seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
+                                                              damping, rank_out, contrib_out, blk);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<false>)) return a_;
+            attr = true;
+        }
+        k_merge_pr<false><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k,
+                                                               seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
+                                                               damping, rank_out, contrib_out, blk);
+    }
+    CAGRA_LAUNCH_CHECK();
+    k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
+                             int32_t *labels_out, int32_t *changed_out, int32_t *blk, hipStream_t st) {
+    const size_t lds = merge_fused_lds_bytes(seg->B, seg->k, 4);
+    static bool attr = false;
+    if (!attr) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_lp)) return a_;
+        attr = true;
+    }
+    k_merge_lp<<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k, seg->B,
+                                                    seg->nb, labels_in, labels_out, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_reduce_i32<<<1, 256, 0, st>>>(blk, seg->nb, changed_out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+}  // namespace cagra

@@ -1,0 +1,130 @@
+"""The C ABI library loads without a GPU, exports every function the header
+declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cagra.h")
+
+
+@pytest.fixture(scope="module")
+def cagra():
+    from paper_1608_01362_amd import cagra as c
+    if not os.path.exists(c.LIB_PATH):
+        from paper_1608_01362_amd import _build
+        _build.build()
+    c.lib()
+    return c
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cagra_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_match_header(cagra):
+    decl = declared_functions()
+    assert decl == sorted(cagra.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", cagra.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (cagra_\w+)", out))
+    assert set(decl) <= exported
+    L = cagra.lib()
+    for name in decl:
+        assert hasattr(L, name)
+    assert L.cagra_abi_version() == 1
+
+
+def test_status_strings(cagra):
+    L = cagra.lib()
+    assert L.cagra_status_string(0) == b"CAGRA_OK"
+    assert L.cagra_status_string(-4) == b"CAGRA_E_BUFFER"
+    assert L.cagra_status_string(99) == b"CAGRA_E_UNKNOWN"
+
+
+def _graph(c, V=10, E=5, off=1, src=1, od=1):
+    return c.CGraph(V, E, off, src, od)
+
+
+def _seg(c, N=4, B=4, T=64):
+    s = c.CSegments()
+    s.N, s.B, s.tile_edges = N, B, T
+    return s
+
+
+@pytest.mark.parametrize("mut,status", [
+    (dict(V=0), -1), (dict(E=-1), -1), (dict(E=2 ** 31), -2), (dict(off=None), -1), (dict(src=None), -1),
+])
+def test_build_rejects_bad_graph(cagra, mut, status):
+    L = cagra.lib()
+    g = _graph(cagra, **mut)
+    s = _seg(cagra)
+    assert L.cagra_build_segments(ctypes.byref(g), ctypes.byref(s), None, 0, None) == status
+    assert L.cagra_last_error()
+
+
+@pytest.mark.parametrize("mut,status", [
+    (dict(N=0), -1), (dict(B=0), -1), (dict(B=16385), -1), (dict(T=63), -1), (dict(N=1, V=40000), -3),
+])
+def test_build_rejects_bad_params(cagra, mut, status):
+    L = cagra.lib()
+    V = mut.pop("V", 10)
+    g = _graph(cagra, V=V)
+    s = _seg(cagra, **mut)
+    assert L.cagra_build_segments(ctypes.byref(g), ctypes.byref(s), None, 0, None) == status
+
+
+def test_query_needs_workspace(cagra):
+    L = cagra.lib()
+    g = _graph(cagra, V=100, E=50)
+    s = _seg(cagra)
+    need = L.cagra_query_workspace_bytes(100, 50, 4)
+    assert need >= 50 * 4
+    assert L.cagra_build_segments(ctypes.byref(g), ctypes.byref(s), None, 0, None) == -4
+    assert L.cagra_build_segments(ctypes.byref(g), ctypes.byref(s), 1, need - 1, None) == -4
+
+
+def test_calls_reject_unbuilt_segments(cagra):
+    L = cagra.lib()
+    s = _seg(cagra)
+    assert L.cagra_segment_gather(ctypes.byref(s), 0, 0, 1, 1, None) == -1
+    assert L.cagra_merge(ctypes.byref(s), 0, 1, 1, None) == -1
+    assert L.cagra_labelprop_iter(ctypes.byref(s), 1, 1, 1, 1, 1, 1 << 20, None) == -1
+    g = _graph(cagra)
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
+                                 None) == -1
+    assert L.cagra_pagerank_init(ctypes.byref(g), 5, 1, 1, 1, 1, 1 << 20, None) == -1
+    assert L.cagra_pagerank_init(ctypes.byref(g), 0, 1, 1, 1, 1, 0, None) == -4
+    assert L.cagra_segment_gather(None, 0, 0, 1, 1, None) == -1
+
+
+def _fake_built(c, V=100, N=10, B=10, E=50, Q=20, align=16):
+    s = _seg(c, N=N, B=B)
+    s.V, s.E, s.Q, s.k, s.nb, s.ntiles = V, E, Q, -(-V // N), -(-V // B), 1
+    for name in ("seg_row_begin", "row_ptr", "row_dst", "block_ptr", "tile_edge", "tile_seg", "tile_span_row"):
+        setattr(s, name, 4096)
+    s.edge_src = 4096 + (0 if align == 16 else 4)
+    return s
+
+
+def test_validation_of_built_segments(cagra):
+    L = cagra.lib()
+    s = _fake_built(cagra, align=4)
+    assert L.cagra_segment_gather(ctypes.byref(s), 0, 0, 1, 1, None) == -1  # misaligned edge_src
+    s = _fake_built(cagra)
+    assert L.cagra_segment_gather(ctypes.byref(s), 1, 0, 1, 1, None) == -1  # min with float values
+    assert L.cagra_merge(ctypes.byref(s), 7, 1, 1, None) == -1
+    # fused merge LDS: 8*B + 8*(k+1) + 64 bytes; B = 16384 with k = 4096 does not fit
+    s = _fake_built(cagra, B=16384, V=32768, N=8)
+    g = _graph(cagra, V=32768, E=50)
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
+                                 None) == -3
+    assert L.cagra_iter_workspace_bytes(ctypes.byref(s)) > 0
+    # workspace too small is reported before any launch
+    s = _fake_built(cagra)
+    g = _graph(cagra, V=100, E=50)
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 8, None) == -4
