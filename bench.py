@@ -1,0 +1,205 @@
+"""Benchmark: segmented pull PageRank on one MI355X.
+
+Workload (default): directed R-MAT scale 25 (33,554,432 vertices), edge factor
+32, a/b/c/d = .57/.19/.19/.05, seeded vertex permutation, self-loops and
+duplicates removed, seed 3; damping 0.85, dangling mass spread uniformly.
+
+A step is one PageRank iteration through segmenting: the segment-processing
+kernel (gather into per-subgraph buffers), the cache-aware merge with the
+vertex update, and the FP64 reductions of dangling mass and L1 residual. The
+segment build is preprocessing, timed once and reported separately. Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line with GTEPS (edges / seconds per iteration / 1e9), the
+HBM roofline fraction of the dominant kernel, the time to an L1 residual below
+1e-6 from a uniform start, and the CPU oracle's rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def byte_model(V, E, Q, k, nb, wc):
+    """Algorithmic HBM bytes per iteration (what the method must move).
+    gather: edge words (4E) + each segment's values staged once (wc*V) + buffer writes (4Q)
+    merge:  buffer reads (4Q) + row destinations (4Q) + block index (4k(nb+1))
+            + rank_in, out_degree, rank_out (12V) + contrib_out (wc*V)"""
+    gather = 4 * E + wc * V + 4 * Q
+    merge = 8 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
+    return gather, merge
+
+
+def cpu_baseline(g, budget_s=12.0):
+    import oracle
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    t0 = time.perf_counter()
+    oracle.pagerank(g, iters=1, threads=cores)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(10, math.floor(budget_s / max(t1, 1e-3)))))
+    t0 = time.perf_counter()
+    oracle.pagerank(g, iters=n, threads=cores)
+    tn = time.perf_counter() - t0
+    return {"value": g.E * n / tn / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} FP64 pull PageRank iterations of the plain CPU oracle on the full graph "
+                      f"(V={g.V}, E={g.E}), OpenMP over destinations; {tn / n * 1e3:.0f} ms per iteration"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=25)
+    ap.add_argument("--edge-factor", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--N", type=int, default=32768, help="vertices per segment")
+    ap.add_argument("--B", type=int, default=8192, help="merge block (vertices)")
+    ap.add_argument("--tile-edges", type=int, default=65536)
+    ap.add_argument("--contrib", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (to calibrate the HBM "
+                         "byte counters of a profiler against a known size) and exit")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}))
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
+              "path is a design note, not a measured configuration.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"generating R-MAT scale {args.scale} edge factor {args.edge_factor} seed {args.seed}")
+    t0 = time.perf_counter()
+    g = graphgen.rmat_graph(args.scale, args.edge_factor, args.seed)
+    log(f"graph V={g.V} E={g.E} in {time.perf_counter() - t0:.1f}s")
+    dg = cagra.DeviceGraph.from_host(g)
+    torch.cuda.synchronize()
+    log("uploaded")
+
+    ev_b0, ev_b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_b0.record()
+    seg = cagra.build_segments(dg, args.N, args.B, args.tile_edges)
+    ev_b1.record()
+    torch.cuda.synchronize()
+    build_ms = ev_b0.elapsed_time(ev_b1)
+    log(f"segments: k={seg.k} Q={seg.Q} q={seg.q:.3f} tiles={seg.c.ntiles} nb={seg.c.nb} build {build_ms:.1f} ms")
+
+    ct = cagra.F32 if args.contrib == "f32" else cagra.BF16
+    wc = 4 if ct == cagra.F32 else 2
+    st = cagra.PageRankState(dg, seg, ct)
+    st.start()
+    for _ in range(args.warmup):
+        st.step_split()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(K):
+        st.step_split(events=evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gather_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    merge_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    total_ms = evs[0][0].elapsed_time(evs[-1][2])
+    ms_per_step = total_ms / K
+    log(f"timed {K} steps: {ms_per_step:.3f} ms/step (gather {sum(gather_ms) / K:.3f}, merge {sum(merge_ms) / K:.3f}),"
+        f" wall {wall / K * 1e3:.3f} ms/step")
+
+    V, E, Q, k, nb = g.V, g.E, seg.Q, seg.k, seg.c.nb
+    gb, mb = byte_model(V, E, Q, k, nb, wc)
+    g_avg, m_avg = sum(gather_ms) / K, sum(merge_ms) / K
+    if g_avg >= m_avg:
+        dom, dbytes, dms = "k_gather", gb, g_avg
+    else:
+        dom, dbytes, dms = "k_merge_pr", mb, m_avg
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    gteps = E / (ms_per_step * 1e-3) / 1e9
+
+    conv = None
+    if not args.no_converge:
+        st.start()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        it, res = 0, float("inf")
+        while it < 100:
+            st.step()
+            it += 1
+            res = float(st.scalars_now[1].item())
+            if res < 1e-6:
+                break
+        conv_ms = (time.perf_counter() - c0) * 1e3
+        conv = {"iterations": it, "ms": round(conv_ms, 3), "final_residual": res, "start": "uniform",
+                "contrib": args.contrib}
+        log(f"converged to L1 residual {res:.2e} in {it} iterations, {conv_ms:.1f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(g)
+        log(f"cpu oracle {cpu['value']:.3f} GTEPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": "GTEPS per PageRank iter at R-MAT-25",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if ct == cagra.F32 else "bf16-gather/f32-accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"pagerank_rmat{args.scale}_ef{args.edge_factor}_seed{args.seed}",
+                   "V": V, "E": E, "N": args.N, "B": args.B, "tile_edges": args.tile_edges, "k": k, "Q": Q,
+                   "q": round(seg.q, 4), "damping": 0.85, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "kernel_ms": round(dms, 4), "algorithmic_bytes": dbytes},
+        "step_roofline_frac": round((gb + mb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels_ms": {"k_gather": round(g_avg, 4), "k_merge_pr+reduce": round(m_avg, 4)},
+        "bytes_per_step": {"gather": gb, "merge": mb},
+        "segment_build_ms": round(build_ms, 2),
+        "time_to_l1_1e-6": conv,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,10 +55,14 @@ enum {
     CAGRA_SUM_F32_COMP = 2   /* float sum with Neumaier compensation (merge only) */
 };
 
-/* Vertices staged per segment: a segment is processed out of LDS when
-   N * element bytes <= CAGRA_LDS_BYTES, otherwise its gathers go through the
-   cache hierarchy (L2 / Infinity Cache sized segments). */
+/* LDS per workgroup on gfx950. */
 #define CAGRA_LDS_BYTES 163840
+/* A segment's values are staged in LDS when N * element bytes <=
+   CAGRA_STAGE_BYTES (32,768 FP32 or 65,536 BF16 / int32 32,768 values); larger
+   segments are gathered through the cache hierarchy (L2- or Infinity-Cache-
+   sized segments). The rest of the LDS collects finished rows for coalesced
+   buffer writes. */
+#define CAGRA_STAGE_BYTES 131072
 /* Waves (64 lanes) that share one staged segment in the gather kernel. */
 #define CAGRA_TILE_WAVES 16
 
@@ -146,7 +150,7 @@ size_t cagra_iter_workspace_bytes(const cagra_segments *seg);
  * subgraph s, partial[r] = op over the row's edges of values[s*N + local src].
  *   op CAGRA_SUM_F32: values are CAGRA_F32 or CAGRA_BF16 (value_type), partial is float[Q]
  *   op CAGRA_MIN_I32: values are CAGRA_I32, partial is int32[Q]
- * Segments with N * element bytes <= CAGRA_LDS_BYTES are staged in LDS.
+ * Segments with N * element bytes <= CAGRA_STAGE_BYTES are staged in LDS.
  */
 cagra_status cagra_segment_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
                                   void *partial, hipStream_t stream);
@@ -191,6 +195,17 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
                                  const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
                                  void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
                                  hipStream_t stream);
+
+/*
+ * The merge half of cagra_pagerank_iter on its own: cache-aware merge of an
+ * already gathered partial[Q] (Section 3.3) followed by the vertex update
+ * (Section 4 VertexMap). cagra_pagerank_iter == cagra_segment_gather(SUM_F32,
+ * contrib_type) + cagra_pagerank_merge; same arguments, same results.
+ */
+cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                  int32_t contrib_type, const float *rank_in, const double *scalars_in,
+                                  const float *partial, float *rank_out, void *contrib_out, double *scalars_out,
+                                  void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * One synchronous min-label propagation step on a segmented undirected graph

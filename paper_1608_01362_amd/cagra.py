@@ -21,6 +21,7 @@ OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_BUFFER, E_HIP = 0, -1, -2, -3, -4, -5
 F32, BF16, I32 = 0, 1, 2
 SUM_F32, MIN_I32, SUM_F32_COMP = 0, 1, 2
 LDS_BYTES = 163840
+STAGE_BYTES = 131072
 TILE_WAVES = 16
 
 _c_i32, _c_i64, _c_size, _c_vp, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
@@ -42,7 +43,7 @@ EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
     "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
-    "cagra_labelprop_iter",
+    "cagra_pagerank_merge", "cagra_labelprop_iter",
 ]
 
 
@@ -75,6 +76,8 @@ def lib():
             "cagra_pagerank_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_pagerank_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                      _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                      _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -230,6 +233,14 @@ def pagerank_iter(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: 
                                      workspace.numel(), _stream(stream)), "cagra_pagerank_iter")
 
 
+def pagerank_merge(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, scalars_in,
+                   partial, rank_out, contrib_out, scalars_out, workspace, stream=None):
+    _check(lib().cagra_pagerank_merge(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, contrib_type,
+                                      _ptr(rank_in), _ptr(scalars_in), _ptr(partial), _ptr(rank_out),
+                                      _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace), workspace.numel(),
+                                      _stream(stream)), "cagra_pagerank_merge")
+
+
 def labelprop_iter(seg: Segments, labels_in, partial, labels_out, changed_out, workspace, stream=None):
     _check(lib().cagra_labelprop_iter(ctypes.byref(seg.c), _ptr(labels_in), _ptr(partial), _ptr(labels_out),
                                       _ptr(changed_out), _ptr(workspace), workspace.numel(), _stream(stream)),
@@ -268,6 +279,21 @@ class PageRankState:
         pagerank_iter(self.dg, self.seg, damping, self.contrib_type, self.rank[a], self.contrib[a],
                       self.scalars[a], self.partial, self.rank[b], self.contrib[b], self.scalars[b], self.ws,
                       stream)
+        self.cur = b
+
+    def step_split(self, damping: float = 0.85, stream=None, events=None):
+        """Same step as step(), issued as the gather call then the merge call;
+        events (3 torch.cuda.Event) are recorded before, between and after."""
+        a, b = self.cur, 1 - self.cur
+        if events:
+            events[0].record()
+        segment_gather(self.seg, SUM_F32, self.contrib_type, self.contrib[a], self.partial, stream)
+        if events:
+            events[1].record()
+        pagerank_merge(self.dg, self.seg, damping, self.contrib_type, self.rank[a], self.scalars[a], self.partial,
+                       self.rank[b], self.contrib[b], self.scalars[b], self.ws, stream)
+        if events:
+            events[2].record()
         self.cur = b
 
     @property

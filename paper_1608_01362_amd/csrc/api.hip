@@ -170,11 +170,8 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
     return launch_pr_init(g, contrib_type, rank, contrib_out, scalars_out, (double *)workspace, stream);
 }
 
-cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                 int32_t contrib_type, const float *rank_in,
-                                 const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
-                                 void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
-                                 hipStream_t stream) {
+static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                   int32_t contrib_type, size_t workspace_bytes, const void *workspace) {
     cagra_status s;
     if ((s = check_graph(g, true)) != CAGRA_OK) return s;
     if ((s = check_built(seg)) != CAGRA_OK) return s;
@@ -182,14 +179,35 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
     if (!(damping >= 0.0 && damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
     if (contrib_type != CAGRA_F32 && contrib_type != CAGRA_BF16)
         return fail(CAGRA_E_INVALID, "contrib_type must be CAGRA_F32 or CAGRA_BF16");
-    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
-        (seg->Q > 0 && !partial))
-        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
     if (!workspace || workspace_bytes < iter_ws_bytes(seg->V, seg->nb))
         return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg->V, seg->nb),
                     workspace_bytes);
+    return CAGRA_OK;
+}
+
+cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                  int32_t contrib_type, const float *rank_in, const double *scalars_in,
+                                  const float *partial, float *rank_out, void *contrib_out, double *scalars_out,
+                                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_pagerank(g, seg, damping, contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (!rank_in || !scalars_in || !rank_out || !contrib_out || !scalars_out || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
+                           scalars_out, (double *)workspace, stream);
+}
+
+cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                 int32_t contrib_type, const float *rank_in, const void *contrib_in,
+                                 const double *scalars_in, float *partial, float *rank_out, void *contrib_out,
+                                 double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_pagerank(g, seg, damping, contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
+        (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
                            scalars_out, (double *)workspace, stream);

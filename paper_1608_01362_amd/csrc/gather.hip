@@ -4,7 +4,7 @@
 //
 // Work unit = tile: a row-aligned range of one subgraph's edges. The 16 waves
 // of a workgroup share the segment's values, staged once into LDS (up to
-// 160 KB: 40,960 FP32 or 81,920 BF16 values); larger segments are read through
+// 128 KB: 32,768 FP32 or 65,536 BF16 values); larger segments are read through
 // the cache hierarchy instead (L2- or Infinity-Cache-sized segments). Each wave
 // streams an equal share of the tile's edge array with 16-byte non-temporal
 // loads. Row boundaries are bit 31 of the edge word, so the per-row
@@ -18,27 +18,14 @@ namespace cagra {
 
 constexpr int kGatherWaves = CAGRA_TILE_WAVES;  // 16 waves, 1024 threads
 constexpr int kGatherThreads = kGatherWaves * kWave;
-constexpr int kEPT = 16;                        // edges per lane per chunk
+constexpr int kEPT = 8;                         // edges per lane per chunk
 constexpr int kChunk = kWave * kEPT;            // edges per wave per chunk
+// Per-wave LDS area where a chunk's finished rows (at most kChunk) are
+// collected, so that they leave as contiguous 256-byte wave stores.
+constexpr int kStageRows = kChunk;
+constexpr size_t kStageBytes = (size_t)kGatherWaves * kStageRows * 4;
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void load_edges(const int32_t *__restrict__ p, int64_t idx, int64_t E,
-                                           int32_t (&w)[kEPT]) {
-    if (idx + kEPT <= E) {
-#pragma unroll
-        for (int j = 0; j < kEPT / 4; ++j) {
-            v4i v = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p + idx) + j);
-            w[4 * j + 0] = v.x;
-            w[4 * j + 1] = v.y;
-            w[4 * j + 2] = v.z;
-            w[4 * j + 3] = v.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < kEPT; ++i) w[i] = (idx + i < E) ? p[idx + i] : 0;
-    }
-}
 
 // Source value fetch: from the staged LDS copy, or from global memory.
 template <typename VT, bool STAGED>
@@ -101,15 +88,159 @@ __device__ __forceinline__ void stage_segment(const VT *__restrict__ g, int32_t 
     }
 }
 
+// ---- wave-level scans with DPP (row shifts within 16 lanes, then row broadcasts)
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int32_t dpp_i(int32_t old, int32_t x) {
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float old, float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWMASK, 0xf,
+                                                      false));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int32_t dpp_t(int32_t old, int32_t x) { return dpp_i<CTRL, ROWMASK>(old, x); }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_t(float old, float x) { return dpp_f<CTRL, ROWMASK>(old, x); }
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void add_step(int32_t &x) { x += dpp_i<CTRL, ROWMASK>(0, x); }
+
+__device__ __forceinline__ int32_t wave_incl_sum(int32_t x) {
+    add_step<kDppRowShr1, 0xf>(x);
+    add_step<kDppRowShr2, 0xf>(x);
+    add_step<kDppRowShr4, 0xf>(x);
+    add_step<kDppRowShr8, 0xf>(x);
+    add_step<kDppRowBcast15, 0xa>(x);
+    add_step<kDppRowBcast31, 0xc>(x);
+    return x;
+}
+
+// One step of the segmented scan (flag f, value v): a lane keeps its value if
+// it holds a row start, else prepends the value of the lanes before it.
+template <class Op, int CTRL, int ROWMASK>
+__device__ __forceinline__ void seg_step(int32_t &f, typename Op::T &v) {
+    using T = typename Op::T;
+    const T pv = dpp_t<CTRL, ROWMASK>(Op::identity(), v);
+    const int32_t pf = dpp_i<CTRL, ROWMASK>(0, f);
+    v = f ? v : Op::apply(pv, v);
+    f |= pf;
+}
+
+template <class Op>
+__device__ __forceinline__ void wave_seg_scan(int32_t &f, typename Op::T &v) {
+    seg_step<Op, kDppRowShr1, 0xf>(f, v);
+    seg_step<Op, kDppRowShr2, 0xf>(f, v);
+    seg_step<Op, kDppRowShr4, 0xf>(f, v);
+    seg_step<Op, kDppRowShr8, 0xf>(f, v);
+    seg_step<Op, kDppRowBcast15, 0xa>(f, v);
+    seg_step<Op, kDppRowBcast31, 0xc>(f, v);
+}
+
+__device__ __forceinline__ int32_t readlane_t(int32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float readlane_t(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+constexpr int32_t kBufFlags = 0x00020000;   // raw buffer descriptor word 3 (gfx9)
+constexpr int kNonTemporal = 2;             // cache policy: streaming
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+// Per-wave state carried from chunk to chunk.
+template <typename T>
+struct SpanState {
+    T carry;        // value of the row open at the current chunk start
+    T head;         // value of the row that began before the wave's share
+    int32_t nflags; // row starts seen in earlier chunks
+};
+
+// Processes one chunk of kChunk edges (this lane: kEPT consecutive edges).
+// Rows finished in the chunk are exactly chunk_nf consecutive rows starting
+// at row0 + nflags - 1; they are collected in `stage` and written with
+// coalesced stores.
+template <class Op, typename VT, bool STAGED>
+__device__ __forceinline__ void process_chunk(const v4i (&wv)[kEPT / 4], int64_t cidx, int64_t w0, int64_t w1,
+                                              const VT *seg_vals, const VT *gvals, typename Op::T *stage,
+                                              __amdgpu_buffer_rsrc_t out, SpanState<typename Op::T> &S) {
+    using T = typename Op::T;
+    using F = Fetch<VT, STAGED>;
+    const int lane = __lane_id();
+    const int64_t idx = cidx + lane * kEPT;
+    int32_t w[kEPT];
+#pragma unroll
+    for (int j = 0; j < kEPT / 4; ++j) {
+        w[4 * j + 0] = wv[j].x;
+        w[4 * j + 1] = wv[j].y;
+        w[4 * j + 2] = wv[j].z;
+        w[4 * j + 3] = wv[j].w;
+    }
+    uint32_t fmask = 0;
+    T v[kEPT];
+#pragma unroll
+    for (int i = 0; i < kEPT; ++i) {
+        const bool valid = (idx + i >= w0) && (idx + i < w1);
+        fmask |= (valid && w[i] < 0) ? (1u << i) : 0u;
+        // words outside the share may belong to another segment: read index 0 instead
+        const T x = F::get(seg_vals, gvals, valid ? (w[i] & 0x7fffffff) : 0);
+        v[i] = valid ? x : Op::identity();
+    }
+    const int32_t nf = __popc(fmask);
+    const int32_t incl_nf = wave_incl_sum(nf);
+    const int32_t excl_nf = incl_nf - nf;
+    const int32_t chunk_nf = __builtin_amdgcn_readlane(incl_nf, 63);
+
+    // lane-local pass: every row start after the lane's first closes a row
+    // that lies entirely inside the lane
+    T run = Op::identity(), headpart = Op::identity();
+    int32_t j = 0;
+#pragma unroll
+    for (int i = 0; i < kEPT; ++i) {
+        const bool f = (fmask >> i) & 1u;
+        if (f && j > 0) stage[excl_nf + j] = run;
+        headpart = (f && j == 0) ? run : headpart;
+        j += f ? 1 : 0;
+        run = f ? v[i] : Op::apply(run, v[i]);
+    }
+    // segmented inclusive scan of (has row start, tail value) over the wave
+    T sv = run;
+    int32_t sf = nf > 0;
+    wave_seg_scan<Op>(sf, sv);
+    const T ex_v = dpp_t<kDppWaveShr1, 0xf>(Op::identity(), sv);
+    const int32_t ex_f = dpp_i<kDppWaveShr1, 0xf>(0, sf);
+    const T incoming = ex_f ? ex_v : Op::apply(S.carry, ex_v);
+    if (nf > 0) stage[excl_nf] = Op::apply(incoming, headpart);
+    __builtin_amdgcn_wave_barrier();
+    // stage[0] is the row that began before this wave's share when the wave
+    // had not seen a row start yet: that one is completed across waves later
+    const bool head_here = S.nflags == 0 && chunk_nf > 0;
+    const int32_t rbase = S.nflags - 1;  // staged index 0 <-> row row0 + rbase
+#pragma unroll
+    for (int r = 0; r < kEPT; ++r) {
+        const int32_t i = r * kWave + lane;
+        const T val = stage[i];
+        const bool ok = i < chunk_nf && !(head_here && i == 0);
+        const uint32_t off = ok ? (uint32_t)(rbase + i) * (uint32_t)sizeof(T) : kOutOfRange;
+        __builtin_amdgcn_raw_buffer_store_b32(*reinterpret_cast<const int32_t *>(&val), out, off, 0, 0);
+    }
+    if (head_here) S.head = stage[0];
+    __builtin_amdgcn_wave_barrier();
+    const T in63 = readlane_t(sv, 63);
+    const int32_t f63 = __builtin_amdgcn_readlane(sf, 63);
+    S.carry = f63 ? in63 : Op::apply(S.carry, in63);
+    S.nflags += chunk_nf;
+}
+
 template <class Op, typename VT, bool STAGED>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
-    const int32_t *__restrict__ edge_src, int64_t E, const int32_t *__restrict__ tile_edge,
+    const int32_t *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
     const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
     int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial) {
     using T = typename Op::T;
-    using F = Fetch<VT, STAGED>;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    VT *seg_vals = reinterpret_cast<VT *>(smem);
+    VT *seg_vals = reinterpret_cast<VT *>(smem + kStageBytes);
 
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
@@ -124,7 +255,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
         __syncthreads();
     }
 
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave index as a scalar, so that everything derived from it stays in SGPRs
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t sl = (e1 - e0 + kGatherWaves - 1) / kGatherWaves;
     int64_t w0 = e0 + w * sl;
     if (w0 > e1) w0 = e1;
@@ -132,96 +264,47 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     if (w1 > e1) w1 = e1;
     const int32_t row0 = span_row[(int64_t)t * kGatherWaves + w];
 
-    T carry = Op::identity();  // value of the row open at the current chunk start
-    T head = Op::identity();
-    int32_t nflags = 0;        // row starts seen by this wave in earlier chunks
-    const uint64_t lt = lanemask_lt();
+    // Buffer descriptors: loads past the share read zero, and stores to rows
+    // outside [row0, Q) are dropped, so the loop needs no bounds branches.
+    const int64_t ebase = w0 & ~(int64_t)3;
+    const __amdgpu_buffer_rsrc_t ein =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(edge_src + ebase), 0, (int32_t)((w1 - ebase) * 4), kBufFlags);
+    int64_t rows_left = Q - row0;
+    if (rows_left > (1 << 28)) rows_left = 1 << 28;
+    if (rows_left < 0) rows_left = 0;
+    const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(partial + row0), 0, (int32_t)(rows_left * (int64_t)sizeof(T)), kBufFlags);
 
-    int64_t c = w0 & ~(int64_t)3;
-    int32_t cur[kEPT], nxt[kEPT];
-    if (c < w1) load_edges(edge_src, c + lane * kEPT, E, cur);
-    for (; c < w1; c += kChunk) {
-        const int64_t cn = c + kChunk;
-        if (cn < w1) load_edges(edge_src, cn + lane * kEPT, E, nxt);
-        const int64_t idx = c + lane * kEPT;
-        uint32_t fmask = 0;
-        T v[kEPT];
+    SpanState<T> S{Op::identity(), Op::identity(), 0};
+    T *stage = reinterpret_cast<T *>(smem) + (size_t)w * kStageRows;
+    const int64_t len = w1 - ebase;
+    v4i A[kEPT / 4], Bv[kEPT / 4];
+    const uint32_t lane_off = (uint32_t)lane * kEPT * 4;
 #pragma unroll
-        for (int i = 0; i < kEPT; ++i) {
-            const bool valid = (idx + i >= w0) && (idx + i < w1);
-            const int32_t wd = cur[i];
-            fmask |= (valid && wd < 0) ? (1u << i) : 0u;
-            v[i] = valid ? F::get(seg_vals, gvals, wd & 0x7fffffff) : Op::identity();
-        }
-        const int nf = __popc(fmask);
-        // exclusive prefix of row starts over lanes, and the chunk total
-        int32_t incl_nf = nf;
+    for (int j = 0; j < kEPT / 4; ++j)
+        A[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, lane_off + 16 * j, 0, kNonTemporal);
+    for (int64_t cc = 0; cc < len; cc += 2 * kChunk) {
+        const uint32_t ob = (uint32_t)(cc + kChunk) * 4 + lane_off;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            int32_t o = __shfl_up(incl_nf, d, 64);
-            if (lane >= d) incl_nf += o;
-        }
-        const int32_t excl_nf = incl_nf - nf;
-        const int32_t chunk_nf = __shfl(incl_nf, 63, 64);
-        const int32_t rb = row0 + nflags + excl_nf;  // row started by this lane's first flag
-
-        // lane-local: rows that start and end inside the lane are written here
-        T run = Op::identity(), headpart = Op::identity();
-        int j = 0;
+        for (int j = 0; j < kEPT / 4; ++j)
+            Bv[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, ob + 16 * j, 0, kNonTemporal);
+        process_chunk<Op, VT, STAGED>(A, ebase + cc, w0, w1, seg_vals, gvals, stage, out, S);
+        const uint32_t oa = (uint32_t)(cc + 2 * kChunk) * 4 + lane_off;
 #pragma unroll
-        for (int i = 0; i < kEPT; ++i) {
-            if ((fmask >> i) & 1u) {
-                if (j == 0) headpart = run;
-                else partial[rb + j - 1] = run;
-                ++j;
-                run = Op::identity();
-            }
-            run = Op::apply(run, v[i]);
-        }
-        // segmented inclusive scan of (has_flag, tail value) across lanes
-        T sv = run;
-        int sf = nf > 0;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            T ov = __shfl_up(sv, d, 64);
-            int of = __shfl_up(sf, d, 64);
-            if (lane >= d) {
-                if (!sf) sv = Op::apply(ov, sv);
-                sf |= of;
-            }
-        }
-        T ex_v = __shfl_up(sv, 1, 64);
-        int ex_f = __shfl_up(sf, 1, 64);
-        if (lane == 0) {
-            ex_v = Op::identity();
-            ex_f = 0;
-        }
-        const T incoming = ex_f ? ex_v : Op::apply(carry, ex_v);
-        const T closed = Op::apply(incoming, headpart);
-        const bool first_of_wave = nf > 0 && nflags + excl_nf == 0;
-        if (nf > 0 && !first_of_wave) partial[rb - 1] = closed;
-        // the row that began before this wave's share ends at the wave's first
-        // row start; that lane's value is broadcast for the cross-wave fix-up
-        const uint64_t hm = __ballot(first_of_wave);
-        if (hm) head = __shfl(closed, __ffsll((unsigned long long)hm) - 1, 64);
-        const T in63 = __shfl(sv, 63, 64);
-        const int f63 = __shfl(sf, 63, 64);
-        carry = f63 ? in63 : Op::apply(carry, in63);
-        nflags += chunk_nf;
-#pragma unroll
-        for (int i = 0; i < kEPT; ++i) cur[i] = nxt[i];
+        for (int j = 0; j < kEPT / 4; ++j)
+            A[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, oa + 16 * j, 0, kNonTemporal);
+        process_chunk<Op, VT, STAGED>(Bv, ebase + cc + kChunk, w0, w1, seg_vals, gvals, stage, out, S);
     }
-    (void)lt;
 
     // complete rows that continue into later waves' shares, in wave order
     __syncthreads();  // all waves are done with the staged values
     WaveFix<T> *fix = reinterpret_cast<WaveFix<T> *>(smem);
     if (lane == 0) {
         WaveFix<T> f;
-        f.has = nflags > 0;
-        f.head = f.has ? head : carry;
-        f.last = carry;
-        f.row = row0 + nflags - 1;
+        f.has = S.nflags > 0;
+        f.head = f.has ? S.head : S.carry;
+        f.last = S.carry;
+        f.row = row0 + S.nflags - 1;
         fix[w] = f;
     }
     __syncthreads();
@@ -243,14 +326,13 @@ static cagra_status launch_gather_t(const cagra_segments *seg, const VT *values,
                                     hipStream_t st) {
     if (seg->ntiles == 0) return CAGRA_OK;
     auto kern = k_gather<Op, VT, STAGED>;
-    size_t lds = STAGED ? (size_t)seg->N * sizeof(VT) : 0;
-    if (lds < kGatherWaves * sizeof(WaveFix<typename Op::T>)) lds = kGatherWaves * sizeof(WaveFix<typename Op::T>);
+    const size_t lds = kStageBytes + (STAGED ? (size_t)seg->N * sizeof(VT) : 0);
     static bool attr_set = false;
     if (!attr_set) {
         if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
         attr_set = true;
     }
-    kern<<<seg->ntiles, kGatherThreads, lds, st>>>(seg->edge_src, seg->E, seg->tile_edge, seg->tile_seg,
+    kern<<<seg->ntiles, kGatherThreads, lds, st>>>(seg->edge_src, seg->E, seg->Q, seg->tile_edge, seg->tile_seg,
                                                   seg->tile_span_row, values, seg->V, seg->N, seg->ntiles, partial);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
@@ -258,7 +340,8 @@ static cagra_status launch_gather_t(const cagra_segments *seg, const VT *values,
 
 bool gather_staged(int32_t N, int32_t value_type) {
     size_t bytes = value_type == CAGRA_BF16 ? 2 : 4;
-    return (size_t)N * bytes <= CAGRA_LDS_BYTES;
+    static_assert(kStageBytes + CAGRA_STAGE_BYTES <= CAGRA_LDS_BYTES, "LDS budget");
+    return (size_t)N * bytes <= CAGRA_STAGE_BYTES;
 }
 
 cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
