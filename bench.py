@@ -36,10 +36,10 @@ def log(msg):
 def byte_model(V, E, Q, k, nb, wc):
     """Algorithmic HBM bytes per iteration (what the method must move).
     gather: edge words (4E) + each segment's values staged once (wc*V) + buffer writes (4Q)
-    merge:  buffer reads (4Q) + row destinations (4Q) + block index (4k(nb+1))
+    merge:  buffer reads (4Q) + destination offsets in the block (2Q, uint16) + block index (4k(nb+1))
             + rank_in, out_degree, rank_out (12V) + contrib_out (wc*V)"""
     gather = 4 * E + wc * V + 4 * Q
-    merge = 8 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
+    merge = 6 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
     return gather, merge
 
 
@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--N", type=int, default=32768, help="vertices per segment")
     ap.add_argument("--B", type=int, default=8192, help="merge block (vertices)")
-    ap.add_argument("--tile-edges", type=int, default=65536)
+    ap.add_argument("--tile-edges", type=int, default=262144)
     ap.add_argument("--contrib", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")

@@ -95,6 +95,8 @@ typedef struct {
  *   tile_seg[ntiles]
  *   tile_span_row[ntiles*CAGRA_TILE_WAVES]  for each tile, the first row that
  *                        starts at or after each wave's share of the tile
+ *   row_dst_lo[Q]        row_dst mod B as uint16: the destination's offset in
+ *                        its merge block (what the fused merges read)
  *
  * edge_src must be 16-byte aligned. All arrays are caller-allocated device
  * memory of the sizes the query call reports.
@@ -117,6 +119,7 @@ typedef struct {
     int32_t *tile_edge;
     int32_t *tile_seg;
     int32_t *tile_span_row;
+    uint16_t *row_dst_lo;
 } cagra_segments;
 
 int cagra_abi_version(void);

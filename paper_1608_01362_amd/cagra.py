@@ -36,7 +36,8 @@ class CSegments(ctypes.Structure):
                 ("V", _c_i32), ("k", _c_i32), ("nb", _c_i32), ("ntiles", _c_i32),
                 ("E", _c_i64), ("Q", _c_i64), ("build_workspace_bytes", _c_size),
                 ("seg_row_begin", _c_vp), ("row_ptr", _c_vp), ("row_dst", _c_vp), ("edge_src", _c_vp),
-                ("block_ptr", _c_vp), ("tile_edge", _c_vp), ("tile_seg", _c_vp), ("tile_span_row", _c_vp)]
+                ("block_ptr", _c_vp), ("tile_edge", _c_vp), ("tile_seg", _c_vp), ("tile_span_row", _c_vp),
+                ("row_dst_lo", _c_vp)]
 
 
 EXPORTS = [
@@ -187,6 +188,7 @@ def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = Non
         "tile_edge": torch.empty(nt + 1, dtype=i32, device=dev),
         "tile_seg": torch.empty(max(nt, 1), dtype=i32, device=dev),
         "tile_span_row": torch.empty(max(nt, 1) * TILE_WAVES, dtype=i32, device=dev),
+        "row_dst_lo": torch.empty(max(Q, 1), dtype=torch.int16, device=dev),
     }
     for name, t in arrays.items():
         setattr(c, name, t.data_ptr())
@@ -199,6 +201,7 @@ def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = Non
     arrays["edge_src"] = arrays["edge_src"][:E]
     arrays["tile_seg"] = arrays["tile_seg"][:nt]
     arrays["tile_span_row"] = arrays["tile_span_row"][:nt * TILE_WAVES]
+    arrays["row_dst_lo"] = arrays["row_dst_lo"][:Q]
     return Segments(c, arrays)
 
 

@@ -70,7 +70,7 @@ static cagra_status check_built(const cagra_segments *seg) {
         seg->nb != (int32_t)ceil_div(seg->V, seg->B) || seg->Q < 0 || seg->Q > seg->E || seg->ntiles < 0)
         return fail(CAGRA_E_INVALID, "segments sizes are inconsistent (not built?)");
     if (!seg->seg_row_begin || !seg->row_ptr || !seg->row_dst || !seg->edge_src || !seg->block_ptr ||
-        !seg->tile_edge || !seg->tile_seg || !seg->tile_span_row)
+        !seg->tile_edge || !seg->tile_seg || !seg->tile_span_row || !seg->row_dst_lo)
         return fail(CAGRA_E_INVALID, "a segments array is NULL");
     if (((uintptr_t)seg->edge_src & 15) != 0) return fail(CAGRA_E_INVALID, "edge_src must be 16-byte aligned");
     return CAGRA_OK;

@@ -280,12 +280,14 @@ __global__ void k_seg_begin(const int32_t *__restrict__ offsets, int32_t k, int3
 }
 
 __global__ void k_rows(const int32_t *__restrict__ run_first, const int32_t *__restrict__ run_dst,
-                       const int32_t *__restrict__ pos, int64_t Q, int32_t *__restrict__ row_dst,
-                       int32_t *__restrict__ row_len) {
+                       const int32_t *__restrict__ pos, int64_t Q, int32_t B, int32_t *__restrict__ row_dst,
+                       uint16_t *__restrict__ row_dst_lo, int32_t *__restrict__ row_len) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < Q) {
         int32_t p = pos[r];
-        row_dst[p] = run_dst[r];
+        int32_t d = run_dst[r];
+        row_dst[p] = d;
+        row_dst_lo[p] = (uint16_t)(d % B);
         row_len[p] = run_first[r + 1] - run_first[r];
     }
     if (r == Q) row_len[Q] = 0;
@@ -529,7 +531,8 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     k_seg_begin<<<grid_for(k + 1, 256), 256, 0, st>>>(counts, k, (int32_t)nchunks, Q, seg->seg_row_begin);
     CAGRA_LAUNCH_CHECK();
     // 3. rows and edges
-    k_rows<<<grid_for(Q + 1, 256), 256, 0, st>>>(run_first, run_dst, pos, Q, seg->row_dst, seg->row_ptr);
+    k_rows<<<grid_for(Q + 1, 256), 256, 0, st>>>(run_first, run_dst, pos, Q, B, seg->row_dst, seg->row_dst_lo,
+                                                 seg->row_ptr);
     CAGRA_LAUNCH_CHECK();
     if ((s = scan_i32<ScanAdd>(seg->row_ptr, seg->row_ptr, Q + 1, false, ar, st)) != CAGRA_OK) return s;
     k_edges<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N, seg->edge_src);

@@ -24,7 +24,6 @@
 namespace cagra {
 
 constexpr int kMergeThreads = 1024;
-constexpr double kFixScale = 72057594037927936.0;      // 2^56
 constexpr double kFixInv = 1.0 / 72057594037927936.0;  // 2^-56
 
 // Dynamic LDS of the fused merges; kFusedStaticLds covers their static arrays.
@@ -156,25 +155,71 @@ __device__ int32_t load_block_ranges(const int32_t *__restrict__ block_ptr, int 
     return P;
 }
 
-// Entry index of flattened position f: subgraph = last s with pre[s] <= f.
-__device__ __forceinline__ int32_t flat_to_entry(const int32_t *pre, const int32_t *lo_s, int32_t k, int32_t f) {
+// Last subgraph s with pre[s] <= f (pre is non-decreasing; empty ranges skipped).
+__device__ __forceinline__ int32_t run_of(const int32_t *pre, int32_t k, int32_t f) {
     int32_t lo = 0, hi = k;
     while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
+        const int32_t mid = (lo + hi) >> 1;
         if (pre[mid] <= f) lo = mid;
         else hi = mid;
     }
-    return lo_s[lo] + (f - pre[lo]);
+    return lo;
 }
 
-constexpr int kUnroll = 4;
+// round(x * 2^56) as a two's-complement int64, computed from the float's bits
+// (exact for |x| < 64; halves round up in magnitude).
+__device__ __forceinline__ unsigned long long fix56(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const int e = (int)((u >> 23) & 0xffu);
+    const uint64_t m = (uint64_t)((u & 0x7fffffu) | (e ? 0x800000u : 0u));
+    const int sh = (e ? e : 1) - 94;
+    uint64_t r = 0;
+    if (sh >= 0) r = m << (sh & 63);
+    else if (sh > -26) r = ((m >> (-sh - 1)) + 1) >> 1;
+    return (u >> 31) ? (unsigned long long)(-(int64_t)r) : (unsigned long long)r;
+}
+
+constexpr int kUnroll = 8;
+
+// Streams block b's buffer entries (the ranges of all subgraphs, flattened).
+// Each wave takes a contiguous share; per pass a lane handles kUnroll entries
+// 64 apart, finding its subgraph by walking forward from the pass's first one.
+// All loads are issued unconditionally (clamped index) so that many are in
+// flight; apply(d, x) updates the LDS accumulator of block offset d.
+template <typename PT, class Apply>
+__device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, const PT *__restrict__ partial,
+                                             const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t P,
+                                             Apply apply) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int32_t share = (((P + 15) / 16) + 63) & ~63;
+    const int32_t fa = min(w * share, P), fb = min(fa + share, P);
+    for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
+        int32_t sl = run_of(pre, k, f0);
+        int32_t d[kUnroll];
+        PT x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + u * kWave + lane;
+            const bool valid = f < fb;
+            const int32_t ff = valid ? f : f0;
+            while (sl + 1 < k && pre[sl + 1] <= ff) ++sl;
+            const int32_t i = lo_s[sl] + (ff - pre[sl]);
+            const int32_t dd = (int32_t)__builtin_nontemporal_load(dlo + i);
+            x[u] = __builtin_nontemporal_load(partial + i);
+            d[u] = valid ? dd : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (d[u] >= 0) apply(d[u], x[u]);
+    }
+}
 
 template <bool BF16OUT>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
-    const int32_t *__restrict__ row_dst, const int32_t *__restrict__ block_ptr, const float *__restrict__ partial,
-    int32_t V, int32_t k, int32_t B, int32_t nb, const float *__restrict__ rank_in,
-    const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
-    float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
+    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
+    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb,
+    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
+    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
@@ -187,26 +232,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-
-    for (int32_t f0 = threadIdx.x; f0 < P; f0 += kMergeThreads * kUnroll) {
-        int32_t d[kUnroll];
-        float x[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + u * kMergeThreads;
-            if (f < P) {
-                const int32_t i = flat_to_entry(pre, lo_s, k, f);
-                d[u] = __builtin_nontemporal_load(row_dst + i) - (int32_t)vb;
-                x[u] = __builtin_nontemporal_load(partial + i);
-            } else {
-                d[u] = -1;
-                x[u] = 0.0f;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (d[u] >= 0) atomicAdd(&acc[d[u]], (unsigned long long)llrint((double)x[u] * kFixScale));
-    }
+    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, P,
+                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
     __syncthreads();
 
     const double dd = damping;
@@ -237,9 +264,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
 }
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
-    const int32_t *__restrict__ row_dst, const int32_t *__restrict__ block_ptr, const int32_t *__restrict__ partial,
-    int32_t V, int32_t k, int32_t B, int32_t nb, const int32_t *__restrict__ labels_in,
-    int32_t *__restrict__ labels_out, int32_t *__restrict__ blk_changed) {
+    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
+    const int32_t *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb,
+    const int32_t *__restrict__ labels_in, int32_t *__restrict__ labels_out, int32_t *__restrict__ blk_changed) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int32_t *acc = reinterpret_cast<int32_t *>(smem);
     int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
@@ -252,25 +279,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-
-    for (int32_t f0 = threadIdx.x; f0 < P; f0 += kMergeThreads * kUnroll) {
-        int32_t d[kUnroll], x[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + u * kMergeThreads;
-            if (f < P) {
-                const int32_t i = flat_to_entry(pre, lo_s, k, f);
-                d[u] = __builtin_nontemporal_load(row_dst + i) - (int32_t)vb;
-                x[u] = __builtin_nontemporal_load(partial + i);
-            } else {
-                d[u] = -1;
-                x[u] = 0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (d[u] >= 0) atomicMin(&acc[d[u]], x[u]);
-    }
+    stream_block<int32_t>(row_dst_lo, partial, lo_s, pre, k, P,
+                          [&](int32_t d, int32_t x) { atomicMin(&acc[d], x); });
     __syncthreads();
     int32_t changed = 0;
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
@@ -365,7 +375,7 @@ cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, do
             if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<true>)) return a_;
             attr = true;
         }
-        k_merge_pr<true><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k,
+        k_merge_pr<true><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k,
                                                               seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
                                                               damping, rank_out, contrib_out, blk);
     } else {
@@ -374,7 +384,7 @@ cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, do
             if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<false>)) return a_;
             attr = true;
         }
-        k_merge_pr<false><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k,
+        k_merge_pr<false><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k,
                                                                seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
                                                                damping, rank_out, contrib_out, blk);
     }
@@ -392,7 +402,7 @@ cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in
         if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_lp)) return a_;
         attr = true;
     }
-    k_merge_lp<<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst, seg->block_ptr, partial, seg->V, seg->k, seg->B,
+    k_merge_lp<<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k, seg->B,
                                                     seg->nb, labels_in, labels_out, blk);
     CAGRA_LAUNCH_CHECK();
     k_reduce_i32<<<1, 256, 0, st>>>(blk, seg->nb, changed_out);

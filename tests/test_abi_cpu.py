@@ -105,7 +105,8 @@ def test_calls_reject_unbuilt_segments(cagra):
 def _fake_built(c, V=100, N=10, B=10, E=50, Q=20, align=16):
     s = _seg(c, N=N, B=B)
     s.V, s.E, s.Q, s.k, s.nb, s.ntiles = V, E, Q, -(-V // N), -(-V // B), 1
-    for name in ("seg_row_begin", "row_ptr", "row_dst", "block_ptr", "tile_edge", "tile_seg", "tile_span_row"):
+    for name in ("seg_row_begin", "row_ptr", "row_dst", "block_ptr", "tile_edge", "tile_seg", "tile_span_row",
+                 "row_dst_lo"):
         setattr(s, name, 4096)
     s.edge_src = 4096 + (0 if align == 16 else 4)
     return s

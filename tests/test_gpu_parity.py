@@ -52,6 +52,7 @@ def check_layout(c, g, N, B, T):
     assert np.array_equal(h["seg_row_begin"], ref.seg_row_begin)
     assert np.array_equal(h["row_ptr"], ref.row_ptr)
     assert np.array_equal(h["row_dst"], ref.row_dst)
+    assert np.array_equal(h["row_dst_lo"].view(np.uint16).astype(np.int64), ref.row_dst.astype(np.int64) % B)
     assert np.array_equal(h["block_ptr"], ref.block_ptr)
     es = h["edge_src"].view(np.uint32)
     assert np.array_equal((es & 0x7FFFFFFF).astype(np.int32), ref.edge_src)
