@@ -43,6 +43,30 @@ def byte_model(V, E, Q, k, nb, wc):
     return gather, merge
 
 
+def measured_traffic(kernel, workload, args):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, if it was taken on this workload and configuration and the
+    kernel's sources have not changed since; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_rmat25_ef32.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("workload") != workload:
+        return None
+    if (rec.get("N"), rec.get("B"), rec.get("tile_edges"), rec.get("contrib")) != \
+            (args.N, args.B, args.tile_edges, args.contrib):
+        return None
+    h = hashlib.sha256()
+    for f in k["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != k["source_sha256_16"]:
+        return None
+    return int(k["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(g, budget_s=12.0):
     import oracle
     cores = max(1, min(len(os.sched_getaffinity(0)), 16))
@@ -148,6 +172,8 @@ def main():
         dom, dbytes, dms = "k_merge_pr", mb, m_avg
     achieved = dbytes / (dms * 1e-3) / 1e9
     gteps = E / (ms_per_step * 1e-3) / 1e9
+    workload = f"pagerank_rmat{args.scale}_ef{args.edge_factor}_seed{args.seed}"
+    traffic = measured_traffic(dom, workload, args)
 
     conv = None
     if not args.no_converge:
@@ -185,11 +211,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if ct == cagra.F32 else "bf16-gather/f32-accumulate",
         "data": "synthetic",
-        "config": {"workload": f"pagerank_rmat{args.scale}_ef{args.edge_factor}_seed{args.seed}",
+        "config": {"workload": workload,
                    "V": V, "E": E, "N": args.N, "B": args.B, "tile_edges": args.tile_edges, "k": k, "Q": Q,
                    "q": round(seg.q, 4), "damping": 0.85, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                      "kernel_ms": round(dms, 4), "algorithmic_bytes": dbytes},
         "step_roofline_frac": round((gb + mb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_ms": {"k_gather": round(g_avg, 4), "k_merge_pr+reduce": round(m_avg, 4)},
