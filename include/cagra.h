@@ -221,6 +221,42 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
                                   int32_t *labels_out, int32_t *changed_out, void *workspace,
                                   size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Personalized PageRank for many restart vertices (segmented SpMM)          */
+/* ------------------------------------------------------------------------ */
+
+/* Columns per vertex row of the batched calls: vertex values are [V][64] float,
+   column j of vertex v at v*64 + j; columns >= ncols are kept at zero. */
+#define CAGRA_PPR_COLS 64
+
+/* Device workspace of cagra_ppr_init / cagra_ppr_iter for these segments
+   (FP64 per-column partial sums). */
+size_t cagra_ppr_workspace_bytes(const cagra_segments *seg);
+
+/*
+ * Start vectors r_0(v, j) = [v == seeds[j]] for j < ncols (1 <= ncols <= 64;
+ * seeds: device int32[ncols], each in [0, V)), contributions r/out_degree, and
+ * per column j: scalars_out[4j] = dangling mass, [4j+2] = mass (FP64).
+ */
+cagra_status cagra_ppr_init(const cagra_graph *g, int32_t ncols, const int32_t *seeds, float *rank_out,
+                            float *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/*
+ * One iteration for all columns at once: segment processing of the [V][64]
+ * contributions into partial[Q][64] (rows gathered through the cache
+ * hierarchy, one 256-byte source row per edge), the cache-aware merge in the
+ * paper's order (subgraphs ascending, FP32), and the personalized update
+ *   rank_out(v, j) = d * sum_{u->v} contrib_in(u, j) + [v == seeds[j]] * ((1-d) + d * D_j)
+ * with D_j = scalars_in[4j] the dangling mass of column j (returned to the
+ * seed). scalars_out per column: [4j] dangling mass, [4j+1] L1 residual,
+ * [4j+2] mass. Requires seg->B <= 512 (the merge keeps B x 64 floats in LDS).
+ */
+cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t ncols,
+                            const int32_t *seeds, const float *rank_in, const float *contrib_in,
+                            const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
+                            double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

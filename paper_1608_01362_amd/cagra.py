@@ -23,6 +23,7 @@ SUM_F32, MIN_I32, SUM_F32_COMP = 0, 1, 2
 LDS_BYTES = 163840
 STAGE_BYTES = 131072
 TILE_WAVES = 16
+PPR_COLS = 64
 
 _c_i32, _c_i64, _c_size, _c_vp, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -44,7 +45,8 @@ EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
     "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
-    "cagra_pagerank_merge", "cagra_labelprop_iter",
+    "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
+    "cagra_ppr_iter",
 ]
 
 
@@ -80,6 +82,10 @@ def lib():
             "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_ppr_workspace_bytes": ([SP], _c_size),
+            "cagra_ppr_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_ppr_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                _c_vp, _c_size, st], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -347,3 +353,57 @@ def labelprop(seg: Segments, max_iters: int = 1 << 20):
         if int(changed.item()) == 0:
             break
     return lab[cur], it
+
+
+# --------------------------------------------------------------------------- batched personalized PageRank
+
+class PPRState:
+    """Device buffers for personalized PageRank over up to 64 restart vertices at once
+    ([V][64] row-major vertex values)."""
+
+    def __init__(self, dg: DeviceGraph, seg: Segments, seeds):
+        import torch
+        dev = _dev()
+        self.dg, self.seg = dg, seg
+        self.ncols = len(seeds)
+        assert 1 <= self.ncols <= PPR_COLS
+        self.seeds = torch.as_tensor(np.asarray(seeds, dtype=np.int32)).to(dev)
+        V = dg.V
+        self.rank = [torch.empty(V * PPR_COLS, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.contrib = [torch.empty(V * PPR_COLS, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.scalars = [torch.zeros(PPR_COLS * 4, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.partial = torch.empty(max(seg.Q, 1) * PPR_COLS, dtype=torch.float32, device=dev)
+        n = lib().cagra_ppr_workspace_bytes(ctypes.byref(seg.c))
+        self.ws = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.cur = 0
+
+    def start(self, stream=None):
+        self.cur = 0
+        _check(lib().cagra_ppr_init(ctypes.byref(self.dg.c), self.ncols, _ptr(self.seeds), _ptr(self.rank[0]),
+                                    _ptr(self.contrib[0]), _ptr(self.scalars[0]), _ptr(self.ws), self.ws.numel(),
+                                    _stream(stream)), "cagra_ppr_init")
+
+    def step(self, damping: float = 0.85, stream=None):
+        a, b = self.cur, 1 - self.cur
+        _check(lib().cagra_ppr_iter(ctypes.byref(self.dg.c), ctypes.byref(self.seg.c), damping, self.ncols,
+                                    _ptr(self.seeds), _ptr(self.rank[a]), _ptr(self.contrib[a]),
+                                    _ptr(self.scalars[a]), _ptr(self.partial), _ptr(self.rank[b]),
+                                    _ptr(self.contrib[b]), _ptr(self.scalars[b]), _ptr(self.ws), self.ws.numel(),
+                                    _stream(stream)), "cagra_ppr_iter")
+        self.cur = b
+
+    def ranks(self):
+        """[V, ncols] view of the current vectors."""
+        return self.rank[self.cur].view(self.dg.V, PPR_COLS)[:, :self.ncols]
+
+    @property
+    def scalars_now(self):
+        return self.scalars[self.cur].view(PPR_COLS, 4)[:self.ncols]
+
+
+def ppr(dg: DeviceGraph, seg: Segments, seeds, iters: int = 20, damping: float = 0.85):
+    st = PPRState(dg, seg, seeds)
+    st.start()
+    for _ in range(iters):
+        st.step(damping)
+    return st.ranks().clone(), st

@@ -38,7 +38,17 @@ cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, do
 cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
                              int32_t *labels_out, int32_t *changed_out, int32_t *blk, hipStream_t st);
 
+int32_t ppr_init_blocks(int32_t V);
+size_t ppr_merge_lds_bytes(int32_t B);
+cagra_status launch_ppr_init(const cagra_graph *g, int32_t ncols, const int32_t *seeds, float *rank_out,
+                             float *contrib_out, double *scalars_out, double *blk, hipStream_t st);
+cagra_status launch_ppr_iter(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t ncols,
+                             const int32_t *seeds, const float *rank_in, const float *contrib_in,
+                             const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
+                             double *scalars_out, double *blk, hipStream_t st);
+
 static constexpr int32_t kMaxSegments = 32768;
+static constexpr int32_t kMaxPprBlock = 512;
 static constexpr int32_t kMaxMergeBlock = 16384;
 
 static cagra_status check_graph(const cagra_graph *g, bool need_outdeg) {
@@ -227,6 +237,46 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
                     workspace_bytes);
     if ((s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, labels_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, (int32_t *)workspace, stream);
+}
+
+size_t cagra_ppr_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->V < 1) return 0;
+    int64_t n = seg->nb > ppr_init_blocks(seg->V) ? seg->nb : ppr_init_blocks(seg->V);
+    return (size_t)n * CAGRA_PPR_COLS * 4 * sizeof(double) + 256;
+}
+
+cagra_status cagra_ppr_init(const cagra_graph *g, int32_t ncols, const int32_t *seeds, float *rank_out,
+                            float *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if (ncols < 1 || ncols > CAGRA_PPR_COLS) return fail(CAGRA_E_INVALID, "ncols must be in [1, %d]", CAGRA_PPR_COLS);
+    if (!seeds || !rank_out || !contrib_out || !scalars_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    size_t need = (size_t)ppr_init_blocks(g->V) * CAGRA_PPR_COLS * 4 * sizeof(double) + 256;
+    if (!workspace || workspace_bytes < need)
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
+    return launch_ppr_init(g, ncols, seeds, rank_out, contrib_out, scalars_out, (double *)workspace, stream);
+}
+
+cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t ncols,
+                            const int32_t *seeds, const float *rank_in, const float *contrib_in,
+                            const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
+                            double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (!(damping >= 0.0 && damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
+    if (ncols < 1 || ncols > CAGRA_PPR_COLS) return fail(CAGRA_E_INVALID, "ncols must be in [1, %d]", CAGRA_PPR_COLS);
+    if (seg->B > kMaxPprBlock) return fail(CAGRA_E_CAPACITY, "batched merge needs B <= %d (got %d)", kMaxPprBlock, seg->B);
+    if (!seeds || !rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
+        (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (!workspace || workspace_bytes < cagra_ppr_workspace_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", cagra_ppr_workspace_bytes(seg),
+                    workspace_bytes);
+    return launch_ppr_iter(g, seg, damping, ncols, seeds, rank_in, contrib_in, scalars_in, partial, rank_out,
+                           contrib_out, scalars_out, (double *)workspace, stream);
 }
 
 }  // extern "C"
