@@ -257,6 +257,47 @@ cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, dou
                             const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
                             double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Many independent graphs in one launch per kernel                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Plan for running PageRank on many graphs at once. Every graph keeps its own
+ * segments (built with cagra_build_segments, N * 4 <= CAGRA_STAGE_BYTES); the
+ * vectors of all graphs live in shared pools, graph i's at the running offset
+ * of the earlier graphs' V (rank, contrib) and Q (partial). Persistent
+ * workgroups stride over the global tile and merge-block lists, so each
+ * iteration of all graphs is three kernel launches without host
+ * synchronization (capturable into one HIP graph).
+ */
+typedef struct {
+    int32_t ngraphs;
+    int32_t max_k, max_B;            /* filled by cagra_multi_query */
+    int64_t total_V, total_Q, total_tiles, total_blocks;
+    size_t desc_bytes;
+    void *desc;                      /* device, desc_bytes, caller-allocated */
+    float *rank[2], *contrib[2];     /* device pools, total_V each */
+    double *scalars[2];              /* device, 4 * ngraphs each: per graph the
+                                        cagra_pagerank_iter scalars */
+    float *partial;                  /* device, total_Q */
+    double *blk;                     /* device, 4 * total_blocks */
+    int32_t grid_gather, grid_merge; /* filled by cagra_multi_setup */
+} cagra_multi;
+
+/* Host only: validates the host arrays graphs[ngraphs], segs[ngraphs] (device
+   pointers inside) and fills the sizes of *m. */
+cagra_status cagra_multi_query(int32_t ngraphs, const cagra_graph *graphs, const cagra_segments *segs,
+                               cagra_multi *m);
+/* Writes the per-graph descriptors into m->desc (pools must be set);
+   SYNCHRONIZES the stream once. */
+cagra_status cagra_multi_setup(cagra_multi *m, const cagra_graph *graphs, const cagra_segments *segs,
+                               hipStream_t stream);
+/* Uniform start vectors of every graph into pools [0]. */
+cagra_status cagra_multi_pagerank_start(const cagra_multi *m, hipStream_t stream);
+/* One PageRank iteration (as cagra_pagerank_iter, FP32 contributions) of every
+   graph: reads pools [parity], writes pools [1 - parity]. */
+cagra_status cagra_multi_pagerank_step(const cagra_multi *m, int32_t parity, double damping, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

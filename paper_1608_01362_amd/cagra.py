@@ -46,8 +46,17 @@ EXPORTS = [
     "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
-    "cagra_ppr_iter",
+    "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
+    "cagra_multi_pagerank_step",
 ]
+
+
+class CMulti(ctypes.Structure):
+    _fields_ = [("ngraphs", _c_i32), ("max_k", _c_i32), ("max_B", _c_i32),
+                ("total_V", _c_i64), ("total_Q", _c_i64), ("total_tiles", _c_i64), ("total_blocks", _c_i64),
+                ("desc_bytes", _c_size), ("desc", _c_vp), ("rank", _c_vp * 2), ("contrib", _c_vp * 2),
+                ("scalars", _c_vp * 2), ("partial", _c_vp), ("blk", _c_vp),
+                ("grid_gather", _c_i32), ("grid_merge", _c_i32)]
 
 
 class CagraError(RuntimeError):
@@ -83,6 +92,10 @@ def lib():
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_ppr_workspace_bytes": ([SP], _c_size),
+            "cagra_multi_query": ([_c_i32, GP, SP, ctypes.POINTER(CMulti)], ctypes.c_int),
+            "cagra_multi_setup": ([ctypes.POINTER(CMulti), GP, SP, st], ctypes.c_int),
+            "cagra_multi_pagerank_start": ([ctypes.POINTER(CMulti), st], ctypes.c_int),
+            "cagra_multi_pagerank_step": ([ctypes.POINTER(CMulti), _c_i32, _c_dbl, st], ctypes.c_int),
             "cagra_ppr_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_ppr_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                 _c_vp, _c_size, st], ctypes.c_int),
@@ -407,3 +420,80 @@ def ppr(dg: DeviceGraph, seg: Segments, seeds, iters: int = 20, damping: float =
     for _ in range(iters):
         st.step(damping)
     return st.ranks().clone(), st
+
+
+# --------------------------------------------------------------------------- many graphs at once
+
+class MultiPageRank:
+    """PageRank on many independent graphs with persistent kernels over a global
+    tile / merge-block list; `run` captures the whole run into one HIP graph."""
+
+    def __init__(self, dgs, segs):
+        import torch
+        dev = _dev()
+        n = len(dgs)
+        assert n == len(segs) and n >= 1
+        self.dgs, self.segs = dgs, segs
+        self.garr = (CGraph * n)(*[d.c for d in dgs])
+        self.sarr = (CSegments * n)(*[s.c for s in segs])
+        m = CMulti()
+        _check(lib().cagra_multi_query(n, self.garr, self.sarr, ctypes.byref(m)), "cagra_multi_query")
+        TV, TQ, TB = m.total_V, m.total_Q, m.total_blocks
+        self.desc = torch.empty(m.desc_bytes, dtype=torch.uint8, device=dev)
+        self.rank = [torch.empty(TV, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.contrib = [torch.empty(TV, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.scalars = [torch.zeros(4 * n, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.partial = torch.empty(max(TQ, 1), dtype=torch.float32, device=dev)
+        self.blk = torch.empty(4 * max(TB, 1), dtype=torch.float64, device=dev)
+        m.desc = self.desc.data_ptr()
+        for p in range(2):
+            m.rank[p] = self.rank[p].data_ptr()
+            m.contrib[p] = self.contrib[p].data_ptr()
+            m.scalars[p] = self.scalars[p].data_ptr()
+        m.partial = self.partial.data_ptr()
+        m.blk = self.blk.data_ptr()
+        _check(lib().cagra_multi_setup(ctypes.byref(m), self.garr, self.sarr, _stream()), "cagra_multi_setup")
+        self.m = m
+        self.offsets = np.concatenate([[0], np.cumsum([d.V for d in dgs])]).astype(np.int64)
+        self.cur = 0
+        self.graph = None
+
+    def start(self, stream=None):
+        _check(lib().cagra_multi_pagerank_start(ctypes.byref(self.m), _stream(stream)), "cagra_multi_pagerank_start")
+        self.cur = 0
+
+    def step(self, damping: float = 0.85, stream=None):
+        _check(lib().cagra_multi_pagerank_step(ctypes.byref(self.m), self.cur, damping, _stream(stream)),
+               "cagra_multi_pagerank_step")
+        self.cur = 1 - self.cur
+
+    def run_eager(self, iters: int = 20, damping: float = 0.85):
+        self.start()
+        for _ in range(iters):
+            self.step(damping)
+
+    def capture(self, iters: int = 20, damping: float = 0.85):
+        """Records start + `iters` iterations of every graph into one HIP graph."""
+        import torch
+        self.run_eager(1, damping)  # first launches set kernel attributes outside the capture
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.run_eager(iters, damping)
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        self.graph_final = self.cur
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        self.cur = self.graph_final
+
+    def rank_of(self, i: int):
+        return self.rank[self.cur][self.offsets[i]:self.offsets[i + 1]]
+
+    def scalars_of(self, i: int):
+        return self.scalars[self.cur][4 * i:4 * i + 4]

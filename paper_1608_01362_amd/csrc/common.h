@@ -59,6 +59,25 @@ static inline cagra_status allow_dynamic_lds(const void *fn) {
     return CAGRA_OK;
 }
 
+// Per-graph descriptor of the persistent multi-graph kernels (device memory).
+struct MultiDesc {
+    const int32_t *edge_src;
+    const int32_t *tile_edge;
+    const int32_t *tile_seg;
+    const int32_t *tile_span_row;
+    const uint16_t *row_dst_lo;
+    const int32_t *block_ptr;
+    const int32_t *out_degree;
+    float *rank[2];
+    float *contrib[2];
+    double *scalars[2];
+    float *partial;
+    int64_t Q;
+    int64_t tile_base;   // first global tile of this graph
+    int64_t block_base;  // first global merge block of this graph
+    int32_t V, N, k, B, nb, ntiles;
+};
+
 // ---------------------------------------------------------------- device helpers
 
 // Workgroups are dispatched round-robin over the 8 XCDs (id mod 8). Remap so

@@ -233,16 +233,17 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kEPT / 4], int64_t
     S.nflags += chunk_nf;
 }
 
+// One gather tile (all 16 waves of the workgroup). `smem` is the workgroup's
+// dynamic LDS: kStageBytes of per-wave row staging, then the segment values.
 template <class Op, typename VT, bool STAGED>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(
-    const int32_t *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
-    const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
-    int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial) {
+__device__ __forceinline__ void gather_tile(const int32_t *__restrict__ edge_src, int64_t Q,
+                                            const int32_t *__restrict__ tile_edge,
+                                            const int32_t *__restrict__ tile_seg,
+                                            const int32_t *__restrict__ span_row, const VT *__restrict__ values,
+                                            int32_t V, int32_t N, int t, typename Op::T *__restrict__ partial,
+                                            unsigned char *smem) {
     using T = typename Op::T;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     VT *seg_vals = reinterpret_cast<VT *>(smem + kStageBytes);
-
-    const int t = xcd_remap(blockIdx.x, ntiles);
     const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
     if (e0 >= e1) return;  // empty tile (uniform over the workgroup)
     const int32_t s = tile_seg[t];
@@ -319,6 +320,45 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
             partial[fix[ww].row] = tot;
         }
     }
+}
+
+template <class Op, typename VT, bool STAGED>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(
+    const int32_t *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
+    const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
+    int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    (void)E;
+    gather_tile<Op, VT, STAGED>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
+                                xcd_remap(blockIdx.x, ntiles), partial, smem);
+}
+
+// Persistent form over many graphs: workgroups stride over a global tile list.
+__global__ __launch_bounds__(kGatherThreads) void k_multi_gather(const MultiDesc *__restrict__ desc,
+                                                                 const int32_t *__restrict__ tile_graph,
+                                                                 int64_t total_tiles, int parity) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    for (int64_t gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
+        __syncthreads();  // LDS reuse across tiles
+        const int gi = tile_graph[gt];
+        const MultiDesc &d = desc[gi];
+        gather_tile<OpSum, float, true>(d.edge_src, d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
+                                        d.contrib[parity], d.V, d.N, (int)(gt - d.tile_base), d.partial, smem);
+    }
+}
+
+cagra_status launch_multi_gather(const MultiDesc *desc, const int32_t *tile_graph, int64_t total_tiles, int parity,
+                                 int grid, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_multi_gather)) return a_;
+        attr_set = true;
+    }
+    if (total_tiles == 0) return CAGRA_OK;
+    k_multi_gather<<<grid, kGatherThreads, kStageBytes + CAGRA_STAGE_BYTES, st>>>(desc, tile_graph, total_tiles,
+                                                                                   parity);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
 }
 
 template <class Op, typename VT, bool STAGED>

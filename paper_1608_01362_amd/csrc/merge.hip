@@ -214,20 +214,21 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
     }
 }
 
+// Merge block b of one graph plus the PageRank vertex update; writes the
+// block's FP64 partial sums to blk_out[0..3].
 template <bool BF16OUT>
-__global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
+__device__ __forceinline__ void merge_pr_block(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
-    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb,
+    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b,
     const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
-    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
+    unsigned char *smem) {
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
     int32_t *pre = lo_s + k;
     __shared__ int32_t tmp[16];
     __shared__ double red[16];
 
-    const int b = xcd_remap(blockIdx.x, nb);
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
@@ -256,11 +257,109 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     res = block_sum_f64<kMergeThreads>(res, red);
     mass = block_sum_f64<kMergeThreads>(mass, red);
     if (threadIdx.x == 0) {
-        blk[(int64_t)b * 4 + 0] = dang;
-        blk[(int64_t)b * 4 + 1] = res;
-        blk[(int64_t)b * 4 + 2] = mass;
-        blk[(int64_t)b * 4 + 3] = 0.0;
+        blk_out[0] = dang;
+        blk_out[1] = res;
+        blk_out[2] = mass;
+        blk_out[3] = 0.0;
     }
+}
+
+template <bool BF16OUT>
+__global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
+    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
+    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb,
+    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
+    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int b = xcd_remap(blockIdx.x, nb);
+    merge_pr_block<BF16OUT>(row_dst_lo, block_ptr, partial, V, k, B, b, rank_in, outdeg, scalars_in, damping,
+                            rank_out, contrib_out, blk + (int64_t)b * 4, smem);
+}
+
+// Persistent form over many graphs: workgroups stride over a global block list.
+__global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *__restrict__ desc,
+                                                               const int32_t *__restrict__ block_graph,
+                                                               int64_t total_blocks, int parity, double damping,
+                                                               double *__restrict__ blk) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    for (int64_t gb = blockIdx.x; gb < total_blocks; gb += gridDim.x) {
+        __syncthreads();  // LDS reuse across blocks
+        const int gi = block_graph[gb];
+        const MultiDesc &d = desc[gi];
+        merge_pr_block<false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base),
+                              d.rank[parity], d.out_degree, d.scalars[parity], damping, d.rank[1 - parity],
+                              d.contrib[1 - parity], blk + gb * 4, smem);
+    }
+}
+
+// Uniform start vectors of many graphs (persistent over the block list).
+__global__ __launch_bounds__(256) void k_multi_start(const MultiDesc *__restrict__ desc,
+                                                     const int32_t *__restrict__ block_graph, int64_t total_blocks,
+                                                     double *__restrict__ blk) {
+    __shared__ double red[4];
+    for (int64_t gb = blockIdx.x; gb < total_blocks; gb += gridDim.x) {
+        const int gi = block_graph[gb];
+        const MultiDesc &d = desc[gi];
+        const int64_t lo = (gb - d.block_base) * (int64_t)d.B;
+        const int64_t hi = lo + d.B < d.V ? lo + d.B : d.V;
+        const float r = 1.0f / (float)d.V;
+        double dang = 0.0, mass = 0.0;
+        for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
+            d.rank[0][v] = r;
+            const int32_t od = d.out_degree[v];
+            d.contrib[0][v] = od > 0 ? r / (float)od : 0.0f;
+            if (od == 0) dang += (double)r;
+            mass += (double)r;
+        }
+        dang = block_sum_f64<256>(dang, red);
+        mass = block_sum_f64<256>(mass, red);
+        if (threadIdx.x == 0) {
+            blk[gb * 4 + 0] = dang;
+            blk[gb * 4 + 1] = 0.0;
+            blk[gb * 4 + 2] = mass;
+            blk[gb * 4 + 3] = 0.0;
+        }
+    }
+}
+
+// Per graph: fixed-order sum of its blocks' partials into scalars[parity].
+__global__ __launch_bounds__(256) void k_multi_reduce(const MultiDesc *__restrict__ desc,
+                                                      const double *__restrict__ blk, int parity) {
+    __shared__ double red[4];
+    const MultiDesc &d = desc[blockIdx.x];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t j = threadIdx.x; j < d.nb; j += 256)
+        for (int c = 0; c < 4; ++c) a[c] += blk[(d.block_base + j) * 4 + c];
+    for (int c = 0; c < 4; ++c) {
+        double t = block_sum_f64<256>(a[c], red);
+        if (threadIdx.x == 0) d.scalars[parity][c] = t;
+    }
+}
+
+cagra_status launch_multi_start(const MultiDesc *desc, const int32_t *block_graph, int64_t total_blocks,
+                                int32_t ngraphs, double *blk, int grid, hipStream_t st) {
+    if (total_blocks == 0) return CAGRA_OK;
+    k_multi_start<<<grid, 256, 0, st>>>(desc, block_graph, total_blocks, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 0);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+cagra_status launch_multi_merge(const MultiDesc *desc, const int32_t *block_graph, int64_t total_blocks,
+                                int32_t ngraphs, int parity, double damping, double *blk, size_t lds, int grid,
+                                hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_multi_merge)) return a_;
+        attr_set = true;
+    }
+    if (total_blocks == 0) return CAGRA_OK;
+    k_multi_merge<<<grid, kMergeThreads, lds, st>>>(desc, block_graph, total_blocks, parity, damping, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 1 - parity);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
 }
 
 __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
