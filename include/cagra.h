@@ -298,6 +298,57 @@ cagra_status cagra_multi_pagerank_start(const cagra_multi *m, hipStream_t stream
    graph: reads pools [parity], writes pools [1 - parity]. */
 cagra_status cagra_multi_pagerank_step(const cagra_multi *m, int32_t parity, double damping, hipStream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned warm start of the PageRank power iteration                        */
+/* ------------------------------------------------------------------------ */
+
+/* Parameters of the 3 -> 64 -> 64 -> 1 GELU network: W1[64][3], b1[64],
+   W2[64][64] (row j = output j), b2[64], w3[64], b3. */
+#define CAGRA_MLP_PARAMS 4481
+
+size_t cagra_features_workspace_bytes(const cagra_segments *seg);
+/*
+ * Per-vertex features (row-major [V][3] float): log(1 + in-degree),
+ * log(1 + out-degree), and the mean over in-neighbours u of log(1 + out-degree(u))
+ * (0 without in-neighbours). The last one is a segmented pull: the segment
+ * gather and the paper-order merge of log(1 + out-degree) over `seg`.
+ */
+cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *seg, float *features,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * y[r] = network(standardized features[r]) for r < n. weights: BF16
+ * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. FP32 arithmetic,
+ * exact GELU (erf).
+ */
+cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t *weights, const float *norm,
+                               float *y, hipStream_t stream);
+
+size_t cagra_mlp_grad_workspace_bytes(void);
+/*
+ * Mean squared error over n rows and its gradient with respect to all
+ * parameters (float[CAGRA_MLP_PARAMS]); *loss (device double). Deterministic:
+ * fixed row-to-workgroup assignment and fixed-order reductions.
+ */
+cagra_status cagra_mlp_grad(const float *features, const float *targets, int64_t n, const uint16_t *weights,
+                            const float *norm, float *grad, double *loss, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/* One Adam step (bias-corrected; step >= 1) on FP32 master weights, which are
+   then rounded to nearest even into the BF16 copy. */
+cagra_status cagra_adam_step(float *master, uint16_t *weights, float *m, float *v, const float *grad, int32_t step,
+                             float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
+size_t cagra_warm_start_workspace_bytes(int32_t V);
+/*
+ * Start vector r0 = exp(y) / sum(exp(y)) over V vertices (FP64 sums, fixed
+ * order). scalars_out (device double[4]): max(y), number of non-finite y,
+ * sum of exp(y - max), 0. The caller falls back to the uniform start when the
+ * count is non-zero or the sum is not a positive finite number.
+ */
+cagra_status cagra_warm_start_vector(const float *y, int32_t V, float *rank0, double *scalars_out,
+                                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

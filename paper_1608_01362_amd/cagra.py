@@ -47,7 +47,9 @@ EXPORTS = [
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
-    "cagra_multi_pagerank_step",
+    "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
+    "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
+    "cagra_warm_start_vector",
 ]
 
 
@@ -92,6 +94,15 @@ def lib():
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_ppr_workspace_bytes": ([SP], _c_size),
+            "cagra_features_workspace_bytes": ([SP], _c_size),
+            "cagra_degree_features": ([GP, SP, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_mlp_forward": ([_c_vp, _c_i64, _c_vp, _c_vp, _c_vp, st], ctypes.c_int),
+            "cagra_mlp_grad_workspace_bytes": ([], _c_size),
+            "cagra_mlp_grad": ([_c_vp, _c_vp, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_adam_step": ([_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, st], ctypes.c_int),
+            "cagra_warm_start_workspace_bytes": ([_c_i32], _c_size),
+            "cagra_warm_start_vector": ([_c_vp, _c_i32, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_multi_query": ([_c_i32, GP, SP, ctypes.POINTER(CMulti)], ctypes.c_int),
             "cagra_multi_setup": ([ctypes.POINTER(CMulti), GP, SP, st], ctypes.c_int),
             "cagra_multi_pagerank_start": ([ctypes.POINTER(CMulti), st], ctypes.c_int),

@@ -47,6 +47,19 @@ cagra_status launch_ppr_iter(const cagra_graph *g, const cagra_segments *seg, do
                              const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
                              double *scalars_out, double *blk, hipStream_t st);
 
+size_t features_ws_bytes(const cagra_segments *seg);
+cagra_status launch_features(const cagra_graph *g, const cagra_segments *seg, float *feats, void *ws,
+                             hipStream_t st);
+cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *wb, const float *norm, float *y,
+                                hipStream_t st);
+size_t mlp_grad_ws_bytes();
+cagra_status launch_mlp_grad(const float *feats, const float *target, int64_t n, const uint16_t *wb,
+                             const float *norm, float *grad, double *loss, void *ws, hipStream_t st);
+cagra_status launch_adam(float *master, uint16_t *wb, float *m, float *v, const float *g, int32_t step, float lr,
+                         float b1, float b2, float eps, hipStream_t st);
+size_t softmax_ws_bytes(int32_t V);
+cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st);
+
 static constexpr int32_t kMaxSegments = 32768;
 static constexpr int32_t kMaxPprBlock = 512;
 static constexpr int32_t kMaxMergeBlock = 16384;
@@ -237,6 +250,65 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
                     workspace_bytes);
     if ((s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, labels_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, (int32_t *)workspace, stream);
+}
+
+size_t cagra_features_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->V < 1) return 0;
+    return features_ws_bytes(seg);
+}
+
+cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *seg, float *features,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (!features) return fail(CAGRA_E_INVALID, "features is NULL");
+    if (merge_ordered_lds_bytes(seg->B, CAGRA_SUM_F32) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "merge block B=%d too large", seg->B);
+    if (!workspace || workspace_bytes < features_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", features_ws_bytes(seg), workspace_bytes);
+    return launch_features(g, seg, features, workspace, stream);
+}
+
+cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t *weights, const float *norm,
+                               float *y, hipStream_t stream) {
+    if (n < 0) return fail(CAGRA_E_INVALID, "n must be >= 0");
+    if (n > 0 && (!features || !weights || !norm || !y)) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    return launch_mlp_forward(features, n, weights, norm, y, stream);
+}
+
+size_t cagra_mlp_grad_workspace_bytes(void) { return mlp_grad_ws_bytes(); }
+
+cagra_status cagra_mlp_grad(const float *features, const float *targets, int64_t n, const uint16_t *weights,
+                            const float *norm, float *grad, double *loss, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    if (n < 1) return fail(CAGRA_E_INVALID, "n must be >= 1");
+    if (!features || !targets || !weights || !norm || !grad || !loss)
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (!workspace || workspace_bytes < mlp_grad_ws_bytes())
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", mlp_grad_ws_bytes(), workspace_bytes);
+    return launch_mlp_grad(features, targets, n, weights, norm, grad, loss, workspace, stream);
+}
+
+cagra_status cagra_adam_step(float *master, uint16_t *weights, float *m, float *v, const float *grad, int32_t step,
+                             float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+    if (!master || !weights || !m || !v || !grad) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (step < 1) return fail(CAGRA_E_INVALID, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+        return fail(CAGRA_E_INVALID, "bad Adam hyper-parameters");
+    return launch_adam(master, weights, m, v, grad, step, lr, beta1, beta2, eps, stream);
+}
+
+size_t cagra_warm_start_workspace_bytes(int32_t V) { return V < 1 ? 0 : softmax_ws_bytes(V); }
+
+cagra_status cagra_warm_start_vector(const float *y, int32_t V, float *rank0, double *scalars_out,
+                                     void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (V < 1) return fail(CAGRA_E_INVALID, "V must be >= 1");
+    if (!y || !rank0 || !scalars_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (!workspace || workspace_bytes < softmax_ws_bytes(V))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", softmax_ws_bytes(V), workspace_bytes);
+    return launch_softmax(y, V, rank0, scalars_out, workspace, stream);
 }
 
 size_t cagra_ppr_workspace_bytes(const cagra_segments *seg) {

@@ -1,0 +1,390 @@
+// Learned warm start for the PageRank power iteration: degree features, a
+// 3 -> 64 -> 64 -> 1 GELU network with BF16 weights and FP32 accumulation
+// (forward, backward and Adam, all on the GPU), and the start vector
+// r0 = softmax(y) (the network predicts log(V * r)). The plain iteration from
+// this vector remains the judge of convergence.
+//
+// Parameter vector (4481 values): W1[64][3], b1[64], W2[64][64] (row j =
+// output j), b2[64], w3[64], b3.
+#include <math.h>
+
+#include "common.h"
+
+namespace cagra {
+
+cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                           void *partial, hipStream_t st);
+cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st);
+
+constexpr int kH = 64;
+constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4480;
+constexpr int kNParam = CAGRA_MLP_PARAMS;
+static_assert(kNParam == 4481, "parameter layout");
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------ features
+
+__global__ void k_log1p_outdeg(const int32_t *__restrict__ outdeg, int32_t V, float *__restrict__ vals) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) vals[v] = log1pf((float)outdeg[v]);
+}
+
+__global__ void k_features(const int32_t *__restrict__ off, const int32_t *__restrict__ outdeg,
+                           const float *__restrict__ sumlog, int32_t V, float *__restrict__ feats) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int32_t indeg = off[v + 1] - off[v];
+    feats[v * 3 + 0] = log1pf((float)indeg);
+    feats[v * 3 + 1] = log1pf((float)outdeg[v]);
+    feats[v * 3 + 2] = indeg > 0 ? sumlog[v] / (float)indeg : 0.0f;
+}
+
+size_t features_ws_bytes(const cagra_segments *seg) {
+    return align_up((size_t)seg->V * 4, 256) * 2 + align_up((size_t)(seg->Q > 0 ? seg->Q : 1) * 4, 256) + 256;
+}
+
+cagra_status launch_features(const cagra_graph *g, const cagra_segments *seg, float *feats, void *ws,
+                             hipStream_t st) {
+    char *p = (char *)ws;
+    float *vals = (float *)p;
+    float *sumlog = (float *)(p + align_up((size_t)seg->V * 4, 256));
+    float *partial = (float *)(p + 2 * align_up((size_t)seg->V * 4, 256));
+    const unsigned grid = (unsigned)ceil_div(g->V, 256);
+    k_log1p_outdeg<<<grid, 256, 0, st>>>(g->out_degree, g->V, vals);
+    CAGRA_LAUNCH_CHECK();
+    cagra_status s;
+    if ((s = launch_gather(seg, CAGRA_SUM_F32, CAGRA_F32, vals, partial, st)) != CAGRA_OK) return s;
+    if ((s = launch_merge(seg, CAGRA_SUM_F32, partial, sumlog, st)) != CAGRA_OK) return s;
+    k_features<<<grid, 256, 0, st>>>(g->in_offsets, g->out_degree, sumlog, g->V, feats);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// ------------------------------------------------------------------ network
+
+// BF16 weights to FP32 in LDS, shared by all rows of the workgroup.
+__device__ __forceinline__ void load_weights(const uint16_t *__restrict__ wb, float *w) {
+    for (int i = threadIdx.x; i < kNParam; i += blockDim.x) w[i] = bf16_to_f32(wb[i]);
+}
+
+constexpr int kFwdThreads = 256;
+
+__global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__restrict__ feats, int64_t n,
+                                                             const uint16_t *__restrict__ wb,
+                                                             const float *__restrict__ norm,
+                                                             float *__restrict__ y) {
+    __shared__ float w[kNParam + 3];
+    load_weights(wb, w);
+    __syncthreads();
+    const float m0 = norm[0], m1 = norm[1], m2 = norm[2], s0 = norm[3], s1 = norm[4], s2 = norm[5];
+    for (int64_t r = (int64_t)blockIdx.x * kFwdThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kFwdThreads) {
+        const float x0 = (feats[r * 3 + 0] - m0) * s0, x1 = (feats[r * 3 + 1] - m1) * s1,
+                    x2 = (feats[r * 3 + 2] - m2) * s2;
+        float h1[kH];
+#pragma unroll
+        for (int i = 0; i < kH; ++i)
+            h1[i] = gelu(fmaf(w[kOffW1 + 3 * i + 2], x2,
+                              fmaf(w[kOffW1 + 3 * i + 1], x1, fmaf(w[kOffW1 + 3 * i], x0, w[kOffB1 + i]))));
+        float out = w[kOffB3];
+#pragma unroll 1
+        for (int j = 0; j < kH; ++j) {
+            float z = w[kOffB2 + j];
+#pragma unroll
+            for (int i = 0; i < kH; ++i) z = fmaf(w[kOffW2 + j * kH + i], h1[i], z);
+            out = fmaf(w[kOffW3 + j], gelu(z), out);
+        }
+        y[r] = out;
+    }
+}
+
+// Backward: persistent workgroups of 128 rows per pass; each thread owns a
+// fixed set of parameters and accumulates their gradient over the rows the
+// workgroup processes; workgroup partials are summed in a fixed order.
+constexpr int kBwdThreads = 128;
+constexpr int kBwdRows = 128;
+constexpr int kPad = kH + 1;  // row pitch in LDS (avoids bank conflicts on row-private reads)
+constexpr int kBwdGrid = 256;
+
+__global__ __launch_bounds__(kBwdThreads) void k_mlp_backward(const float *__restrict__ feats,
+                                                              const float *__restrict__ target, int64_t n,
+                                                              const uint16_t *__restrict__ wb,
+                                                              const float *__restrict__ norm,
+                                                              float *__restrict__ part_grad,
+                                                              double *__restrict__ part_loss) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float *w = reinterpret_cast<float *>(smem);              // kNParam (+3 pad)
+    float *xs = w + ((kNParam + 3 + 3) & ~3);                 // [rows][4]
+    float *dys = xs + kBwdRows * 4;                           // [rows]
+    float *h1s = dys + kBwdRows;                              // [rows][kPad]
+    float *z2s = h1s + kBwdRows * kPad;                       // [rows][kPad]
+    float *dz2s = z2s + kBwdRows * kPad;                      // [rows][kPad]
+    float *dz1s = dz2s + kBwdRows * kPad;                     // [rows][kPad]
+    load_weights(wb, w);
+    __syncthreads();
+    const int t = threadIdx.x;
+    const float m0 = norm[0], m1 = norm[1], m2 = norm[2], s0 = norm[3], s1 = norm[4], s2 = norm[5];
+    const float inv_n2 = 2.0f / (float)n;
+    // owned parameters: W2[j][i0..i0+31], and for t < 64: w3[t], b2[t], W1[t][0..2], b1[t]; t == 0: b3
+    const int jw = t >> 1, i0 = (t & 1) * 32;
+    float gW2[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) gW2[q] = 0.0f;
+    float gw3 = 0.0f, gb2 = 0.0f, gW1a = 0.0f, gW1b = 0.0f, gW1c = 0.0f, gb1 = 0.0f, gb3 = 0.0f;
+    double loss = 0.0;
+
+    for (int64_t base = (int64_t)blockIdx.x * kBwdRows; base < n; base += (int64_t)gridDim.x * kBwdRows) {
+        const int64_t r = base + t;
+        const bool live = r < n;
+        // forward for this thread's row
+        const float x0 = live ? (feats[r * 3 + 0] - m0) * s0 : 0.0f;
+        const float x1 = live ? (feats[r * 3 + 1] - m1) * s1 : 0.0f;
+        const float x2 = live ? (feats[r * 3 + 2] - m2) * s2 : 0.0f;
+        float h1[kH];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) {
+            const float z1 = fmaf(w[kOffW1 + 3 * i + 2], x2,
+                                  fmaf(w[kOffW1 + 3 * i + 1], x1, fmaf(w[kOffW1 + 3 * i], x0, w[kOffB1 + i])));
+            h1[i] = gelu(z1);
+            h1s[t * kPad + i] = h1[i];
+        }
+        float out = w[kOffB3];
+        for (int j = 0; j < kH; ++j) {
+            float z = w[kOffB2 + j];
+#pragma unroll
+            for (int i = 0; i < kH; ++i) z = fmaf(w[kOffW2 + j * kH + i], h1[i], z);
+            z2s[t * kPad + j] = z;
+            out = fmaf(w[kOffW3 + j], gelu(z), out);
+        }
+        const float res = live ? out - target[r] : 0.0f;
+        loss += (double)res * (double)res;
+        const float dy = res * inv_n2;
+        dys[t] = dy;
+        xs[t * 4 + 0] = x0;
+        xs[t * 4 + 1] = x1;
+        xs[t * 4 + 2] = x2;
+        // dz2 = dy * w3 * gelu'(z2); dh1 = W2^T dz2; dz1 = dh1 * gelu'(z1)
+        float dh1[kH];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) dh1[i] = 0.0f;
+        for (int j = 0; j < kH; ++j) {
+            const float dz2 = dy * w[kOffW3 + j] * gelu_grad(z2s[t * kPad + j]);
+            dz2s[t * kPad + j] = dz2;
+#pragma unroll
+            for (int i = 0; i < kH; ++i) dh1[i] = fmaf(w[kOffW2 + j * kH + i], dz2, dh1[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kH; ++i) {
+            const float z1 = fmaf(w[kOffW1 + 3 * i + 2], x2,
+                                  fmaf(w[kOffW1 + 3 * i + 1], x1, fmaf(w[kOffW1 + 3 * i], x0, w[kOffB1 + i])));
+            dz1s[t * kPad + i] = dh1[i] * gelu_grad(z1);
+        }
+        __syncthreads();
+        // parameter-owner accumulation over the pass's rows, in row order
+        for (int q = 0; q < kBwdRows; ++q) {
+            const float dz2 = dz2s[q * kPad + jw];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) gW2[c] = fmaf(dz2, h1s[q * kPad + i0 + c], gW2[c]);
+        }
+        if (t < kH) {
+            for (int q = 0; q < kBwdRows; ++q) {
+                const float dyq = dys[q];
+                gw3 = fmaf(dyq, gelu(z2s[q * kPad + t]), gw3);
+                gb2 += dz2s[q * kPad + t];
+                const float dz1 = dz1s[q * kPad + t];
+                gW1a = fmaf(dz1, xs[q * 4 + 0], gW1a);
+                gW1b = fmaf(dz1, xs[q * 4 + 1], gW1b);
+                gW1c = fmaf(dz1, xs[q * 4 + 2], gW1c);
+                gb1 += dz1;
+                if (t == 0) gb3 += dyq;
+            }
+        }
+        __syncthreads();
+    }
+    float *pg = part_grad + (int64_t)blockIdx.x * kNParam;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) pg[kOffW2 + jw * kH + i0 + c] = gW2[c];
+    if (t < kH) {
+        pg[kOffW3 + t] = gw3;
+        pg[kOffB2 + t] = gb2;
+        pg[kOffW1 + 3 * t + 0] = gW1a;
+        pg[kOffW1 + 3 * t + 1] = gW1b;
+        pg[kOffW1 + 3 * t + 2] = gW1c;
+        pg[kOffB1 + t] = gb1;
+    }
+    if (t == 0) pg[kOffB3] = gb3;
+    // loss: fixed-order sum over the workgroup's threads
+    __shared__ double lred[kBwdThreads];
+    lred[t] = loss;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int q = 0; q < kBwdThreads; ++q) s += lred[q];
+        part_loss[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_grad_reduce(const float *__restrict__ part_grad, const double *__restrict__ part_loss, int grid,
+                              int64_t n, float *__restrict__ grad, double *__restrict__ loss_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNParam) {
+        double s = 0.0;
+        for (int b = 0; b < grid; ++b) s += (double)part_grad[(int64_t)b * kNParam + i];
+        grad[i] = (float)s;
+    }
+    if (i == 0) {
+        double s = 0.0;
+        for (int b = 0; b < grid; ++b) s += part_loss[b];
+        loss_out[0] = s / (double)n;
+    }
+}
+
+size_t mlp_grad_ws_bytes() { return align_up((size_t)kBwdGrid * kNParam * 4, 256) + (size_t)kBwdGrid * 8 + 256; }
+
+static size_t bwd_lds_bytes() {
+    return (size_t)(((kNParam + 3 + 3) & ~3) + kBwdRows * 4 + kBwdRows + 4 * kBwdRows * kPad) * sizeof(float);
+}
+
+cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *wb, const float *norm, float *y,
+                                hipStream_t st) {
+    if (n == 0) return CAGRA_OK;
+    int64_t g = ceil_div(n, kFwdThreads);
+    if (g > 4096) g = 4096;
+    k_mlp_forward<<<(unsigned)g, kFwdThreads, 0, st>>>(feats, n, wb, norm, y);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+cagra_status launch_mlp_grad(const float *feats, const float *target, int64_t n, const uint16_t *wb,
+                             const float *norm, float *grad, double *loss, void *ws, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_mlp_backward)) return a_;
+        attr_set = true;
+    }
+    float *pg = (float *)ws;
+    double *pl = (double *)((char *)ws + align_up((size_t)kBwdGrid * kNParam * 4, 256));
+    k_mlp_backward<<<kBwdGrid, kBwdThreads, bwd_lds_bytes(), st>>>(feats, target, n, wb, norm, pg, pl);
+    CAGRA_LAUNCH_CHECK();
+    k_grad_reduce<<<(unsigned)ceil_div(kNParam, 256), 256, 0, st>>>(pg, pl, kBwdGrid, n, grad, loss);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights, then round to BF16.
+__global__ void k_adam(float *__restrict__ master, uint16_t *__restrict__ wb, float *__restrict__ m,
+                       float *__restrict__ v, const float *__restrict__ g, int32_t step, float lr, float b1,
+                       float b2, float eps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParam) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(b1, (float)step));
+    const float vh = vi / (1.0f - powf(b2, (float)step));
+    const float p = master[i] - lr * mh / (sqrtf(vh) + eps);
+    master[i] = p;
+    wb[i] = f32_to_bf16(p);
+}
+
+cagra_status launch_adam(float *master, uint16_t *wb, float *m, float *v, const float *g, int32_t step, float lr,
+                         float b1, float b2, float eps, hipStream_t st) {
+    k_adam<<<(unsigned)ceil_div(kNParam, 256), 256, 0, st>>>(master, wb, m, v, g, step, lr, b1, b2, eps);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// ------------------------------------------------------------------ start vector
+
+constexpr int kSoftSpan = 65536;
+
+__global__ __launch_bounds__(256) void k_soft_max(const float *__restrict__ y, int32_t V, double *__restrict__ blk) {
+    __shared__ double red[4];
+    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan, hi = lo + kSoftSpan < V ? lo + kSoftSpan : V;
+    double mx = -INFINITY, bad = 0.0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
+        const float x = y[v];
+        if (!isfinite(x)) bad += 1.0;
+        else mx = fmax(mx, (double)x);
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_down(mx, d, 64));
+        bad += __shfl_down(bad, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    double m2 = red[0];
+    for (int i = 1; i < 4; ++i) m2 = fmax(m2, red[i]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        blk[blockIdx.x * 2 + 0] = m2;
+        blk[blockIdx.x * 2 + 1] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// scal[0] = max, scal[1] = count of non-finite outputs (fixed order)
+__global__ void k_soft_max_final(const double *__restrict__ blk, int32_t nblk, double *__restrict__ scal) {
+    if (threadIdx.x == 0) {
+        double mx = -INFINITY, bad = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            mx = fmax(mx, blk[b * 2]);
+            bad += blk[b * 2 + 1];
+        }
+        scal[0] = mx;
+        scal[1] = bad;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_soft_sum(const float *__restrict__ y, int32_t V,
+                                                  const double *__restrict__ scal, double *__restrict__ blk) {
+    __shared__ double red[4];
+    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan, hi = lo + kSoftSpan < V ? lo + kSoftSpan : V;
+    const double mx = scal[0];
+    double s = 0.0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) s += exp((double)y[v] - mx);
+    s = block_sum_f64<256>(s, red);
+    if (threadIdx.x == 0) blk[blockIdx.x] = s;
+}
+
+// scal[2] = sum of exp(y - max) over all vertices
+__global__ void k_soft_sum_final(const double *__restrict__ blk, int32_t nblk, double *__restrict__ scal) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += blk[b];
+        scal[2] = s;
+        scal[3] = 0.0;
+    }
+}
+
+__global__ void k_soft_write(const float *__restrict__ y, int32_t V, const double *__restrict__ scal,
+                             float *__restrict__ r0) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) r0[v] = (float)(exp((double)y[v] - scal[0]) / scal[2]);
+}
+
+size_t softmax_ws_bytes(int32_t V) { return (size_t)ceil_div(V, kSoftSpan) * 2 * sizeof(double) + 256; }
+
+cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st) {
+    const int32_t nblk = (int32_t)ceil_div(V, kSoftSpan);
+    double *blk = (double *)ws;
+    k_soft_max<<<nblk, 256, 0, st>>>(y, V, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_soft_max_final<<<1, 64, 0, st>>>(blk, nblk, scal);
+    CAGRA_LAUNCH_CHECK();
+    k_soft_sum<<<nblk, 256, 0, st>>>(y, V, scal, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_soft_sum_final<<<1, 64, 0, st>>>(blk, nblk, scal);
+    CAGRA_LAUNCH_CHECK();
+    k_soft_write<<<(unsigned)ceil_div(V, 256), 256, 0, st>>>(y, V, scal, r0);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+}  // namespace cagra
