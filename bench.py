@@ -96,6 +96,10 @@ def main():
     ap.add_argument("--contrib", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--workload", default="pagerank",
+                    choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart"],
+                    help="pagerank: the headline line (default); the others measure the secondary "
+                         "configurations and print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (to calibrate the HBM "
                          "byte counters of a profiler against a known size) and exit")
@@ -123,6 +127,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload != "pagerank":
+        import bench_workloads
+        print(json.dumps(bench_workloads.run(args.workload, args, log)), flush=True)
+        return
     log(f"generating R-MAT scale {args.scale} edge factor {args.edge_factor} seed {args.seed}")
     t0 = time.perf_counter()
     g = graphgen.rmat_graph(args.scale, args.edge_factor, args.seed)

@@ -1,0 +1,195 @@
+"""Secondary measurements for bench.py --workload (each prints one JSON line).
+
+labelprop   min-label propagation, R-MAT scale 22 / ef 16 / seed 2, symmetrized,
+            to the fixed point (GTEPS over the symmetric edge count)
+ppr         personalized PageRank with 64 seed vertices at once (restart 0.15),
+            R-MAT scale 22 / ef 16 / seed 4, 20 iterations; segment sizes from the
+            autotuner's candidates; compared with the plain single-vector iteration
+ppr         ...
+multigraph  256 independent R-MAT graphs (scale U{10..20}, ef U{8..32}, seed 4),
+            start + 20 iterations of all of them captured into one HIP graph,
+            compared with running the graphs one after another
+warmstart   MLP warm start trained on 200 R-MAT graphs (scale U{16..20}, ef 16,
+            seeds 1000+i) from PageRank vectors the method computes; held-out
+            R-MAT scale 24 / ef 24 / seed 5; iterations and time to L1 residual
+            < 1e-6 from the learned start (features and network included) vs
+            the uniform start
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def labelprop(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    g = graphgen.symmetrize(graphgen.rmat_graph(22, 16, 2))
+    log(f"labelprop graph V={g.V} E_sym={g.E}")
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 32768, 8192, 262144)
+    lab, it = cagra.labelprop(seg)  # warm-up and iteration count
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    lab, it = cagra.labelprop(seg)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    comps = int(torch.unique(lab).numel())
+    return {"metric": "GTEPS per label-propagation iteration at R-MAT-22 (symmetrized)",
+            "value": round(g.E * it / (ms * 1e-3) / 1e9, 3), "unit": "GTEPS", "iterations_to_fixed_point": it,
+            "ms_total": round(ms, 3), "ms_per_iteration": round(ms / it, 4), "components": comps,
+            "config": {"workload": "labelprop_rmat22_ef16_seed2_sym", "V": g.V, "E_sym": g.E, "N": 32768,
+                       "B": 8192, "k": seg.k, "Q": seg.Q}, "dtype": "i32", "data": "synthetic"}
+
+
+def ppr(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    g = graphgen.rmat_graph(22, 16, 4)
+    rng = np.random.default_rng(4)
+    ok = np.where((np.diff(g.in_offsets) > 0) | (g.out_degree > 0))[0]
+    seeds = rng.choice(ok, size=64, replace=False).astype(np.int32)
+    dg = cagra.DeviceGraph.from_host(g)
+    trials = []
+    for N in (1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22):  # L2- to Infinity-Cache-sized segments of 256-byte rows
+        for T in (16384, 65536):
+            seg = cagra.build_segments(dg, N, 512, T)
+            st = cagra.PPRState(dg, seg, seeds)
+            st.start()
+            ms = _time(st.step, 5)
+            trials.append((ms, N, T, seg.q))
+            log(f"ppr N={N} T={T} q={seg.q:.3f}: {ms:.3f} ms/iteration")
+            del st, seg
+            torch.cuda.empty_cache()
+    ms, N, T, q = min(trials)
+    seg = cagra.build_segments(dg, N, 512, T)
+    st = cagra.PPRState(dg, seg, seeds)
+    st.start()
+    ms = _time(st.step, 20)
+    # plain single-vector PageRank iteration on the same graph (LDS-staged, tuned)
+    seg1 = cagra.build_segments(dg, 32768, 8192, 262144)
+    st1 = cagra.PageRankState(dg, seg1)
+    st1.start()
+    ms1 = _time(st1.step, 20)
+    return {"metric": "edge-columns per second, 64-seed personalized PageRank at R-MAT-22",
+            "value": round(g.E * 64 / (ms * 1e-3) / 1e9, 3), "unit": "G edge-columns/s",
+            "ms_per_iteration": round(ms, 4), "plain_single_vector_ms_per_iteration": round(ms1, 4),
+            "plain_single_vector_GTEPS": round(g.E / (ms1 * 1e-3) / 1e9, 3),
+            "speedup_vs_64_plain_iterations": round(64 * ms1 / ms, 3),
+            "config": {"workload": "ppr64_rmat22_ef16_seed4", "V": g.V, "E": g.E, "N": N, "B": 512,
+                       "tile_edges": T, "q": round(q, 4), "columns": 64, "restart": 0.15},
+            "autotune_trials": [{"N": n, "tile_edges": t, "ms": round(m, 4)} for m, n, t, _ in trials],
+            "dtype": "f32", "data": "synthetic"}
+
+
+def multigraph(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    specs = graphgen.multigraph_specs(256, seed=4)
+    t0 = time.perf_counter()
+    gs = [graphgen.rmat_graph(s.scale, s.edge_factor, s.seed) for s in specs]
+    log(f"generated 256 graphs, E total {sum(g.E for g in gs)} in {time.perf_counter() - t0:.1f}s")
+    dgs = [cagra.DeviceGraph.from_host(g) for g in gs]
+    segs = [cagra.build_segments(d, min(32768, d.V), 8192, 65536) for d in dgs]
+    Etot = sum(g.E for g in gs)
+    mp = cagra.MultiPageRank(dgs, segs)
+    mp.capture(20)
+    torch.cuda.synchronize()
+    a, b = _events()
+    reps = 3
+    a.record()
+    for _ in range(reps):
+        mp.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    # the same work graph by graph, eager launches
+    states = [cagra.PageRankState(d, s) for d, s in zip(dgs, segs)]
+    torch.cuda.synchronize()
+    a.record()
+    for st in states:
+        st.start()
+        for _ in range(20):
+            st.step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_seq = a.elapsed_time(b)
+    return {"metric": "aggregate GTEPS, 256 uneven R-MAT graphs x 20 PageRank iterations in one captured launch",
+            "value": round(Etot * 20 / (ms * 1e-3) / 1e9, 3), "unit": "GTEPS", "ms_total": round(ms, 3),
+            "graph_by_graph_ms": round(ms_seq, 3), "speedup_vs_graph_by_graph": round(ms_seq / ms, 3),
+            "config": {"workload": "multigraph256_rmat_s10-20_ef8-32_seed4", "graphs": 256, "E_total": Etot,
+                       "V_total": int(sum(g.V for g in gs)), "tiles": int(mp.m.total_tiles),
+                       "blocks": int(mp.m.total_blocks)},
+            "dtype": "f32", "data": "synthetic"}
+
+
+def warmstart(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    from paper_1608_01362_amd import warmstart as ws
+    t0 = time.perf_counter()
+    Fs, Ts, rows = [], [], 0
+    rng = np.random.default_rng(1000)
+    for i in range(200):
+        sc = int(rng.integers(16, 21))
+        g = graphgen.rmat_graph(sc, 16, 1000 + i)
+        dg = cagra.DeviceGraph.from_host(g)
+        seg = cagra.build_segments(dg, 32768, 8192, 65536)
+        Fs.append(ws.features(dg, seg))
+        Ts.append(ws.pagerank_target(dg, seg))
+        rows += g.V
+        del dg, seg
+    F, T = torch.cat(Fs), torch.cat(Ts)
+    del Fs, Ts
+    log(f"training data: {rows} rows from 200 graphs in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = ws.train(F, T, seed=0, steps=600, batch=65536, lr=3e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del F, T
+    gt = graphgen.rmat_graph(24, 24, 5)
+    dg = cagra.DeviceGraph.from_host(gt)
+    seg = cagra.build_segments(dg, 32768, 8192, 262144)
+    ws.solve(dg, seg, tol=1e-6)  # warm-up
+    r_u, it_u, ms_u, _ = ws.solve(dg, seg, tol=1e-6)
+    r_w, it_w, ms_w, used = ws.solve(dg, seg, tol=1e-6, net=net)
+    l1 = float((r_u.double() - r_w.double()).abs().sum().item())
+    return {"metric": "time to L1 residual < 1e-6, learned warm start vs uniform, held-out R-MAT-24",
+            "value": round(ms_w, 3), "unit": "ms", "higher_is_better": False,
+            "uniform": {"iterations": it_u, "ms": round(ms_u, 3)},
+            "learned": {"iterations": it_w, "ms": round(ms_w, 3), "start_used": used},
+            "speedup": round(ms_u / ms_w, 3), "l1_between_answers": l1,
+            "training": {"graphs": 200, "rows": rows, "steps": 600, "batch": 65536, "seconds": round(train_s, 2),
+                         "loss_first": net.losses[0], "loss_last": net.losses[-1]},
+            "config": {"workload": "warmstart_rmat24_ef24_seed5", "V": gt.V, "E": gt.E, "N": 32768, "B": 8192},
+            "dtype": "f32 iteration, bf16-weight network", "data": "synthetic"}
+
+
+def run(name, args, log):
+    return {"labelprop": labelprop, "ppr": ppr, "multigraph": multigraph, "warmstart": warmstart}[name](args, log)

@@ -311,15 +311,18 @@ size_t cagra_features_workspace_bytes(const cagra_segments *seg);
  * Per-vertex features (row-major [V][3] float): log(1 + in-degree),
  * log(1 + out-degree), and the mean over in-neighbours u of log(1 + out-degree(u))
  * (0 without in-neighbours). The last one is a segmented pull: the segment
- * gather and the paper-order merge of log(1 + out-degree) over `seg`.
+ * gather of log(1 + out-degree) over `seg` and an order-free merge (int64
+ * fixed point, 2^-24 resolution). Requires 8*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES.
  */
 cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *seg, float *features,
                                    void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * y[r] = network(standardized features[r]) for r < n. weights: BF16
- * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. FP32 arithmetic,
- * exact GELU (erf).
+ * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. Exact GELU (erf);
+ * FP32 arithmetic except the 64 x 64 hidden product, which runs on the matrix
+ * cores with BF16 inputs (first-layer outputs rounded to BF16) and FP32
+ * accumulation.
  */
 cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t *weights, const float *norm,
                                float *y, hipStream_t stream);
@@ -327,8 +330,9 @@ cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t 
 size_t cagra_mlp_grad_workspace_bytes(void);
 /*
  * Mean squared error over n rows and its gradient with respect to all
- * parameters (float[CAGRA_MLP_PARAMS]); *loss (device double). Deterministic:
- * fixed row-to-workgroup assignment and fixed-order reductions.
+ * parameters (float[CAGRA_MLP_PARAMS]); *loss (device double). FP32
+ * activations throughout. Deterministic: fixed row-to-workgroup assignment and
+ * fixed-order reductions.
  */
 cagra_status cagra_mlp_grad(const float *features, const float *targets, int64_t n, const uint16_t *weights,
                             const float *norm, float *grad, double *loss, void *workspace, size_t workspace_bytes,

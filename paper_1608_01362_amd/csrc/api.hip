@@ -264,8 +264,8 @@ cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *s
     if ((s = check_built(seg)) != CAGRA_OK) return s;
     if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
     if (!features) return fail(CAGRA_E_INVALID, "features is NULL");
-    if (merge_ordered_lds_bytes(seg->B, CAGRA_SUM_F32) > CAGRA_LDS_BYTES)
-        return fail(CAGRA_E_CAPACITY, "merge block B=%d too large", seg->B);
+    if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
     if (!workspace || workspace_bytes < features_ws_bytes(seg))
         return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", features_ws_bytes(seg), workspace_bytes);
     return launch_features(g, seg, features, workspace, stream);

@@ -179,6 +179,18 @@ __device__ __forceinline__ unsigned long long fix56(float x) {
     return (u >> 31) ? (unsigned long long)(-(int64_t)r) : (unsigned long long)r;
 }
 
+// round(x * 2^24) as int64 (exact for |x| < 2^38; halves round up in magnitude).
+__device__ __forceinline__ unsigned long long fix24(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const int e = (int)((u >> 23) & 0xffu);
+    const uint64_t m = (uint64_t)((u & 0x7fffffu) | (e ? 0x800000u : 0u));
+    const int sh = (e ? e : 1) - 126;
+    uint64_t r = 0;
+    if (sh >= 0) r = m << (sh & 63);
+    else if (sh > -26) r = ((m >> (-sh - 1)) + 1) >> 1;
+    return (u >> 31) ? (unsigned long long)(-(int64_t)r) : (unsigned long long)r;
+}
+
 constexpr int kUnroll = 8;
 
 // Streams block b's buffer entries (the ranges of all subgraphs, flattened).
@@ -274,6 +286,43 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const int b = xcd_remap(blockIdx.x, nb);
     merge_pr_block<BF16OUT>(row_dst_lo, block_ptr, partial, V, k, B, b, rank_in, outdeg, scalars_in, damping,
                             rank_out, contrib_out, blk + (int64_t)b * 4, smem);
+}
+
+// Order-free merge of float buffer values into float sums (int64 fixed point,
+// 2^-24 resolution, |sums| < 2^38): used where the values are not bounded by
+// one, e.g. sums of log-degrees.
+__global__ __launch_bounds__(kMergeThreads) void k_merge_sum_fixed24(
+    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
+    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb, float *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
+    int32_t *pre = lo_s + k;
+    __shared__ int32_t tmp[16];
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
+    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, P,
+                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix24(x)); });
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads)
+        out[vb + i] = (float)((double)(long long)acc[i] * (1.0 / 16777216.0));
+}
+
+cagra_status launch_merge_sum_fixed24(const cagra_segments *seg, const float *partial, float *out, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_sum_fixed24)) return a_;
+        attr_set = true;
+    }
+    if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    k_merge_sum_fixed24<<<seg->nb, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
+        seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k, seg->B, seg->nb, out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
 }
 
 // Persistent form over many graphs: workgroups stride over a global block list.

@@ -15,15 +15,31 @@ namespace cagra {
 cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
                            void *partial, hipStream_t st);
 cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st);
+cagra_status launch_merge_sum_fixed24(const cagra_segments *seg, const float *partial, float *out, hipStream_t st);
 
 constexpr int kH = 64;
 constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4480;
 constexpr int kNParam = CAGRA_MLP_PARAMS;
 static_assert(kNParam == 4481, "parameter layout");
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf(x) by Abramowitz & Stegun, Handbook of Mathematical Functions, formula
+// 7.1.26 (|error| <= 1.5e-7): branch-free, one reciprocal and one exp2.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    p *= t;
+    const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+    return copysignf(fmaf(-p, e, 1.0f), x);
+}
+// GELU(x) = x * Phi(x) (Hendrycks & Gimpel 2016) and its derivative Phi(x) + x * phi(x).
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+           x * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f) * 0.39894228040143268f;
 }
 
 // ------------------------------------------------------------------ features
@@ -58,7 +74,7 @@ cagra_status launch_features(const cagra_graph *g, const cagra_segments *seg, fl
     CAGRA_LAUNCH_CHECK();
     cagra_status s;
     if ((s = launch_gather(seg, CAGRA_SUM_F32, CAGRA_F32, vals, partial, st)) != CAGRA_OK) return s;
-    if ((s = launch_merge(seg, CAGRA_SUM_F32, partial, sumlog, st)) != CAGRA_OK) return s;
+    if ((s = launch_merge_sum_fixed24(seg, partial, sumlog, st)) != CAGRA_OK) return s;
     k_features<<<grid, 256, 0, st>>>(g->in_offsets, g->out_degree, sumlog, g->V, feats);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
@@ -73,31 +89,87 @@ __device__ __forceinline__ void load_weights(const uint16_t *__restrict__ wb, fl
 
 constexpr int kFwdThreads = 256;
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// Forward pass, 16 rows per wave step. The 64x64 hidden layer is a dense
+// contraction and runs on the matrix cores (v_mfma_f32_16x16x32_bf16: BF16
+// inputs, FP32 accumulation). Lane l computes the first-layer units
+// u = 32s + 8(l/16) + t of row l%16 directly in the A-operand layout, holds the
+// BF16 weights of W2 as B operands for the whole kernel, and receives
+// z2[4(l/16) + r][16c + l%16] in the accumulators; the output layer is a
+// 16-lane butterfly sum.
 __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__restrict__ feats, int64_t n,
                                                              const uint16_t *__restrict__ wb,
                                                              const float *__restrict__ norm,
                                                              float *__restrict__ y) {
-    __shared__ float w[kNParam + 3];
-    load_weights(wb, w);
-    __syncthreads();
-    const float m0 = norm[0], m1 = norm[1], m2 = norm[2], s0 = norm[3], s1 = norm[4], s2 = norm[5];
-    for (int64_t r = (int64_t)blockIdx.x * kFwdThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kFwdThreads) {
-        const float x0 = (feats[r * 3 + 0] - m0) * s0, x1 = (feats[r * 3 + 1] - m1) * s1,
-                    x2 = (feats[r * 3 + 2] - m2) * s2;
-        float h1[kH];
+    const int lane = threadIdx.x & 63, kq = lane >> 4, jl = lane & 15;
+    // first-layer weights of this lane's 16 units, second-layer operands, output weights
+    float w1[16][3], b1[16];
+    bf16x8 B[4][2];
+    float b2[4], w3[4];
 #pragma unroll
-        for (int i = 0; i < kH; ++i)
-            h1[i] = gelu(fmaf(w[kOffW1 + 3 * i + 2], x2,
-                              fmaf(w[kOffW1 + 3 * i + 1], x1, fmaf(w[kOffW1 + 3 * i], x0, w[kOffB1 + i]))));
-        float out = w[kOffB3];
-#pragma unroll 1
-        for (int j = 0; j < kH; ++j) {
-            float z = w[kOffB2 + j];
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int i = 0; i < kH; ++i) z = fmaf(w[kOffW2 + j * kH + i], h1[i], z);
-            out = fmaf(w[kOffW3 + j], gelu(z), out);
+        for (int t = 0; t < 8; ++t) {
+            const int u = 32 * s + 8 * kq + t;
+            w1[8 * s + t][0] = bf16_to_f32(wb[kOffW1 + 3 * u + 0]);
+            w1[8 * s + t][1] = bf16_to_f32(wb[kOffW1 + 3 * u + 1]);
+            w1[8 * s + t][2] = bf16_to_f32(wb[kOffW1 + 3 * u + 2]);
+            b1[8 * s + t] = bf16_to_f32(wb[kOffB1 + u]);
         }
-        y[r] = out;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = 16 * c + jl;
+        b2[c] = bf16_to_f32(wb[kOffB2 + j]);
+        w3[c] = bf16_to_f32(wb[kOffW3 + j]);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) B[c][s][t] = bits_to_bf16(wb[kOffW2 + j * kH + 32 * s + 8 * kq + t]);
+    }
+    const float b3 = bf16_to_f32(wb[kOffB3]);
+    const float m0 = norm[0], m1 = norm[1], m2 = norm[2], s0 = norm[3], s1 = norm[4], s2 = norm[5];
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t wave = ((int64_t)blockIdx.x * kFwdThreads + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kFwdThreads) >> 6;
+    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+        const int64_t r = tile * 16 + jl;
+        const bool live = r < n;
+        const float x0 = live ? (feats[r * 3 + 0] - m0) * s0 : 0.0f;
+        const float x1 = live ? (feats[r * 3 + 1] - m1) * s1 : 0.0f;
+        const float x2 = live ? (feats[r * 3 + 2] - m2) * s2 : 0.0f;
+        bf16x8 A[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int q = 8 * s + t;
+                A[s][t] = (__bf16)gelu(fmaf(w1[q][2], x2, fmaf(w1[q][1], x1, fmaf(w1[q][0], x0, b1[q]))));
+            }
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[c][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[c][1], acc, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) part[q] = fmaf(w3[c], gelu(acc[q] + b2[c]), part[q]);
+        }
+        // sum over the 16 lanes (output units) that hold the same four rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 8; m >= 1; m >>= 1) part[q] += __shfl_xor(part[q], m, 16);
+        if (jl == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t ro = tile * 16 + 4 * kq + q;
+                if (ro < n) y[ro] = part[q] + b3;
+            }
+        }
     }
 }
 
@@ -251,7 +323,7 @@ static size_t bwd_lds_bytes() {
 cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *wb, const float *norm, float *y,
                                 hipStream_t st) {
     if (n == 0) return CAGRA_OK;
-    int64_t g = ceil_div(n, kFwdThreads);
+    int64_t g = ceil_div(ceil_div(n, 16), kFwdThreads / 64);
     if (g > 4096) g = 4096;
     k_mlp_forward<<<(unsigned)g, kFwdThreads, 0, st>>>(feats, n, wb, norm, y);
     CAGRA_LAUNCH_CHECK();
