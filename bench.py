@@ -33,12 +33,13 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def byte_model(V, E, Q, k, nb, wc):
+def byte_model(V, E, Q, k, nb, wc, we=4):
     """Algorithmic HBM bytes per iteration (what the method must move).
-    gather: edge words (4E) + each segment's values staged once (wc*V) + buffer writes (4Q)
+    gather: edge words (we*E; we = 2 for 16-bit words, N <= 32768) + each segment's values
+            staged once (wc*V) + buffer writes (4Q)
     merge:  buffer reads (4Q) + destination offsets in the block (2Q, uint16) + block index (4k(nb+1))
             + rank_in, out_degree, rank_out (12V) + contrib_out (wc*V)"""
-    gather = 4 * E + wc * V + 4 * Q
+    gather = we * E + wc * V + 4 * Q
     merge = 6 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
     return gather, merge
 
@@ -172,7 +173,8 @@ def main():
         f" wall {wall / K * 1e3:.3f} ms/step")
 
     V, E, Q, k, nb = g.V, g.E, seg.Q, seg.k, seg.c.nb
-    gb, mb = byte_model(V, E, Q, k, nb, wc)
+    we = 2 if args.N <= cagra.EDGE16_MAX_N else 4
+    gb, mb = byte_model(V, E, Q, k, nb, wc, we)
     g_avg, m_avg = sum(gather_ms) / K, sum(merge_ms) / K
     if g_avg >= m_avg:
         dom, dbytes, dms = "k_gather", gb, g_avg

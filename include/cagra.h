@@ -63,6 +63,10 @@ enum {
    sized segments). The rest of the LDS collects finished rows for coalesced
    buffer writes. */
 #define CAGRA_STAGE_BYTES 131072
+/* Segments of at most this many vertices store 16-bit edge words: a local
+   source index needs 15 bits and bit 15 marks a row start. This halves the
+   dominant edge stream of segment processing. */
+#define CAGRA_EDGE16_MAX_N 32768
 /* Waves (64 lanes) that share one staged segment in the gather kernel. */
 #define CAGRA_TILE_WAVES 16
 
@@ -83,8 +87,11 @@ typedef struct {
  *   seg_row_begin[k+1]   first row of subgraph s; seg_row_begin[k] = Q
  *   row_ptr[Q+1]         first edge of each row; row_ptr[Q] = E
  *   row_dst[Q]           global destination of each row (the paper's idxMap)
- *   edge_src[E]          local source index u - s*N; bit 31 is set on the first
- *                        edge of every row (mask with 0x7fffffff for the index)
+ *   edge_src[E]          edge words: the local source index u - s*N plus a
+ *                        row-start flag on the first edge of every row. Word
+ *                        width depends on N: uint16 when N <= CAGRA_EDGE16_MAX_N
+ *                        (flag = bit 15, index = bits 0-14), int32 otherwise
+ *                        (flag = bit 31, index = bits 0-30)
  *   block_ptr[(nb+1)*k]  merge block index: block_ptr[b*k + s] = first row of
  *                        subgraph s whose destination is >= b*B (Section 3.3's
  *                        block starts; block b of subgraph s ends at
@@ -98,8 +105,9 @@ typedef struct {
  *   row_dst_lo[Q]        row_dst mod B as uint16: the destination's offset in
  *                        its merge block (what the fused merges read)
  *
- * edge_src must be 16-byte aligned. All arrays are caller-allocated device
- * memory of the sizes the query call reports.
+ * edge_src must be 16-byte aligned and hold E * cagra_edge_word_bytes(N)
+ * bytes. All arrays are caller-allocated device memory of the sizes the query
+ * call reports.
  */
 typedef struct {
     /* parameters (set by the caller before the query call) */
@@ -114,7 +122,7 @@ typedef struct {
     int32_t *seg_row_begin;
     int32_t *row_ptr;
     int32_t *row_dst;
-    int32_t *edge_src;
+    void *edge_src;
     int32_t *block_ptr;
     int32_t *tile_edge;
     int32_t *tile_seg;
@@ -128,6 +136,10 @@ const char *cagra_status_string(int status);
 const char *cagra_last_error(void);
 /* Largest merge block B accepted (LDS capacity of the merge kernel). */
 int32_t cagra_max_merge_block(void);
+
+/* Bytes per edge word of a segmentation with segment size N: 2 when
+   N <= CAGRA_EDGE16_MAX_N, else 4 (0 for N < 1). */
+int32_t cagra_edge_word_bytes(int32_t N);
 
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);

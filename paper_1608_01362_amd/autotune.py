@@ -58,9 +58,13 @@ def fused_merge_fits(B: int, k: int, acc_bytes: int = 8) -> bool:
     return acc_bytes * B + 8 * (k + 1) + 320 <= cagra.LDS_BYTES
 
 
-def byte_model(V: int, E: int, Q: int, k: int, B: int, wc: int) -> int:
+def edge_word_bytes(N: int) -> int:
+    return 2 if N <= cagra.EDGE16_MAX_N else 4
+
+
+def byte_model(V: int, E: int, Q: int, k: int, B: int, wc: int, we: int = 4) -> int:
     nb = -(-V // B)
-    return 4 * E + wc * V + 4 * Q + 6 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
+    return we * E + wc * V + 4 * Q + 6 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
 
 
 def query_Q(dg, N: int, B: int, tile_edges: int) -> int:
@@ -132,7 +136,8 @@ def tune(dg, value_type: int = cagra.F32, op: str = "pagerank", cache_path: str 
             if not fused_merge_fits(B, k):
                 continue
             for T in tiles:
-                cands.append(Choice(N, B, T, N <= lds_staged_max(value_type), Q, byte_model(dg.V, dg.E, Q, k, B, wc)))
+                cands.append(Choice(N, B, T, N <= lds_staged_max(value_type), Q,
+                                    byte_model(dg.V, dg.E, Q, k, B, wc, edge_word_bytes(N))))
     best_bytes = min(c.predicted_bytes for c in cands)
     # staged candidates first: gathers through the cache hierarchy are request-bound
     pool = sorted([c for c in cands if c.predicted_bytes <= prune_factor * best_bytes],

@@ -23,6 +23,7 @@ SUM_F32, MIN_I32, SUM_F32_COMP = 0, 1, 2
 LDS_BYTES = 163840
 STAGE_BYTES = 131072
 TILE_WAVES = 16
+EDGE16_MAX_N = 32768
 PPR_COLS = 64
 
 _c_i32, _c_i64, _c_size, _c_vp, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
@@ -43,7 +44,7 @@ class CSegments(ctypes.Structure):
 
 EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
-    "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
+    "cagra_edge_word_bytes", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
@@ -82,6 +83,7 @@ def lib():
             "cagra_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "cagra_last_error": ([], ctypes.c_char_p),
             "cagra_max_merge_block": ([], _c_i32),
+            "cagra_edge_word_bytes": ([_c_i32], _c_i32),
             "cagra_query_workspace_bytes": ([_c_i32, _c_i64, _c_i32], _c_size),
             "cagra_build_segments": ([GP, SP, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_iter_workspace_bytes": ([SP], _c_size),
@@ -213,7 +215,10 @@ def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = Non
         "seg_row_begin": torch.empty(k + 1, dtype=i32, device=dev),
         "row_ptr": torch.empty(Q + 1, dtype=i32, device=dev),
         "row_dst": torch.empty(max(Q, 1), dtype=i32, device=dev),
-        "edge_src": torch.empty(max(E, 4), dtype=i32, device=dev),
+        # 16-bit edge words for N <= EDGE16_MAX_N, 32-bit otherwise; the
+        # allocation is rounded up to 16 bytes (the gather loads 16-byte chunks)
+        "edge_src": (torch.empty(max(-(-E // 8) * 8, 8), dtype=torch.int16, device=dev) if N <= EDGE16_MAX_N
+                     else torch.empty(max(-(-E // 4) * 4, 4), dtype=i32, device=dev)),
         "block_ptr": torch.empty((nb + 1) * k, dtype=i32, device=dev),
         "tile_edge": torch.empty(nt + 1, dtype=i32, device=dev),
         "tile_seg": torch.empty(max(nt, 1), dtype=i32, device=dev),

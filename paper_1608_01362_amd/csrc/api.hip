@@ -128,6 +128,8 @@ const char *cagra_last_error(void) { return g_last_error; }
 
 int32_t cagra_max_merge_block(void) { return kMaxMergeBlock; }
 
+int32_t cagra_edge_word_bytes(int32_t N) { return N < 1 ? 0 : (edge16(N) ? 2 : 4); }
+
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
     if (V < 1 || N < 1 || E < 0) return 0;
     return query_workspace_bytes(V, E, N);

@@ -293,16 +293,17 @@ __global__ void k_rows(const int32_t *__restrict__ run_first, const int32_t *__r
     if (r == Q) row_len[Q] = 0;
 }
 
+template <typename W>
 __global__ void k_edges(const int32_t *__restrict__ src, const int32_t *__restrict__ runincl,
                         const int32_t *__restrict__ run_first, const int32_t *__restrict__ pos,
-                        const int32_t *__restrict__ row_ptr, int64_t E, int32_t N, int32_t *__restrict__ edge_src) {
+                        const int32_t *__restrict__ row_ptr, int64_t E, int32_t N, W *__restrict__ edge_src) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int32_t r = runincl[e] - 1;
     int32_t off = (int32_t)e - run_first[r];
     int32_t u = src[e];
-    int32_t local = u - (u / N) * N;
-    edge_src[row_ptr[pos[r]] + off] = off == 0 ? (int32_t)((uint32_t)local | 0x80000000u) : local;
+    uint32_t local = (uint32_t)(u - (u / N) * N);
+    edge_src[row_ptr[pos[r]] + off] = (W)(off == 0 ? (local | EdgeWord<W>::kFlag) : local);
 }
 
 // First index in [lo, hi) with a[i] >= x (hi if none).
@@ -535,7 +536,12 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
                                                  seg->row_ptr);
     CAGRA_LAUNCH_CHECK();
     if ((s = scan_i32<ScanAdd>(seg->row_ptr, seg->row_ptr, Q + 1, false, ar, st)) != CAGRA_OK) return s;
-    k_edges<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N, seg->edge_src);
+    if (edge16(N))
+        k_edges<uint16_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N,
+                                                             (uint16_t *)seg->edge_src);
+    else
+        k_edges<uint32_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N,
+                                                             (uint32_t *)seg->edge_src);
     CAGRA_LAUNCH_CHECK();
     // 4. merge block index and gather tiles
     k_block_ptr<<<grid_for((int64_t)(nb + 1) * k, 256), 256, 0, st>>>(seg->row_dst, seg->seg_row_begin, k, nb, B,

@@ -61,7 +61,7 @@ static inline cagra_status allow_dynamic_lds(const void *fn) {
 
 // Per-graph descriptor of the persistent multi-graph kernels (device memory).
 struct MultiDesc {
-    const int32_t *edge_src;
+    const void *edge_src;  // 16-bit edge words (multi-graph runs use N <= CAGRA_EDGE16_MAX_N)
     const int32_t *tile_edge;
     const int32_t *tile_seg;
     const int32_t *tile_span_row;
@@ -76,6 +76,20 @@ struct MultiDesc {
     int64_t tile_base;   // first global tile of this graph
     int64_t block_base;  // first global merge block of this graph
     int32_t V, N, k, B, nb, ntiles;
+};
+
+// Edge words of a segmented graph: local source index plus a row-start flag.
+// 16-bit words for N <= CAGRA_EDGE16_MAX_N, 32-bit words otherwise.
+__host__ __device__ static inline bool edge16(int32_t N) { return N <= CAGRA_EDGE16_MAX_N; }
+template <typename W>
+struct EdgeWord;
+template <>
+struct EdgeWord<uint16_t> {
+    static constexpr uint32_t kFlag = 0x8000u, kIndex = 0x7fffu;
+};
+template <>
+struct EdgeWord<uint32_t> {
+    static constexpr uint32_t kFlag = 0x80000000u, kIndex = 0x7fffffffu;
 };
 
 // ---------------------------------------------------------------- device helpers

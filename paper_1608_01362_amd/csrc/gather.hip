@@ -7,7 +7,9 @@
 // 128 KB: 32,768 FP32 or 65,536 BF16 values); larger segments are read through
 // the cache hierarchy instead (L2- or Infinity-Cache-sized segments). Each wave
 // streams an equal share of the tile's edge array with 16-byte non-temporal
-// loads. Row boundaries are bit 31 of the edge word, so the per-row
+// loads, three chunks ahead. Edge words are 16-bit for segments of at most
+// 32,768 vertices (15-bit local index) and 32-bit otherwise; the row-start
+// flag is the word's top bit, so the per-row
 // combination is a segmented scan across the wave (shuffles), and rows that
 // cross from one wave's share into the next are completed after a barrier in
 // wave order. No atomics; the combination order is fixed by the data layout,
@@ -161,30 +163,39 @@ struct SpanState {
 // Rows finished in the chunk are exactly chunk_nf consecutive rows starting
 // at row0 + nflags - 1; they are collected in `stage` and written with
 // coalesced stores.
-template <class Op, typename VT, bool STAGED>
-__device__ __forceinline__ void process_chunk(const v4i (&wv)[kEPT / 4], int64_t cidx, int64_t w0, int64_t w1,
+// 16-byte loads per lane per chunk for edge words of type W.
+template <typename W>
+constexpr int kLoads = kEPT * (int)sizeof(W) / 16;
+
+template <class Op, typename VT, bool STAGED, typename W>
+__device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int64_t cidx, int64_t w0, int64_t w1,
                                               const VT *seg_vals, const VT *gvals, typename Op::T *stage,
                                               __amdgpu_buffer_rsrc_t out, SpanState<typename Op::T> &S) {
     using T = typename Op::T;
     using F = Fetch<VT, STAGED>;
     const int lane = __lane_id();
     const int64_t idx = cidx + lane * kEPT;
-    int32_t w[kEPT];
+    uint32_t w[kEPT];
+    if constexpr (sizeof(W) == 4) {
 #pragma unroll
-    for (int j = 0; j < kEPT / 4; ++j) {
-        w[4 * j + 0] = wv[j].x;
-        w[4 * j + 1] = wv[j].y;
-        w[4 * j + 2] = wv[j].z;
-        w[4 * j + 3] = wv[j].w;
+        for (int j = 0; j < kLoads<W>; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) w[4 * j + c] = (uint32_t)wv[j][c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            w[2 * c] = (uint32_t)wv[0][c] & 0xffffu;
+            w[2 * c + 1] = (uint32_t)wv[0][c] >> 16;
+        }
     }
     uint32_t fmask = 0;
     T v[kEPT];
 #pragma unroll
     for (int i = 0; i < kEPT; ++i) {
         const bool valid = (idx + i >= w0) && (idx + i < w1);
-        fmask |= (valid && w[i] < 0) ? (1u << i) : 0u;
+        fmask |= (valid && (w[i] & EdgeWord<W>::kFlag)) ? (1u << i) : 0u;
         // words outside the share may belong to another segment: read index 0 instead
-        const T x = F::get(seg_vals, gvals, valid ? (w[i] & 0x7fffffff) : 0);
+        const T x = F::get(seg_vals, gvals, valid ? (int32_t)(w[i] & EdgeWord<W>::kIndex) : 0);
         v[i] = valid ? x : Op::identity();
     }
     const int32_t nf = __popc(fmask);
@@ -235,8 +246,16 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kEPT / 4], int64_t
 
 // One gather tile (all 16 waves of the workgroup). `smem` is the workgroup's
 // dynamic LDS: kStageBytes of per-wave row staging, then the segment values.
-template <class Op, typename VT, bool STAGED>
-__device__ __forceinline__ void gather_tile(const int32_t *__restrict__ edge_src, int64_t Q,
+template <typename W>
+__device__ __forceinline__ void load_chunk(v4i (&r)[kLoads<W>], __amdgpu_buffer_rsrc_t ein, uint32_t off) {
+#pragma unroll
+    for (int j = 0; j < kLoads<W>; ++j) r[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, off + 16 * j, 0, kNonTemporal);
+}
+
+constexpr int kStages = 4;  // chunks in flight per wave (three ahead of the one processed)
+
+template <class Op, typename VT, bool STAGED, typename W>
+__device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int64_t Q,
                                             const int32_t *__restrict__ tile_edge,
                                             const int32_t *__restrict__ tile_seg,
                                             const int32_t *__restrict__ span_row, const VT *__restrict__ values,
@@ -267,9 +286,12 @@ __device__ __forceinline__ void gather_tile(const int32_t *__restrict__ edge_src
 
     // Buffer descriptors: loads past the share read zero, and stores to rows
     // outside [row0, Q) are dropped, so the loop needs no bounds branches.
-    const int64_t ebase = w0 & ~(int64_t)3;
-    const __amdgpu_buffer_rsrc_t ein =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(edge_src + ebase), 0, (int32_t)((w1 - ebase) * 4), kBufFlags);
+    // ebase: the share's start rounded down to a 16-byte boundary; the range
+    // is rounded up to whole dwords so the share's last word is never cut off
+    constexpr int kWB = (int)sizeof(W);
+    const int64_t ebase = w0 & ~(int64_t)(16 / kWB - 1);
+    const __amdgpu_buffer_rsrc_t ein = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(edge_src + ebase), 0, (int32_t)align_up((size_t)(w1 - ebase) * kWB, 4), kBufFlags);
     int64_t rows_left = Q - row0;
     if (rows_left > (1 << 28)) rows_left = 1 << 28;
     if (rows_left < 0) rows_left = 0;
@@ -279,22 +301,18 @@ __device__ __forceinline__ void gather_tile(const int32_t *__restrict__ edge_src
     SpanState<T> S{Op::identity(), Op::identity(), 0};
     T *stage = reinterpret_cast<T *>(smem) + (size_t)w * kStageRows;
     const int64_t len = w1 - ebase;
-    v4i A[kEPT / 4], Bv[kEPT / 4];
-    const uint32_t lane_off = (uint32_t)lane * kEPT * 4;
+    const uint32_t lane_off = (uint32_t)(lane * kEPT * kWB);
+    v4i R[kStages][kLoads<W>];
 #pragma unroll
-    for (int j = 0; j < kEPT / 4; ++j)
-        A[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, lane_off + 16 * j, 0, kNonTemporal);
-    for (int64_t cc = 0; cc < len; cc += 2 * kChunk) {
-        const uint32_t ob = (uint32_t)(cc + kChunk) * 4 + lane_off;
+    for (int c = 0; c < kStages - 1; ++c) load_chunk<W>(R[c], ein, (uint32_t)(c * kChunk * kWB) + lane_off);
+    for (int64_t cc = 0; cc < len; cc += kStages * kChunk) {
 #pragma unroll
-        for (int j = 0; j < kEPT / 4; ++j)
-            Bv[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, ob + 16 * j, 0, kNonTemporal);
-        process_chunk<Op, VT, STAGED>(A, ebase + cc, w0, w1, seg_vals, gvals, stage, out, S);
-        const uint32_t oa = (uint32_t)(cc + 2 * kChunk) * 4 + lane_off;
-#pragma unroll
-        for (int j = 0; j < kEPT / 4; ++j)
-            A[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, oa + 16 * j, 0, kNonTemporal);
-        process_chunk<Op, VT, STAGED>(Bv, ebase + cc + kChunk, w0, w1, seg_vals, gvals, stage, out, S);
+        for (int c = 0; c < kStages; ++c) {
+            if (cc + c * kChunk >= len) break;  // uniform: len and cc are wave-wide
+            load_chunk<W>(R[(c + kStages - 1) % kStages], ein,
+                          (uint32_t)((cc + (c + kStages - 1) * kChunk) * kWB) + lane_off);
+            process_chunk<Op, VT, STAGED, W>(R[c], ebase + cc + c * kChunk, w0, w1, seg_vals, gvals, stage, out, S);
+        }
     }
 
     // complete rows that continue into later waves' shares, in wave order
@@ -322,14 +340,14 @@ __device__ __forceinline__ void gather_tile(const int32_t *__restrict__ edge_src
     }
 }
 
-template <class Op, typename VT, bool STAGED>
+template <class Op, typename VT, bool STAGED, typename W>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
-    const int32_t *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
+    const W *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
     const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
     int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     (void)E;
-    gather_tile<Op, VT, STAGED>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
+    gather_tile<Op, VT, STAGED, W>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
                                 xcd_remap(blockIdx.x, ntiles), partial, smem);
 }
 
@@ -342,7 +360,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_multi_gather(const MultiDesc
         __syncthreads();  // LDS reuse across tiles
         const int gi = tile_graph[gt];
         const MultiDesc &d = desc[gi];
-        gather_tile<OpSum, float, true>(d.edge_src, d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
+        gather_tile<OpSum, float, true, uint16_t>(static_cast<const uint16_t *>(d.edge_src), d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
                                         d.contrib[parity], d.V, d.N, (int)(gt - d.tile_base), d.partial, smem);
     }
 }
@@ -361,21 +379,37 @@ cagra_status launch_multi_gather(const MultiDesc *desc, const int32_t *tile_grap
     return CAGRA_OK;
 }
 
-template <class Op, typename VT, bool STAGED>
-static cagra_status launch_gather_t(const cagra_segments *seg, const VT *values, typename Op::T *partial,
+template <class Op, typename VT, bool STAGED, typename W>
+static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values, typename Op::T *partial,
                                     hipStream_t st) {
     if (seg->ntiles == 0) return CAGRA_OK;
-    auto kern = k_gather<Op, VT, STAGED>;
+    auto kern = k_gather<Op, VT, STAGED, W>;
     const size_t lds = kStageBytes + (STAGED ? (size_t)seg->N * sizeof(VT) : 0);
     static bool attr_set = false;
     if (!attr_set) {
         if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
         attr_set = true;
     }
-    kern<<<seg->ntiles, kGatherThreads, lds, st>>>(seg->edge_src, seg->E, seg->Q, seg->tile_edge, seg->tile_seg,
-                                                  seg->tile_span_row, values, seg->V, seg->N, seg->ntiles, partial);
+    kern<<<seg->ntiles, kGatherThreads, lds, st>>>(static_cast<const W *>(seg->edge_src), seg->E, seg->Q,
+                                                  seg->tile_edge, seg->tile_seg, seg->tile_span_row, values, seg->V,
+                                                  seg->N, seg->ntiles, partial);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
+}
+
+// Staged segments of at most CAGRA_EDGE16_MAX_N vertices use 16-bit edge
+// words; larger staged ones (BF16 values) and all unstaged ones use 32-bit words.
+template <class Op, typename VT, bool STAGED>
+static cagra_status launch_gather_t(const cagra_segments *seg, const VT *values, typename Op::T *partial,
+                                    hipStream_t st) {
+    if constexpr (STAGED) {
+        if (edge16(seg->N)) return launch_gather_w<Op, VT, true, uint16_t>(seg, values, partial, st);
+        if constexpr (sizeof(VT) == 2) return launch_gather_w<Op, VT, true, uint32_t>(seg, values, partial, st);
+        return fail(CAGRA_E_INVALID, "internal: staged segment of %d vertices with 32-bit edge words", seg->N);
+    } else {
+        if (edge16(seg->N)) return fail(CAGRA_E_INVALID, "internal: unstaged segment of %d vertices", seg->N);
+        return launch_gather_w<Op, VT, false, uint32_t>(seg, values, partial, st);
+    }
 }
 
 bool gather_staged(int32_t N, int32_t value_type) {

@@ -197,7 +197,10 @@ constexpr int kUnroll = 8;
 // Each wave takes a contiguous share; per pass a lane handles kUnroll entries
 // 64 apart, finding its subgraph by walking forward from the pass's first one.
 // All loads are issued unconditionally (clamped index) so that many are in
-// flight; apply(d, x) updates the LDS accumulator of block offset d.
+// flight; apply(d, x) updates the LDS accumulator of block offset d. The loads
+// keep the default cache policy: the cache line at each end of a (subgraph,
+// block) range is shared with the neighbouring block, which is merged at the
+// same time on the same XCD and finds the line in L2.
 template <typename PT, class Apply>
 __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, const PT *__restrict__ partial,
                                              const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t P,
@@ -216,8 +219,8 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
             const int32_t ff = valid ? f : f0;
             while (sl + 1 < k && pre[sl + 1] <= ff) ++sl;
             const int32_t i = lo_s[sl] + (ff - pre[sl]);
-            const int32_t dd = (int32_t)__builtin_nontemporal_load(dlo + i);
-            x[u] = __builtin_nontemporal_load(partial + i);
+            const int32_t dd = (int32_t)dlo[i];
+            x[u] = partial[i];
             d[u] = valid ? dd : -1;
         }
 #pragma unroll

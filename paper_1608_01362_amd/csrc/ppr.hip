@@ -22,7 +22,8 @@ constexpr int kPprWaves = CAGRA_TILE_WAVES;
 constexpr int kPprThreads = kPprWaves * kWave;
 constexpr int kBatch = 16;  // source rows loaded ahead per wave
 
-__global__ __launch_bounds__(kPprThreads) void k_gather_cols(const int32_t *__restrict__ edge_src, int64_t E,
+template <typename W>
+__global__ __launch_bounds__(kPprThreads) void k_gather_cols(const W *__restrict__ edge_src, int64_t E,
                                                              const int32_t *__restrict__ tile_edge,
                                                              const int32_t *__restrict__ tile_seg,
                                                              const int32_t *__restrict__ span_row,
@@ -52,20 +53,20 @@ __global__ __launch_bounds__(kPprThreads) void k_gather_cols(const int32_t *__re
 
     for (int64_t b0 = w0; b0 < w1; b0 += kWave) {
         const int64_t e = b0 + lane;
-        const int32_t word = e < w1 ? edge_src[e] : 0;
+        const uint32_t word = e < w1 ? (uint32_t)edge_src[e] : 0u;
         const int n = (int)(w1 - b0 < kWave ? w1 - b0 : kWave);
         for (int jb = 0; jb < n; jb += kBatch) {
-            int32_t wv[kBatch];
+            uint32_t wv[kBatch];
             float x[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                wv[u] = __builtin_amdgcn_readlane(word, jb + u);
-                x[u] = vals[(int64_t)(wv[u] & 0x7fffffff) * kCols];
+                wv[u] = (uint32_t)__builtin_amdgcn_readlane((int32_t)word, jb + u);
+                x[u] = vals[(int64_t)(wv[u] & EdgeWord<W>::kIndex) * kCols];
             }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 if (jb + u < n) {
-                    if (wv[u] < 0) {  // a row starts: the open row is complete
+                    if (wv[u] & EdgeWord<W>::kFlag) {  // a row starts: the open row is complete
                         if (seen) partial[(int64_t)row * kCols + lane] = acc + comp;
                         else head = acc + comp;
                         seen = 1;
@@ -230,9 +231,14 @@ cagra_status launch_ppr_iter(const cagra_graph *g, const cagra_segments *seg, do
                              const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
                              double *scalars_out, double *blk, hipStream_t st) {
     if (seg->ntiles > 0) {
-        k_gather_cols<<<seg->ntiles, kPprThreads, 0, st>>>(seg->edge_src, seg->E, seg->tile_edge, seg->tile_seg,
-                                                            seg->tile_span_row, contrib_in, seg->N, seg->ntiles,
-                                                            partial);
+        if (edge16(seg->N))
+            k_gather_cols<uint16_t><<<seg->ntiles, kPprThreads, 0, st>>>(
+                static_cast<const uint16_t *>(seg->edge_src), seg->E, seg->tile_edge, seg->tile_seg,
+                seg->tile_span_row, contrib_in, seg->N, seg->ntiles, partial);
+        else
+            k_gather_cols<uint32_t><<<seg->ntiles, kPprThreads, 0, st>>>(
+                static_cast<const uint32_t *>(seg->edge_src), seg->E, seg->tile_edge, seg->tile_seg,
+                seg->tile_span_row, contrib_in, seg->N, seg->ntiles, partial);
         CAGRA_LAUNCH_CHECK();
     }
     static bool attr = false;

@@ -129,3 +129,15 @@ def test_validation_of_built_segments(cagra):
     s = _fake_built(cagra)
     g = _graph(cagra, V=100, E=50)
     assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 8, None) == -4
+
+
+def test_edge_word_bytes(cagra):
+    """16-bit edge words exactly when a local index fits 15 bits (N <= 32768)."""
+    L = cagra.lib()
+    assert L.cagra_edge_word_bytes(0) == 0
+    assert L.cagra_edge_word_bytes(1) == 2
+    assert L.cagra_edge_word_bytes(cagra.EDGE16_MAX_N) == 2
+    assert L.cagra_edge_word_bytes(cagra.EDGE16_MAX_N + 1) == 4
+    assert L.cagra_edge_word_bytes(1 << 24) == 4
+    text = open(HEADER).read()
+    assert re.search(r"#define CAGRA_EDGE16_MAX_N (\d+)", text).group(1) == str(cagra.EDGE16_MAX_N)

@@ -54,11 +54,17 @@ def check_layout(c, g, N, B, T):
     assert np.array_equal(h["row_dst"], ref.row_dst)
     assert np.array_equal(h["row_dst_lo"].view(np.uint16).astype(np.int64), ref.row_dst.astype(np.int64) % B)
     assert np.array_equal(h["block_ptr"], ref.block_ptr)
-    es = h["edge_src"].view(np.uint32)
-    assert np.array_equal((es & 0x7FFFFFFF).astype(np.int32), ref.edge_src)
+    # edge words: 16-bit (flag bit 15) for N <= 32768, else 32-bit (flag bit 31)
+    if N <= c.EDGE16_MAX_N:
+        assert h["edge_src"].dtype == np.int16
+        es, top = h["edge_src"].view(np.uint16).astype(np.uint32), 15
+    else:
+        assert h["edge_src"].dtype == np.int32
+        es, top = h["edge_src"].view(np.uint32), 31
+    assert np.array_equal((es & ((1 << top) - 1)).astype(np.int32), ref.edge_src)
     flags = np.zeros(g.E, dtype=bool)
     flags[ref.row_ptr[:-1]] = True
-    assert np.array_equal((es >> 31).astype(bool), flags)
+    assert np.array_equal((es >> top).astype(bool), flags)
     # gather tiles: row-aligned, inside one subgraph, covering every edge once
     te, ts, sr = h["tile_edge"], h["tile_seg"], h["tile_span_row"].reshape(-1, c.TILE_WAVES)
     nt = seg.c.ntiles
@@ -87,9 +93,33 @@ def test_builder_bit_exact(cagra, gi, N, B, T):
     check_layout(cagra, g, N, B, T)
 
 
-@pytest.mark.parametrize("N,B,T", [(4096, 2048, 4096), (16384, 16384, 65536), (40960, 16384, 65536)])
+@pytest.mark.parametrize("N,B,T", [(4096, 2048, 4096), (16384, 16384, 65536), (32768, 8192, 65536),
+                                   (32769, 8192, 65536), (40960, 16384, 65536)])
 def test_builder_bit_exact_rmat16(cagra, N, B, T):
     check_layout(cagra, graphgen.rmat_graph(16, 16, 1), N, B, T)
+
+
+@pytest.mark.parametrize("N", [32767, 32768, 32769])
+def test_gather_edge_word_width_boundary(cagra, N):
+    """Around the 16/32-bit edge word switch: local indices use all 15 bits
+    (R-MAT 16 has 65,536 vertices, so the segments are full), ragged shares."""
+    import torch
+    g = graphgen.rmat_graph(16, 16, 1)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, N, 8192, 1000)
+    ref = oracle.segment(g, N, 8192)
+    rng = np.random.default_rng(N)
+    x = rng.random(g.V).astype(np.float32)
+    part = torch.full((seg.Q,), float("nan"), dtype=torch.float32, device="cuda")
+    cagra.segment_gather(seg, cagra.SUM_F32, cagra.F32, torch.from_numpy(x).cuda(), part)
+    want = oracle.segment_gather(ref, x.astype(np.float64), oracle.SUM)
+    got = _host(part).astype(np.float64)
+    assert np.all(np.abs(got - want) <= _rows_len(ref) * 2.0 ** -23 * want + 1e-30)
+    lab = rng.permutation(g.V).astype(np.int32)
+    pl = torch.full((seg.Q,), -7, dtype=torch.int32, device="cuda")
+    cagra.segment_gather(seg, cagra.MIN_I32, cagra.I32, torch.from_numpy(lab).cuda(), pl)
+    want_l = oracle.segment_gather(ref, lab.astype(np.float64), oracle.MIN)
+    assert np.array_equal(_host(pl), want_l.astype(np.int32))
 
 
 def _rows_len(ref):
