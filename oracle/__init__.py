@@ -13,6 +13,7 @@ What each function follows:
   segment_gather      Section 3.2 parallel segment processing (per-row buffer values)
   merge               Section 3.3 cache-aware merge
   segmented_pagerank_step  the three above composed with the PageRank update of Section 4
+  cluster.cluster     Section 5 frequency-based clustering and relabelling (numpy, oracle/cluster.py)
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
