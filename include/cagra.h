@@ -104,6 +104,13 @@ typedef struct {
  *                        starts at or after each wave's share of the tile
  *   row_dst_lo[Q]        row_dst mod B as uint16: the destination's offset in
  *                        its merge block (what the fused merges read)
+ *   block_items[nb+1]    merge work items of the fused PageRank merge: block b
+ *                        is merged by items [block_items[b], block_items[b+1]),
+ *                        which split its entries (flattened over subgraphs)
+ *                        into equal parts. A block is split when it holds more
+ *                        than four times the mean number of entries per block
+ *                        (destinations of very high in-degree, e.g. after
+ *                        clustering); at most max_items items in all
  *
  * edge_src must be 16-byte aligned and hold E * cagra_edge_word_bytes(N)
  * bytes. All arrays are caller-allocated device memory of the sizes the query
@@ -118,6 +125,7 @@ typedef struct {
     int32_t V, k, nb, ntiles;
     int64_t E, Q;
     size_t build_workspace_bytes;
+    int32_t max_items;    /* bound on block_items[nb] */
     /* device arrays */
     int32_t *seg_row_begin;
     int32_t *row_ptr;
@@ -128,6 +136,7 @@ typedef struct {
     int32_t *tile_seg;
     int32_t *tile_span_row;
     uint16_t *row_dst_lo;
+    int32_t *block_items;
 } cagra_segments;
 
 int cagra_abi_version(void);
@@ -140,6 +149,32 @@ int32_t cagra_max_merge_block(void);
 /* Bytes per edge word of a segmentation with segment size N: 2 when
    N <= CAGRA_EDGE16_MAX_N, else 4 (0 for N < 1). */
 int32_t cagra_edge_word_bytes(int32_t N);
+
+/*
+ * Frequency-based clustering (Section 5), applied to the whole graph before
+ * segmenting. Vertices whose out-degree is strictly above the average degree
+ * E / V are moved to the front, ordered by out-degree from high to low; the
+ * order is stable (equal out-degrees keep their original order), and every
+ * other vertex follows in its original order. The graph is relabelled: old
+ * vertex perm[i] becomes vertex i, and each in-edge row lists its sources
+ * ascending under the new ids. PageRank on the result, read through perm,
+ * equals PageRank on the input.
+ *
+ *   g           input graph (device arrays; out_degree required)
+ *   perm        device int32[V], written: old id of each new vertex
+ *   in_offsets  device int32[V+1], written: new row offsets
+ *   in_sources  device int32[E], written: new sources (may be NULL when E = 0)
+ *   out_degree  device int32[V], written: new out-degrees
+ *   hot         device int32[1] or NULL, written: number of clustered vertices
+ *   workspace   device memory of cagra_cluster_workspace_bytes(V, E) bytes
+ *               (about 16 bytes per edge; the caller owns it)
+ * Outputs must not alias the inputs. Errors: CAGRA_E_INVALID / _OVERFLOW for
+ * bad arguments, CAGRA_E_BUFFER for a missing or small workspace, nothing
+ * launched in those cases. Asynchronous on `stream`.
+ */
+size_t cagra_cluster_workspace_bytes(int32_t V, int64_t E);
+int cagra_cluster(const cagra_graph *g, int32_t *perm, int32_t *in_offsets, int32_t *in_sources,
+                  int32_t *out_degree, int32_t *hot, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
@@ -157,7 +192,9 @@ size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 cagra_status cagra_build_segments(const cagra_graph *g, cagra_segments *seg, void *workspace,
                                   size_t workspace_bytes, hipStream_t stream);
 
-/* Device workspace needed by the per-iteration calls below (FP64 partial sums). */
+/* Device workspace of the per-iteration calls below: per-block FP64 partial
+   sums, then one int64 slot of B values for each work item of a split merge
+   block (2 * (max_items - nb) slots). It carries no state between calls. */
 size_t cagra_iter_workspace_bytes(const cagra_segments *seg);
 
 /*
@@ -184,6 +221,8 @@ cagra_status cagra_merge(const cagra_segments *seg, int32_t op, const void *part
  * out-degree is 0) stored as contrib_type (CAGRA_F32 or CAGRA_BF16, round to
  * nearest even); scalars_out[0] = dangling mass sum_{out_degree=0} rank (FP64),
  * scalars_out[1] = 0, scalars_out[2] = sum of rank (FP64), scalars_out[3] = 0.
+ * The workspace needs 32*ceil(V/16384) + 256 bytes (the iteration workspace
+ * of any segmentation of the graph is large enough).
  */
 cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
                                  double *scalars_out, void *workspace, size_t workspace_bytes,

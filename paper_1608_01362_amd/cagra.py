@@ -36,15 +36,15 @@ class CGraph(ctypes.Structure):
 class CSegments(ctypes.Structure):
     _fields_ = [("N", _c_i32), ("B", _c_i32), ("tile_edges", _c_i32),
                 ("V", _c_i32), ("k", _c_i32), ("nb", _c_i32), ("ntiles", _c_i32),
-                ("E", _c_i64), ("Q", _c_i64), ("build_workspace_bytes", _c_size),
+                ("E", _c_i64), ("Q", _c_i64), ("build_workspace_bytes", _c_size), ("max_items", _c_i32),
                 ("seg_row_begin", _c_vp), ("row_ptr", _c_vp), ("row_dst", _c_vp), ("edge_src", _c_vp),
                 ("block_ptr", _c_vp), ("tile_edge", _c_vp), ("tile_seg", _c_vp), ("tile_span_row", _c_vp),
-                ("row_dst_lo", _c_vp)]
+                ("row_dst_lo", _c_vp), ("block_items", _c_vp)]
 
 
 EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
-    "cagra_edge_word_bytes", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
+    "cagra_edge_word_bytes", "cagra_cluster_workspace_bytes", "cagra_cluster", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
@@ -84,6 +84,8 @@ def lib():
             "cagra_last_error": ([], ctypes.c_char_p),
             "cagra_max_merge_block": ([], _c_i32),
             "cagra_edge_word_bytes": ([_c_i32], _c_i32),
+            "cagra_cluster_workspace_bytes": ([_c_i32, _c_i64], _c_size),
+            "cagra_cluster": ([GP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_query_workspace_bytes": ([_c_i32, _c_i64, _c_i32], _c_size),
             "cagra_build_segments": ([GP, SP, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_iter_workspace_bytes": ([SP], _c_size),
@@ -168,6 +170,32 @@ class DeviceGraph:
         return dg
 
 
+def cluster(dg: "DeviceGraph", stream=None):
+    """Section 5 frequency-based clustering on the GPU. Returns (clustered
+    DeviceGraph, perm, H): perm[i] (device int32) is the old id of new vertex i,
+    H the number of clustered vertices."""
+    import torch
+    dev = _dev()
+    L = lib()
+    V, E = dg.V, dg.E
+    wb = L.cagra_cluster_workspace_bytes(V, E)
+    if wb == 0:
+        _check(E_INVALID, "cagra_cluster_workspace_bytes")
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    perm = torch.empty(V, dtype=torch.int32, device=dev)
+    off = torch.empty(V + 1, dtype=torch.int32, device=dev)
+    src = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    od = torch.empty(V, dtype=torch.int32, device=dev)
+    hot = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(L.cagra_cluster(ctypes.byref(dg.c), _ptr(perm), _ptr(off), _ptr(src), _ptr(od), _ptr(hot), _ptr(ws), wb,
+                           _stream(stream)), "cagra_cluster")
+    H = int(hot.item())  # synchronizes the stream
+    del ws
+    out = DeviceGraph(V, E, off, src, od)
+    out.c = CGraph(V, E, off.data_ptr(), src.data_ptr(), od.data_ptr())
+    return out, perm, H
+
+
 @dataclass
 class Segments:
     c: CSegments
@@ -224,6 +252,7 @@ def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = Non
         "tile_seg": torch.empty(max(nt, 1), dtype=i32, device=dev),
         "tile_span_row": torch.empty(max(nt, 1) * TILE_WAVES, dtype=i32, device=dev),
         "row_dst_lo": torch.empty(max(Q, 1), dtype=torch.int16, device=dev),
+        "block_items": torch.empty(nb + 1, dtype=i32, device=dev),
     }
     for name, t in arrays.items():
         setattr(c, name, t.data_ptr())

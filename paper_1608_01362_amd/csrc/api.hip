@@ -24,6 +24,9 @@ size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
 cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
 bool gather_staged(int32_t N, int32_t value_type);
+cagra_status cluster_workspace_bytes(int32_t V, int64_t E, size_t *bytes);
+cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offsets_new, int32_t *in_sources_new,
+                           int32_t *outdeg_new, int32_t *hot, void *ws, size_t ws_bytes, hipStream_t st);
 cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
                            void *partial, hipStream_t st);
 size_t merge_ordered_lds_bytes(int32_t B, int32_t op);
@@ -31,12 +34,14 @@ size_t merge_fused_lds_total(int32_t B, int32_t k, int acc_bytes);
 cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st);
 int32_t init_blocks(int32_t V);
 cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
-                            double *scalars_out, double *blk, hipStream_t st);
+                            double *scalars_out, void *ws, hipStream_t st);
+size_t ws_blk_bytes(int32_t V, int32_t nb);
+size_t ws_slot_bytes(const cagra_segments *seg);
 cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
                              const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
-                             void *contrib_out, double *scalars_out, double *blk, hipStream_t st);
+                             void *contrib_out, double *scalars_out, void *ws, hipStream_t st);
 cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
-                             int32_t *labels_out, int32_t *changed_out, int32_t *blk, hipStream_t st);
+                             int32_t *labels_out, int32_t *changed_out, void *ws, hipStream_t st);
 
 int32_t ppr_init_blocks(int32_t V);
 size_t ppr_merge_lds_bytes(int32_t B);
@@ -90,18 +95,18 @@ static cagra_status check_params(const cagra_segments *seg, int32_t V) {
 static cagra_status check_built(const cagra_segments *seg) {
     if (!seg) return fail(CAGRA_E_INVALID, "segments is NULL");
     if (seg->V < 1 || seg->N < 1 || seg->B < 1 || seg->k != (int32_t)ceil_div(seg->V, seg->N) ||
-        seg->nb != (int32_t)ceil_div(seg->V, seg->B) || seg->Q < 0 || seg->Q > seg->E || seg->ntiles < 0)
+        seg->nb != (int32_t)ceil_div(seg->V, seg->B) || seg->Q < 0 || seg->Q > seg->E || seg->ntiles < 0 ||
+        seg->max_items < seg->nb)
         return fail(CAGRA_E_INVALID, "segments sizes are inconsistent (not built?)");
     if (!seg->seg_row_begin || !seg->row_ptr || !seg->row_dst || !seg->edge_src || !seg->block_ptr ||
-        !seg->tile_edge || !seg->tile_seg || !seg->tile_span_row || !seg->row_dst_lo)
+        !seg->tile_edge || !seg->tile_seg || !seg->tile_span_row || !seg->row_dst_lo || !seg->block_items)
         return fail(CAGRA_E_INVALID, "a segments array is NULL");
     if (((uintptr_t)seg->edge_src & 15) != 0) return fail(CAGRA_E_INVALID, "edge_src must be 16-byte aligned");
     return CAGRA_OK;
 }
 
-static size_t iter_ws_bytes(int32_t V, int32_t nb) {
-    int64_t n = nb > init_blocks(V) ? nb : init_blocks(V);
-    return (size_t)n * 4 * sizeof(double) + 256;
+static size_t iter_ws_bytes(const cagra_segments *seg) {
+    return ws_blk_bytes(seg->V, seg->nb) + ws_slot_bytes(seg) + 256;
 }
 
 }  // namespace cagra
@@ -127,6 +132,26 @@ const char *cagra_status_string(int status) {
 const char *cagra_last_error(void) { return g_last_error; }
 
 int32_t cagra_max_merge_block(void) { return kMaxMergeBlock; }
+
+size_t cagra_cluster_workspace_bytes(int32_t V, int64_t E) {
+    if (V < 1 || E < 0 || E > (int64_t)INT32_MAX - 1) return 0;
+    size_t b = 0;
+    return cluster_workspace_bytes(V, E, &b) == CAGRA_OK ? b : 0;
+}
+
+int cagra_cluster(const cagra_graph *g, int32_t *perm, int32_t *in_offsets, int32_t *in_sources, int32_t *out_degree,
+                  int32_t *hot, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if (!perm || !in_offsets || !out_degree || (g->E > 0 && !in_sources))
+        return fail(CAGRA_E_INVALID, "a clustering output array is NULL");
+    if ((const void *)in_offsets == (const void *)g->in_offsets ||
+        (in_sources && (const void *)in_sources == (const void *)g->in_sources) ||
+        (const void *)out_degree == (const void *)g->out_degree)
+        return fail(CAGRA_E_INVALID, "clustering outputs must not alias the input graph");
+    if (!workspace || workspace_bytes == 0) return fail(CAGRA_E_BUFFER, "clustering workspace is NULL");
+    return cluster_graph(g, perm, in_offsets, in_sources, out_degree, hot, workspace, workspace_bytes, stream);
+}
 
 int32_t cagra_edge_word_bytes(int32_t N) { return N < 1 ? 0 : (edge16(N) ? 2 : 4); }
 
@@ -156,8 +181,8 @@ cagra_status cagra_build_segments(const cagra_graph *g, cagra_segments *seg, voi
 }
 
 size_t cagra_iter_workspace_bytes(const cagra_segments *seg) {
-    if (!seg || seg->V < 1) return 0;
-    return iter_ws_bytes(seg->V, seg->nb);
+    if (!seg || seg->V < 1 || seg->nb < 1 || seg->max_items < seg->nb) return 0;
+    return iter_ws_bytes(seg);
 }
 
 cagra_status cagra_segment_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
@@ -192,7 +217,7 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
     size_t need = (size_t)init_blocks(g->V) * 4 * sizeof(double) + 256;
     if (!workspace || workspace_bytes < need)
         return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", need, workspace_bytes);
-    return launch_pr_init(g, contrib_type, rank, contrib_out, scalars_out, (double *)workspace, stream);
+    return launch_pr_init(g, contrib_type, rank, contrib_out, scalars_out, workspace, stream);
 }
 
 static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *seg, double damping,
@@ -206,8 +231,8 @@ static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *s
         return fail(CAGRA_E_INVALID, "contrib_type must be CAGRA_F32 or CAGRA_BF16");
     if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
-    if (!workspace || workspace_bytes < iter_ws_bytes(seg->V, seg->nb))
-        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg->V, seg->nb),
+    if (!workspace || workspace_bytes < iter_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg),
                     workspace_bytes);
     return CAGRA_OK;
 }
@@ -221,7 +246,7 @@ cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *se
     if (!rank_in || !scalars_in || !rank_out || !contrib_out || !scalars_out || (seg->Q > 0 && !partial))
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
-                           scalars_out, (double *)workspace, stream);
+                           scalars_out, workspace, stream);
 }
 
 cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
@@ -235,7 +260,7 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
-                           scalars_out, (double *)workspace, stream);
+                           scalars_out, workspace, stream);
 }
 
 cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,
@@ -247,11 +272,11 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if (merge_fused_lds_total(seg->B, seg->k, 4) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
-    if (!workspace || workspace_bytes < iter_ws_bytes(seg->V, seg->nb))
-        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg->V, seg->nb),
+    if (!workspace || workspace_bytes < iter_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg),
                     workspace_bytes);
     if ((s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, labels_in, partial, stream)) != CAGRA_OK) return s;
-    return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, (int32_t *)workspace, stream);
+    return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, workspace, stream);
 }
 
 size_t cagra_features_workspace_bytes(const cagra_segments *seg) {

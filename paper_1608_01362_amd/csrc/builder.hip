@@ -306,6 +306,25 @@ __global__ void k_edges(const int32_t *__restrict__ src, const int32_t *__restri
     edge_src[row_ptr[pos[r]] + off] = (W)(off == 0 ? (local | EdgeWord<W>::kFlag) : local);
 }
 
+// Merge work items (see block_items in cagra.h): a block whose entries exceed
+// four times the mean per block is cut into ceil(P_b / T) equal parts.
+static int64_t merge_split_entries(int64_t Q, int32_t nb) {
+    const int64_t mean = nb > 0 ? ceil_div(Q, nb) : 1;
+    return mean > 0 ? 4 * mean : 4;
+}
+
+__global__ __launch_bounds__(64) void k_block_items(const int32_t *__restrict__ block_ptr, int32_t k, int32_t nb,
+                                                    int64_t T, int32_t *__restrict__ items) {
+    const int64_t b = blockIdx.x;
+    int64_t P = 0;
+    for (int32_t s = threadIdx.x; s < k; s += 64) P += block_ptr[(b + 1) * k + s] - block_ptr[b * k + s];
+    for (int d = 32; d >= 1; d >>= 1) P += __shfl_down(P, d, 64);
+    if (threadIdx.x == 0) {
+        items[b] = P > T ? (int32_t)ceil_div(P, T) : 1;
+        if (b == nb - 1) items[nb] = 0;
+    }
+}
+
 // First index in [lo, hi) with a[i] >= x (hi if none).
 __device__ __forceinline__ int32_t lower_bound_i32(const int32_t *a, int32_t lo, int32_t hi, int64_t x) {
     while (lo < hi) {
@@ -402,7 +421,7 @@ size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
 }
 
 // Layout of the build workspace (mirrors build_segments below).
-static size_t build_workspace_size(int64_t E, int64_t Q, int32_t k) {
+static size_t build_workspace_size(int64_t E, int64_t Q, int32_t k, int32_t nb) {
     int32_t C = sort_chunk(k);
     int64_t nchunks = ceil_div(Q, C);
     ArenaSize a;
@@ -417,6 +436,7 @@ static size_t build_workspace_size(int64_t E, int64_t Q, int32_t k) {
     int64_t mx = E;
     if (k * nchunks > mx) mx = k * nchunks;
     if (Q + 1 > mx) mx = Q + 1;
+    if ((int64_t)nb + 1 > mx) mx = (int64_t)nb + 1;
     return a.used + scan_ws_bytes(mx) + 256;
 }
 
@@ -466,7 +486,10 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     seg->nb = (int32_t)ceil_div(V, seg->B);
     seg->Q = Q;
     seg->ntiles = (int32_t)ntiles;
-    seg->build_workspace_bytes = build_workspace_size(E, Q, k);
+    const int64_t items = (int64_t)seg->nb + ceil_div(Q, merge_split_entries(Q, seg->nb)) + 1;
+    if (items > INT32_MAX) return fail(CAGRA_E_OVERFLOW, "too many merge work items");
+    seg->max_items = (int32_t)items;
+    seg->build_workspace_bytes = build_workspace_size(E, Q, k, seg->nb);
     return CAGRA_OK;
 }
 
@@ -479,6 +502,14 @@ static cagra_status allow_big_lds_impl() {
         done = true;
     }
     return CAGRA_OK;
+}
+
+// 5. merge work items per block (needs block_ptr)
+static cagra_status build_block_items(cagra_segments *seg, Arena &ar, hipStream_t st) {
+    k_block_items<<<(unsigned)seg->nb, 64, 0, st>>>(seg->block_ptr, seg->k, seg->nb,
+                                                     merge_split_entries(seg->Q, seg->nb), seg->block_items);
+    CAGRA_LAUNCH_CHECK();
+    return scan_i32<ScanAdd>(seg->block_items, seg->block_items, (int64_t)seg->nb + 1, false, ar, st);
 }
 
 cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st) {
@@ -509,7 +540,7 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
         CAGRA_LAUNCH_CHECK();
         k_fill_i32<<<1, 64, 0, st>>>(seg->tile_edge, 1, 0);
         CAGRA_LAUNCH_CHECK();
-        return CAGRA_OK;
+        return build_block_items(seg, ar, st);
     }
     // 1. run starts, destinations, run ids
     k_fill_i32<<<grid_for(E, 256), 256, 0, st>>>(mark, E, 0);
@@ -558,7 +589,7 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
             seg->row_ptr, seg->seg_row_begin, seg->tile_edge, seg->tile_seg, ntiles, seg->tile_span_row);
         CAGRA_LAUNCH_CHECK();
     }
-    return CAGRA_OK;
+    return build_block_items(seg, ar, st);
 }
 
 }  // namespace cagra

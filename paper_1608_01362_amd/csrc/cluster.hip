@@ -1,0 +1,188 @@
+// Frequency-based clustering (Section 5) and relabelling, before segmenting.
+//
+// 1. Vertex keys: out-degree where it is strictly above the average degree
+//    E / V, else 0. A stable radix sort of (key, id) pairs in descending key
+//    order gives the new order: clustered vertices by out-degree from high to
+//    low (ties keep the original order), then every other vertex in its
+//    original order.
+// 2. inv[perm[i]] = i; new out-degrees and in-degrees follow perm; a scan of
+//    the in-degrees gives the new row offsets.
+// 3. Every edge u -> v becomes the key (inv[v] << b) | inv[u] (b bits per id);
+//    one radix sort of these keys lays the edges out row by row with sources
+//    ascending, and the low bits are the new source ids.
+//
+// The sorts and the scan are rocPRIM's device primitives; clustering runs once
+// per graph, off the iteration's hot path.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "common.h"
+
+namespace cagra {
+
+constexpr int kEdgesPerThread = 16;
+
+__global__ void k_cl_vertex_keys(const int32_t *__restrict__ outdeg, int32_t V, int64_t E,
+                                 uint32_t *__restrict__ key, int32_t *__restrict__ id) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const int64_t od = outdeg[v];
+    key[v] = od * (int64_t)V > E ? (uint32_t)od : 0u;
+    id[v] = (int32_t)v;
+}
+
+// inv, the new out-degrees and in-degrees, and the clustered-vertex count.
+__global__ void k_cl_relabel(const int32_t *__restrict__ perm, const uint32_t *__restrict__ key_sorted,
+                             const int32_t *__restrict__ in_offsets, const int32_t *__restrict__ outdeg, int32_t V,
+                             int32_t *__restrict__ inv, int32_t *__restrict__ outdeg_new, int32_t *__restrict__ cnt,
+                             int32_t *__restrict__ hot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > V) return;
+    if (i == V) {
+        cnt[V] = 0;
+        return;
+    }
+    const int32_t old = perm[i];
+    inv[old] = (int32_t)i;
+    outdeg_new[i] = outdeg[old];
+    cnt[i] = in_offsets[old + 1] - in_offsets[old];
+    if (hot) {
+        // exactly one writer: the last clustered vertex, or vertex 0 when there is none
+        const bool last_hot = key_sorted[i] > 0 && (i + 1 == V || key_sorted[i + 1] == 0);
+        if (last_hot) *hot = (int32_t)(i + 1);
+        if (i == 0 && key_sorted[0] == 0) *hot = 0;
+    }
+}
+
+// Last row r with in_offsets[r] <= e (the non-empty row holding edge e).
+__device__ __forceinline__ int32_t row_of_edge(const int32_t *__restrict__ off, int32_t V, int64_t e) {
+    int32_t lo = 0, hi = V;  // off[lo] <= e < off[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Edge keys (new destination, new source); each thread takes kEdgesPerThread
+// consecutive edges, finds the first one's row by binary search and walks on.
+__global__ void k_cl_edge_keys(const int32_t *__restrict__ in_offsets, const int32_t *__restrict__ in_sources,
+                               int32_t V, int64_t E, const int32_t *__restrict__ inv, int bits,
+                               unsigned long long *__restrict__ keys) {
+    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kEdgesPerThread;
+    if (e0 >= E) return;
+    const int64_t e1 = e0 + kEdgesPerThread < E ? e0 + kEdgesPerThread : E;
+    int32_t r = row_of_edge(in_offsets, V, e0);
+    for (int64_t e = e0; e < e1; ++e) {
+        while ((int64_t)in_offsets[r + 1] <= e) ++r;
+        keys[e] = ((unsigned long long)(uint32_t)inv[r] << bits) | (unsigned long long)(uint32_t)inv[in_sources[e]];
+    }
+}
+
+__global__ void k_cl_sources(const unsigned long long *__restrict__ keys, int64_t E, unsigned long long mask,
+                             int32_t *__restrict__ in_sources_new) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) in_sources_new[e] = (int32_t)(keys[e] & mask);
+}
+
+static int id_bits(int32_t V) {
+    int b = 1;
+    while (b < 31 && (1LL << b) < (int64_t)V) ++b;
+    return b;
+}
+
+static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// rocPRIM temporary-storage sizes (no launches with a null storage pointer).
+struct ClusterTemps {
+    size_t vsort = 0, scan = 0, esort = 0;
+};
+
+static cagra_status cluster_temps(int32_t V, int64_t E, ClusterTemps &t) {
+    const int bits = id_bits(V);
+    hipError_t e = rocprim::radix_sort_pairs_desc(nullptr, t.vsort, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                  (int32_t *)nullptr, (int32_t *)nullptr, (size_t)V, 0, 32);
+    if (e != hipSuccess) return fail(CAGRA_E_HIP, "vertex sort size query failed: %s", hipGetErrorString(e));
+    e = rocprim::exclusive_scan(nullptr, t.scan, (int32_t *)nullptr, (int32_t *)nullptr, 0, (size_t)V + 1,
+                                rocprim::plus<int32_t>());
+    if (e != hipSuccess) return fail(CAGRA_E_HIP, "scan size query failed: %s", hipGetErrorString(e));
+    if (E > 0) {
+        e = rocprim::radix_sort_keys(nullptr, t.esort, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                     (size_t)E, 0, 2 * bits);
+        if (e != hipSuccess) return fail(CAGRA_E_HIP, "edge sort size query failed: %s", hipGetErrorString(e));
+    }
+    return CAGRA_OK;
+}
+
+static size_t cluster_layout(int32_t V, int64_t E, const ClusterTemps &t) {
+    ArenaSize a;
+    a.take<uint32_t>(V);                 // key
+    a.take<uint32_t>(V);                 // key_sorted
+    a.take<int32_t>(V);                  // id
+    a.take<int32_t>(V);                  // inv
+    a.take<int32_t>((int64_t)V + 1);     // cnt
+    a.take<unsigned long long>(E);       // edge keys
+    a.take<unsigned long long>(E);       // sorted edge keys
+    size_t tmp = t.vsort > t.scan ? t.vsort : t.scan;
+    if (t.esort > tmp) tmp = t.esort;
+    a.take<char>((int64_t)tmp);
+    return a.used + 256;
+}
+
+cagra_status cluster_workspace_bytes(int32_t V, int64_t E, size_t *bytes) {
+    ClusterTemps t;
+    if (cagra_status s = cluster_temps(V, E, t)) return s;
+    *bytes = cluster_layout(V, E, t);
+    return CAGRA_OK;
+}
+
+cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offsets_new, int32_t *in_sources_new,
+                           int32_t *outdeg_new, int32_t *hot, void *ws, size_t ws_bytes, hipStream_t st) {
+    const int32_t V = g->V;
+    const int64_t E = g->E;
+    ClusterTemps t;
+    if (cagra_status s = cluster_temps(V, E, t)) return s;
+    const size_t need = cluster_layout(V, E, t);
+    if (ws_bytes < need) return fail(CAGRA_E_BUFFER, "cluster workspace needs %zu bytes (got %zu)", need, ws_bytes);
+    Arena ar{(char *)ws, ws_bytes, 0};
+    uint32_t *key = ar.take<uint32_t>(V);
+    uint32_t *key_sorted = ar.take<uint32_t>(V);
+    int32_t *id = ar.take<int32_t>(V);
+    int32_t *inv = ar.take<int32_t>(V);
+    int32_t *cnt = ar.take<int32_t>((int64_t)V + 1);
+    unsigned long long *ekeys = ar.take<unsigned long long>(E);
+    unsigned long long *ekeys_sorted = ar.take<unsigned long long>(E);
+    size_t tmp_bytes = t.vsort > t.scan ? t.vsort : t.scan;
+    if (t.esort > tmp_bytes) tmp_bytes = t.esort;
+    char *tmp = ar.take<char>((int64_t)tmp_bytes);
+    if (!key || !key_sorted || !id || !inv || !cnt || !ekeys || !ekeys_sorted || !tmp)
+        return fail(CAGRA_E_BUFFER, "cluster workspace smaller than %zu bytes", need);
+
+    // 1. new vertex order
+    k_cl_vertex_keys<<<grid_of(V, 256), 256, 0, st>>>(g->out_degree, V, E, key, id);
+    CAGRA_LAUNCH_CHECK();
+    size_t b = t.vsort;
+    CAGRA_HIP_CHECK(rocprim::radix_sort_pairs_desc(tmp, b, key, key_sorted, id, perm, (size_t)V, 0, 32, st));
+    // 2. relabel vertices, new row offsets
+    k_cl_relabel<<<grid_of((int64_t)V + 1, 256), 256, 0, st>>>(perm, key_sorted, g->in_offsets, g->out_degree, V,
+                                                                inv, outdeg_new, cnt, hot);
+    CAGRA_LAUNCH_CHECK();
+    b = t.scan;
+    CAGRA_HIP_CHECK(rocprim::exclusive_scan(tmp, b, cnt, in_offsets_new, 0, (size_t)V + 1,
+                                            rocprim::plus<int32_t>(), st));
+    if (E == 0) return CAGRA_OK;
+    // 3. relabel edges: one sort by (new destination, new source)
+    const int bits = id_bits(V);
+    k_cl_edge_keys<<<grid_of(ceil_div(E, kEdgesPerThread), 256), 256, 0, st>>>(g->in_offsets, g->in_sources, V, E,
+                                                                               inv, bits, ekeys);
+    CAGRA_LAUNCH_CHECK();
+    b = t.esort;
+    CAGRA_HIP_CHECK(rocprim::radix_sort_keys(tmp, b, ekeys, ekeys_sorted, (size_t)E, 0, 2 * bits, st));
+    k_cl_sources<<<grid_of(E, 256), 256, 0, st>>>(ekeys_sorted, E, (1ull << bits) - 1ull, in_sources_new);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+}  // namespace cagra

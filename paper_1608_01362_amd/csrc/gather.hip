@@ -159,22 +159,24 @@ struct SpanState {
     int32_t nflags; // row starts seen in earlier chunks
 };
 
-// Processes one chunk of kChunk edges (this lane: kEPT consecutive edges).
-// Rows finished in the chunk are exactly chunk_nf consecutive rows starting
-// at row0 + nflags - 1; they are collected in `stage` and written with
-// coalesced stores.
 // 16-byte loads per lane per chunk for edge words of type W.
 template <typename W>
 constexpr int kLoads = kEPT * (int)sizeof(W) / 16;
 
-template <class Op, typename VT, bool STAGED, typename W>
-__device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int64_t cidx, int64_t w0, int64_t w1,
+// Processes one chunk of kChunk edges (this lane: kEPT consecutive edges).
+// rel0 is the chunk's first edge relative to the wave's share [0, len) (it is
+// negative for a first chunk that starts before the share); FULL chunks lie
+// entirely inside the share and skip the per-edge bounds tests. Rows finished
+// in the chunk are exactly chunk_nf consecutive rows starting at row0 + nflags
+// - 1; they are collected in `stage` and written with coalesced stores.
+template <class Op, typename VT, bool STAGED, typename W, bool FULL>
+__device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int32_t rel0, int32_t len,
                                               const VT *seg_vals, const VT *gvals, typename Op::T *stage,
                                               __amdgpu_buffer_rsrc_t out, SpanState<typename Op::T> &S) {
     using T = typename Op::T;
     using F = Fetch<VT, STAGED>;
     const int lane = __lane_id();
-    const int64_t idx = cidx + lane * kEPT;
+    const int32_t rel = rel0 + lane * kEPT;
     uint32_t w[kEPT];
     if constexpr (sizeof(W) == 4) {
 #pragma unroll
@@ -192,11 +194,16 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int64_
     T v[kEPT];
 #pragma unroll
     for (int i = 0; i < kEPT; ++i) {
-        const bool valid = (idx + i >= w0) && (idx + i < w1);
-        fmask |= (valid && (w[i] & EdgeWord<W>::kFlag)) ? (1u << i) : 0u;
-        // words outside the share may belong to another segment: read index 0 instead
-        const T x = F::get(seg_vals, gvals, valid ? (int32_t)(w[i] & EdgeWord<W>::kIndex) : 0);
-        v[i] = valid ? x : Op::identity();
+        if constexpr (FULL) {
+            fmask |= (w[i] & EdgeWord<W>::kFlag) ? (1u << i) : 0u;
+            v[i] = F::get(seg_vals, gvals, (int32_t)(w[i] & EdgeWord<W>::kIndex));
+        } else {
+            const bool valid = (uint32_t)(rel + i) < (uint32_t)len;
+            fmask |= (valid && (w[i] & EdgeWord<W>::kFlag)) ? (1u << i) : 0u;
+            // words outside the share may belong to another segment: read index 0 instead
+            const T x = F::get(seg_vals, gvals, valid ? (int32_t)(w[i] & EdgeWord<W>::kIndex) : 0);
+            v[i] = valid ? x : Op::identity();
+        }
     }
     const int32_t nf = __popc(fmask);
     const int32_t incl_nf = wave_incl_sum(nf);
@@ -230,6 +237,7 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int64_
     const int32_t rbase = S.nflags - 1;  // staged index 0 <-> row row0 + rbase
 #pragma unroll
     for (int r = 0; r < kEPT; ++r) {
+        if (r * kWave >= chunk_nf) break;  // uniform: chunk_nf is wave-wide
         const int32_t i = r * kWave + lane;
         const T val = stage[i];
         const bool ok = i < chunk_nf && !(head_here && i == 0);
@@ -244,8 +252,6 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int64_
     S.nflags += chunk_nf;
 }
 
-// One gather tile (all 16 waves of the workgroup). `smem` is the workgroup's
-// dynamic LDS: kStageBytes of per-wave row staging, then the segment values.
 template <typename W>
 __device__ __forceinline__ void load_chunk(v4i (&r)[kLoads<W>], __amdgpu_buffer_rsrc_t ein, uint32_t off) {
 #pragma unroll
@@ -301,6 +307,7 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
     SpanState<T> S{Op::identity(), Op::identity(), 0};
     T *stage = reinterpret_cast<T *>(smem) + (size_t)w * kStageRows;
     const int64_t len = w1 - ebase;
+    const int32_t share = (int32_t)(w1 - w0);
     const uint32_t lane_off = (uint32_t)(lane * kEPT * kWB);
     v4i R[kStages][kLoads<W>];
 #pragma unroll
@@ -311,7 +318,11 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
             if (cc + c * kChunk >= len) break;  // uniform: len and cc are wave-wide
             load_chunk<W>(R[(c + kStages - 1) % kStages], ein,
                           (uint32_t)((cc + (c + kStages - 1) * kChunk) * kWB) + lane_off);
-            process_chunk<Op, VT, STAGED, W>(R[c], ebase + cc + c * kChunk, w0, w1, seg_vals, gvals, stage, out, S);
+            const int32_t rel0 = (int32_t)(ebase + cc + c * kChunk - w0);
+            if (rel0 >= 0 && rel0 + kChunk <= share)
+                process_chunk<Op, VT, STAGED, W, true>(R[c], rel0, share, seg_vals, gvals, stage, out, S);
+            else
+                process_chunk<Op, VT, STAGED, W, false>(R[c], rel0, share, seg_vals, gvals, stage, out, S);
         }
     }
 

@@ -195,7 +195,7 @@ constexpr int kUnroll = 8;
 
 // Streams block b's buffer entries (the ranges of all subgraphs, flattened).
 // Each wave takes a contiguous share; per pass a lane handles kUnroll entries
-// 64 apart, finding its subgraph by walking forward from the pass's first one.
+// 64 apart, finding its subgraph by walking forward from the previous one.
 // All loads are issued unconditionally (clamped index) so that many are in
 // flight; apply(d, x) updates the LDS accumulator of block offset d. The loads
 // keep the default cache policy: the cache line at each end of a (subgraph,
@@ -203,11 +203,11 @@ constexpr int kUnroll = 8;
 // same time on the same XCD and finds the line in L2.
 template <typename PT, class Apply>
 __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, const PT *__restrict__ partial,
-                                             const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t P,
-                                             Apply apply) {
+                                             const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t F0,
+                                             int32_t F1, Apply apply) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int32_t share = (((P + 15) / 16) + 63) & ~63;
-    const int32_t fa = min(w * share, P), fb = min(fa + share, P);
+    const int32_t share = ((((F1 - F0) + 15) / 16) + 63) & ~63;
+    const int32_t fa = min(F0 + w * share, F1), fb = min(fa + share, F1);
     for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
         int32_t sl = run_of(pre, k, f0);
         int32_t d[kUnroll];
@@ -229,29 +229,14 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
     }
 }
 
-// Merge block b of one graph plus the PageRank vertex update; writes the
-// block's FP64 partial sums to blk_out[0..3].
+// PageRank vertex update of block b from its exact sums acc (LDS, int64 fixed
+// point); writes the block's FP64 partial sums to blk_out[0..3].
 template <bool BF16OUT>
-__device__ __forceinline__ void merge_pr_block(
-    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
-    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b,
-    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
-    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
-    unsigned char *smem) {
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
-    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
-    int32_t *pre = lo_s + k;
-    __shared__ int32_t tmp[16];
-    __shared__ double red[16];
-
-    const int64_t vb = (int64_t)b * B;
-    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
-    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, P,
-                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
-    __syncthreads();
-
+__device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32_t V, int64_t vb, int32_t nv,
+                                            const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
+                                            const double *__restrict__ scalars_in, double damping,
+                                            float *__restrict__ rank_out, void *__restrict__ contrib_out,
+                                            double *__restrict__ blk_out, double *red) {
     const double dd = damping;
     const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
     double dang = 0.0, res = 0.0, mass = 0.0;
@@ -279,16 +264,116 @@ __device__ __forceinline__ void merge_pr_block(
     }
 }
 
+// Item j of the S items of block b: the block's entries (flattened over
+// subgraphs) [P*j/S, P*(j+1)/S). With S == 1 the item is the whole block and
+// the vertex update follows at once. Otherwise the item stores its exact int64
+// sums in its own slot of the workspace, and k_merge_pr_finish adds the S
+// slots of the block (exactly, so the split does not change any result) and
+// applies the update.
+template <bool BF16OUT>
+__device__ __forceinline__ void merge_pr_block(
+    const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
+    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b, int32_t j, int32_t S,
+    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
+    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
+    unsigned long long *__restrict__ slot, unsigned char *smem) {
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
+    int32_t *pre = lo_s + k;
+    __shared__ int32_t tmp[16];
+    __shared__ double red[16];
+
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
+    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+    const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
+    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, F0, F1,
+                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
+    __syncthreads();
+    if (S > 1) {
+        for (int i = threadIdx.x; i < nv; i += kMergeThreads) slot[i] = acc[i];
+        return;
+    }
+    pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out, blk_out, red);
+}
+
+// Slot of item j of a split block b whose first item is items_b: 2*(items_b - b)
+// + j. items_b - b counts the extra items of earlier blocks; a split block has
+// S >= 2 items and adds S - 1 >= S / 2 extra ones, so the slot ranges of split
+// blocks are disjoint and all lie below 2 * (items[nb] - nb).
+__device__ __forceinline__ int64_t split_slot(int32_t items_b, int32_t b, int32_t j) {
+    return 2 * (int64_t)(items_b - b) + j;
+}
+
+// Groups of g consecutive work items share an XCD (workgroup id mod 8), and
+// the groups cycle over the XCDs: neighbouring blocks still meet in one L2,
+// while the heavy blocks at the front (high in-degree destinations after
+// clustering) spread over all XCDs. Bijective on [0, n): ids past the last
+// whole round of 8 g keep their place.
+__device__ __forceinline__ int32_t xcd_group_map(int32_t id, int32_t n, int32_t g) {
+    const int32_t round = 8 * g;
+    if (id >= n / round * round) return id;
+    const int32_t x = id & 7, q = id >> 3;
+    return (q / g) * round + x * g + (q % g);
+}
+constexpr int32_t kItemGroup = 4;  // work items per XCD group (1, 2, 4 and 16 time alike; contiguous is slower)
+
+// Block of merge work item i: last b with items[b] <= i (items ascending).
+__device__ __forceinline__ int32_t block_of_item(const int32_t *__restrict__ items, int32_t nb, int32_t i) {
+    int32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (items[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <bool BF16OUT>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
-    const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb,
-    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
-    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk) {
+    const int32_t *__restrict__ block_items, const float *__restrict__ partial, int32_t V, int32_t k, int32_t B,
+    int32_t nb, const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
+    const double *__restrict__ scalars_in, double damping, float *__restrict__ rank_out,
+    void *__restrict__ contrib_out, double *__restrict__ blk, unsigned long long *__restrict__ slots) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int b = xcd_remap(blockIdx.x, nb);
-    merge_pr_block<BF16OUT>(row_dst_lo, block_ptr, partial, V, k, B, b, rank_in, outdeg, scalars_in, damping,
-                            rank_out, contrib_out, blk + (int64_t)b * 4, smem);
+    // the grid is the bound max_items; slots past the actual item count exit,
+    // and the XCD remap spreads the actual items (not the bound) over the XCDs
+    const int32_t total = block_items[nb];
+    if ((int32_t)blockIdx.x >= total) return;  // uniform over the workgroup
+    const int32_t i = xcd_group_map(blockIdx.x, total, kItemGroup);
+    const int32_t b = block_of_item(block_items, nb, i);
+    const int32_t j = i - block_items[b], S = block_items[b + 1] - block_items[b];
+    unsigned long long *slot = S > 1 ? slots + split_slot(block_items[b], b, j) * B : nullptr;
+    merge_pr_block<BF16OUT>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in, damping,
+                            rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
+}
+
+// Vertex update of the split blocks: the sum of the block's item slots.
+template <bool BF16OUT>
+__global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
+    const int32_t *__restrict__ block_items, int32_t V, int32_t B, int32_t nb, const float *__restrict__ rank_in,
+    const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
+    float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk,
+    const unsigned long long *__restrict__ slots) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ double red[16];
+    const int32_t b = blockIdx.x;
+    const int32_t S = block_items[b + 1] - block_items[b];
+    if (S <= 1) return;  // merged in one piece
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    const unsigned long long *first = slots + split_slot(block_items[b], b, 0) * B;
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
+        unsigned long long t = 0ull;
+        for (int32_t j = 0; j < S; ++j) t += first[(int64_t)j * B + i];
+        acc[i] = t;
+    }
+    __syncthreads();
+    pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out,
+                         blk + (int64_t)b * 4, red);
 }
 
 // Order-free merge of float buffer values into float sums (int64 fixed point,
@@ -307,7 +392,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_sum_fixed24(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, P,
+    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, 0, P,
                         [&](int32_t d, float x) { atomicAdd(&acc[d], fix24(x)); });
     __syncthreads();
     for (int i = threadIdx.x; i < nv; i += kMergeThreads)
@@ -338,9 +423,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *
         __syncthreads();  // LDS reuse across blocks
         const int gi = block_graph[gb];
         const MultiDesc &d = desc[gi];
-        merge_pr_block<false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base),
+        merge_pr_block<false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base), 0, 1,
                               d.rank[parity], d.out_degree, d.scalars[parity], damping, d.rank[1 - parity],
-                              d.contrib[1 - parity], blk + gb * 4, smem);
+                              d.contrib[1 - parity], blk + gb * 4, nullptr, smem);
     }
 }
 
@@ -430,7 +515,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<int32_t>(row_dst_lo, partial, lo_s, pre, k, P,
+    stream_block<int32_t>(row_dst_lo, partial, lo_s, pre, k, 0, P,
                           [&](int32_t d, int32_t x) { atomicMin(&acc[d], x); });
     __syncthreads();
     int32_t changed = 0;
@@ -505,9 +590,20 @@ __global__ __launch_bounds__(256) void k_reduce_i32(const int32_t *__restrict__ 
 
 int32_t init_blocks(int32_t V) { return (int32_t)ceil_div(V, kInitSpan); }
 
+// Iteration workspace: the FP64 (or int32) per-block partial sums at offset 0,
+// then the int64 slots of the work items of split merge blocks.
+size_t ws_blk_bytes(int32_t V, int32_t nb) {
+    const int64_t n = nb > init_blocks(V) ? nb : init_blocks(V);
+    return align_up((size_t)n * 4 * sizeof(double), 256);
+}
+size_t ws_slot_bytes(const cagra_segments *seg) {
+    return (size_t)2 * (size_t)(seg->max_items - seg->nb) * (size_t)seg->B * sizeof(unsigned long long);
+}
+
 cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
-                            double *scalars_out, double *blk, hipStream_t st) {
+                            double *scalars_out, void *ws, hipStream_t st) {
     const int32_t nblk = init_blocks(g->V);
+    double *blk = reinterpret_cast<double *>(ws);
     if (contrib_type == CAGRA_BF16) k_pr_init<true><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
     else k_pr_init<false><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
     CAGRA_LAUNCH_CHECK();
@@ -516,37 +612,46 @@ cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const fl
     return CAGRA_OK;
 }
 
-cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
-                             const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
-                             void *contrib_out, double *scalars_out, double *blk, hipStream_t st) {
-    const size_t lds = merge_fused_lds_bytes(seg->B, seg->k, 8);
-    if (contrib_type == CAGRA_BF16) {
-        static bool attr = false;
-        if (!attr) {
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<true>)) return a_;
-            attr = true;
-        }
-        k_merge_pr<true><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k,
-                                                              seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
-                                                              damping, rank_out, contrib_out, blk);
-    } else {
-        static bool attr = false;
-        if (!attr) {
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<false>)) return a_;
-            attr = true;
-        }
-        k_merge_pr<false><<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k,
-                                                               seg->B, seg->nb, rank_in, g->out_degree, scalars_in,
-                                                               damping, rank_out, contrib_out, blk);
+template <bool BF16OUT>
+static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                      const float *rank_in, const double *scalars_in, const float *partial,
+                                      float *rank_out, void *contrib_out, double *scalars_out, void *ws,
+                                      hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<BF16OUT>)) return a_;
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr_finish<BF16OUT>)) return a_;
+        attr = true;
     }
+    double *blk = reinterpret_cast<double *>(ws);
+    unsigned long long *slots =
+        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + ws_blk_bytes(seg->V, seg->nb));
+    k_merge_pr<BF16OUT><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
+        seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
+        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots);
+    CAGRA_LAUNCH_CHECK();
+    k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
+        seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
+        contrib_out, blk, slots);
     CAGRA_LAUNCH_CHECK();
     k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
 
+cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
+                             const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
+                             void *contrib_out, double *scalars_out, void *ws, hipStream_t st) {
+    if (contrib_type == CAGRA_BF16)
+        return launch_merge_pr_t<true>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
+                                       scalars_out, ws, st);
+    return launch_merge_pr_t<false>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
+                                    scalars_out, ws, st);
+}
+
 cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
-                             int32_t *labels_out, int32_t *changed_out, int32_t *blk, hipStream_t st) {
+                             int32_t *labels_out, int32_t *changed_out, void *ws, hipStream_t st) {
+    int32_t *blk = reinterpret_cast<int32_t *>(ws);
     const size_t lds = merge_fused_lds_bytes(seg->B, seg->k, 4);
     static bool attr = false;
     if (!attr) {

@@ -106,8 +106,9 @@ def _fake_built(c, V=100, N=10, B=10, E=50, Q=20, align=16):
     s = _seg(c, N=N, B=B)
     s.V, s.E, s.Q, s.k, s.nb, s.ntiles = V, E, Q, -(-V // N), -(-V // B), 1
     for name in ("seg_row_begin", "row_ptr", "row_dst", "block_ptr", "tile_edge", "tile_seg", "tile_span_row",
-                 "row_dst_lo"):
+                 "row_dst_lo", "block_items"):
         setattr(s, name, 4096)
+    s.max_items = s.nb
     s.edge_src = 4096 + (0 if align == 16 else 4)
     return s
 
@@ -141,3 +142,20 @@ def test_edge_word_bytes(cagra):
     assert L.cagra_edge_word_bytes(1 << 24) == 4
     text = open(HEADER).read()
     assert re.search(r"#define CAGRA_EDGE16_MAX_N (\d+)", text).group(1) == str(cagra.EDGE16_MAX_N)
+
+
+def test_cluster_validation(cagra):
+    """cagra_cluster rejects bad arguments before any HIP call."""
+    L = cagra.lib()
+    assert L.cagra_cluster_workspace_bytes(0, 10) == 0
+    assert L.cagra_cluster_workspace_bytes(10, -1) == 0
+    assert L.cagra_cluster_workspace_bytes(10, 2 ** 31) == 0
+    g = _graph(cagra, V=10, E=5, off=4096, src=8192, od=12288)
+    assert L.cagra_cluster(None, 1, 1, 1, 1, None, 1, 1 << 20, None) == -1
+    assert L.cagra_cluster(ctypes.byref(_graph(cagra, od=None)), 1, 1, 1, 1, None, 1, 1 << 20, None) == -1
+    assert L.cagra_cluster(ctypes.byref(g), None, 1, 1, 1, None, 1, 1 << 20, None) == -1
+    assert L.cagra_cluster(ctypes.byref(g), 1, 1, None, 1, None, 1, 1 << 20, None) == -1
+    assert L.cagra_cluster(ctypes.byref(g), 1, 4096, 1, 1, None, 1, 1 << 20, None) == -1  # aliases in_offsets
+    assert L.cagra_cluster(ctypes.byref(g), 1, 1, 8192, 1, None, 1, 1 << 20, None) == -1  # aliases in_sources
+    assert L.cagra_cluster(ctypes.byref(g), 1, 1, 1, 1, None, None, 1 << 20, None) == -4  # no workspace
+    assert L.cagra_cluster(ctypes.byref(g), 1, 1, 1, 1, None, 1, 0, None) == -4
