@@ -190,37 +190,39 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int32_
             w[2 * c + 1] = (uint32_t)wv[0][c] >> 16;
         }
     }
-    uint32_t fmask = 0;
+    bool fl[kEPT];  // row starts
     T v[kEPT];
 #pragma unroll
     for (int i = 0; i < kEPT; ++i) {
         if constexpr (FULL) {
-            fmask |= (w[i] & EdgeWord<W>::kFlag) ? (1u << i) : 0u;
+            fl[i] = (w[i] & EdgeWord<W>::kFlag) != 0u;
             v[i] = F::get(seg_vals, gvals, (int32_t)(w[i] & EdgeWord<W>::kIndex));
         } else {
             const bool valid = (uint32_t)(rel + i) < (uint32_t)len;
-            fmask |= (valid && (w[i] & EdgeWord<W>::kFlag)) ? (1u << i) : 0u;
+            fl[i] = valid && (w[i] & EdgeWord<W>::kFlag) != 0u;
             // words outside the share may belong to another segment: read index 0 instead
             const T x = F::get(seg_vals, gvals, valid ? (int32_t)(w[i] & EdgeWord<W>::kIndex) : 0);
             v[i] = valid ? x : Op::identity();
         }
     }
-    const int32_t nf = __popc(fmask);
+    int32_t nf = 0;
+#pragma unroll
+    for (int i = 0; i < kEPT; ++i) nf += fl[i] ? 1 : 0;
     const int32_t incl_nf = wave_incl_sum(nf);
     const int32_t excl_nf = incl_nf - nf;
     const int32_t chunk_nf = __builtin_amdgcn_readlane(incl_nf, 63);
 
-    // lane-local pass: every row start after the lane's first closes a row
-    // that lies entirely inside the lane
-    T run = Op::identity(), headpart = Op::identity();
-    int32_t j = 0;
+    // lane-local pass: at every row start the running value is written to the
+    // lane's next stage slot. The first one is the part of a row that began
+    // before the lane (completed below with the incoming value); every later
+    // one closes a row that lies entirely inside the lane.
+    T run = Op::identity();
+    T *slot = stage + excl_nf;
 #pragma unroll
     for (int i = 0; i < kEPT; ++i) {
-        const bool f = (fmask >> i) & 1u;
-        if (f && j > 0) stage[excl_nf + j] = run;
-        headpart = (f && j == 0) ? run : headpart;
-        j += f ? 1 : 0;
-        run = f ? v[i] : Op::apply(run, v[i]);
+        if (fl[i]) *slot = run;
+        slot += fl[i] ? 1 : 0;
+        run = fl[i] ? v[i] : Op::apply(run, v[i]);
     }
     // segmented inclusive scan of (has row start, tail value) over the wave
     T sv = run;
@@ -229,7 +231,7 @@ __device__ __forceinline__ void process_chunk(const v4i (&wv)[kLoads<W>], int32_
     const T ex_v = dpp_t<kDppWaveShr1, 0xf>(Op::identity(), sv);
     const int32_t ex_f = dpp_i<kDppWaveShr1, 0xf>(0, sf);
     const T incoming = ex_f ? ex_v : Op::apply(S.carry, ex_v);
-    if (nf > 0) stage[excl_nf] = Op::apply(incoming, headpart);
+    if (nf > 0) stage[excl_nf] = Op::apply(incoming, stage[excl_nf]);
     __builtin_amdgcn_wave_barrier();
     // stage[0] is the row that began before this wave's share when the wave
     // had not seen a row start yet: that one is completed across waves later
