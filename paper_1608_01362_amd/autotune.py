@@ -9,7 +9,11 @@ On gfx950 the levels are LDS (staged segments), L2 and the Infinity Cache.
    and one segment (N >= V); B values the merge kernel's LDS allows for k.
 2. Pruning: the builder's query call gives the exact row count Q for each N
    cheaply; the byte model ranks candidates and drops those predicted worse
-   than `prune_factor` times the best.
+   than `prune_factor` times the best of their class. The classes are LDS-
+   staged and cache-gathered segments: the byte model counts HBM bytes only,
+   and a gather through the cache hierarchy pays for its random reads in
+   requests, not bytes, so the two are never pruned against each other; the
+   best staged candidates and the best cache-gathered one are always timed.
 3. Timing: the survivors are built and timed (gather + merge, HIP events);
    the fastest wins. Results are cached in a JSON file keyed by the graph's
    size, value type and operation.
@@ -81,6 +85,23 @@ def query_Q(dg, N: int, B: int, tile_edges: int) -> int:
     return int(c.Q)
 
 
+def select_pool(cands, prune_factor: float, max_trials: int):
+    """Candidates to time: per class (LDS-staged / cache-gathered), those within
+    prune_factor of the class's best predicted bytes, fewest bytes first; up to
+    max_trials - 1 staged ones plus the best cache-gathered one."""
+    def pruned(cls):
+        if not cls:
+            return []
+        best_bytes = min(c.predicted_bytes for c in cls)
+        return sorted([c for c in cls if c.predicted_bytes <= prune_factor * best_bytes],
+                      key=lambda c: c.predicted_bytes)
+    staged = pruned([c for c in cands if c.staged])
+    unstaged = pruned([c for c in cands if not c.staged])
+    if not staged:
+        return unstaged[:max_trials]
+    return staged[:max(1, max_trials - 1)] + unstaged[:1]
+
+
 def _time_pagerank(dg, seg, value_type: int, reps: int = 3) -> float:
     import torch
     st = cagra.PageRankState(dg, seg, value_type)
@@ -138,13 +159,7 @@ def tune(dg, value_type: int = cagra.F32, op: str = "pagerank", cache_path: str 
             for T in tiles:
                 cands.append(Choice(N, B, T, N <= lds_staged_max(value_type), Q,
                                     byte_model(dg.V, dg.E, Q, k, B, wc, edge_word_bytes(N))))
-    best_bytes = min(c.predicted_bytes for c in cands)
-    # staged candidates first: gathers through the cache hierarchy are request-bound
-    pool = sorted([c for c in cands if c.predicted_bytes <= prune_factor * best_bytes],
-                  key=lambda c: (not c.staged, c.predicted_bytes))[:max_trials]
-    if not any(not c.staged for c in pool):
-        unstaged = sorted([c for c in cands if not c.staged], key=lambda c: c.predicted_bytes)
-        pool += unstaged[:1]
+    pool = select_pool(cands, prune_factor, max_trials)
     timed = []
     for c in pool:
         seg = cagra.build_segments(dg, c.N, c.B, c.tile_edges)

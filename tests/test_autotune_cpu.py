@@ -29,3 +29,20 @@ def test_cache_roundtrip(tmp_path):
     autotune.save_cache(p, {"k": {"N": 1, "B": 2, "tile_edges": 64, "staged": True}})
     assert autotune.load_cache(p)["k"]["B"] == 2
     assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+def test_pool_keeps_staged_candidates_when_cache_gathers_move_fewer_bytes():
+    """A one-segment pull moves fewer HBM bytes than LDS-sized segments but pays
+    for its random reads in requests; the pool must still time staged sizes."""
+    C = autotune.Choice
+    cands = [C(1 << 25, 8192, 262144, False, 17_000_000, 5_030_000_000),
+             C(1 << 24, 8192, 262144, False, 28_000_000, 5_140_000_000),
+             C(32768, 8192, 262144, True, 575_000_000, 8_540_000_000),
+             C(32768, 4096, 262144, True, 575_000_000, 8_560_000_000),
+             C(8192, 8192, 262144, True, 900_000_000, 14_000_000_000)]
+    pool = autotune.select_pool(cands, 1.6, 4)
+    assert [c.staged for c in pool] == [True, True, False]
+    assert pool[0].N == 32768 and pool[-1].N == 1 << 25
+    assert all(c.N != 8192 for c in pool)  # 1.64x the best staged bytes: pruned
+    only_unstaged = autotune.select_pool(cands[:2], 1.6, 4)
+    assert [c.N for c in only_unstaged] == [1 << 25, 1 << 24]
