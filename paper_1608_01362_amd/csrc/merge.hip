@@ -193,15 +193,42 @@ __device__ __forceinline__ unsigned long long fix24(float x) {
 
 constexpr int kUnroll = 8;
 
+// Subgraph of flattened entry f, searching forward from sl (pre[sl] <= f,
+// pre[k] > f). A 64-entry step advances 64 / (mean range length) subgraphs on
+// average: WIDE = false reads the next two starts per LDS round trip (ranges
+// of 64 entries or more); WIDE = true tests one start and then reads four per
+// round trip (short ranges, e.g. blocks of low in-degree vertices after
+// clustering). pre is non-decreasing, so the starts <= f form a prefix.
+template <bool WIDE>
+__device__ __forceinline__ int32_t advance(const int32_t *pre, int32_t k, int32_t sl, int32_t f) {
+    if (!WIDE) {
+        for (;;) {
+            const int32_t q1 = pre[min(sl + 1, k)], q2 = pre[min(sl + 2, k)];
+            const int32_t adv = (q1 <= f) + (q2 <= f);
+            sl += adv;
+            if (adv < 2) return sl;
+        }
+    }
+    if (pre[min(sl + 1, k)] > f) return sl;
+    ++sl;
+    for (;;) {
+        const int32_t q1 = pre[min(sl + 1, k)], q2 = pre[min(sl + 2, k)];
+        const int32_t q3 = pre[min(sl + 3, k)], q4 = pre[min(sl + 4, k)];
+        const int32_t adv = (q1 <= f) + (q2 <= f) + (q3 <= f) + (q4 <= f);
+        sl += adv;
+        if (adv < 4) return sl;
+    }
+}
+
 // Streams block b's buffer entries (the ranges of all subgraphs, flattened).
 // Each wave takes a contiguous share; per pass a lane handles kUnroll entries
-// 64 apart, finding its subgraph by walking forward from the previous one.
+// 64 apart, finding its subgraph by searching forward from the previous one.
 // All loads are issued unconditionally (clamped index) so that many are in
 // flight; apply(d, x) updates the LDS accumulator of block offset d. The loads
 // keep the default cache policy: the cache line at each end of a (subgraph,
 // block) range is shared with the neighbouring block, which is merged at the
 // same time on the same XCD and finds the line in L2.
-template <typename PT, class Apply>
+template <typename PT, bool WIDE, class Apply>
 __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, const PT *__restrict__ partial,
                                              const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t F0,
                                              int32_t F1, Apply apply) {
@@ -217,7 +244,7 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
             const int32_t f = f0 + u * kWave + lane;
             const bool valid = f < fb;
             const int32_t ff = valid ? f : f0;
-            while (sl + 1 < k && pre[sl + 1] <= ff) ++sl;
+            sl = advance<WIDE>(pre, k, sl, ff);
             const int32_t i = lo_s[sl] + (ff - pre[sl]);
             const int32_t dd = (int32_t)dlo[i];
             x[u] = partial[i];
@@ -270,7 +297,7 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
 // sums in its own slot of the workspace, and k_merge_pr_finish adds the S
 // slots of the block (exactly, so the split does not change any result) and
 // applies the update.
-template <bool BF16OUT>
+template <bool BF16OUT, bool WIDE>
 __device__ __forceinline__ void merge_pr_block(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b, int32_t j, int32_t S,
@@ -288,8 +315,8 @@ __device__ __forceinline__ void merge_pr_block(
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
     const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
-    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, F0, F1,
-                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
+    stream_block<float, WIDE>(row_dst_lo, partial, lo_s, pre, k, F0, F1,
+                              [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
     __syncthreads();
     if (S > 1) {
         for (int i = threadIdx.x; i < nv; i += kMergeThreads) slot[i] = acc[i];
@@ -330,7 +357,7 @@ __device__ __forceinline__ int32_t block_of_item(const int32_t *__restrict__ ite
     return lo;
 }
 
-template <bool BF16OUT>
+template <bool BF16OUT, bool WIDE>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const int32_t *__restrict__ block_items, const float *__restrict__ partial, int32_t V, int32_t k, int32_t B,
@@ -346,8 +373,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const int32_t b = block_of_item(block_items, nb, i);
     const int32_t j = i - block_items[b], S = block_items[b + 1] - block_items[b];
     unsigned long long *slot = S > 1 ? slots + split_slot(block_items[b], b, j) * B : nullptr;
-    merge_pr_block<BF16OUT>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in, damping,
-                            rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
+    merge_pr_block<BF16OUT, WIDE>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in,
+                                  damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
 }
 
 // Vertex update of the split blocks: the sum of the block's item slots.
@@ -366,9 +393,18 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     const unsigned long long *first = slots + split_slot(block_items[b], b, 0) * B;
+    constexpr int kSlotBatch = 8;  // independent loads in flight per thread
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
         unsigned long long t = 0ull;
-        for (int32_t j = 0; j < S; ++j) t += first[(int64_t)j * B + i];
+        int32_t j = 0;
+        for (; j + kSlotBatch <= S; j += kSlotBatch) {
+            unsigned long long x[kSlotBatch];
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u) x[u] = first[(int64_t)(j + u) * B + i];
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u) t += x[u];
+        }
+        for (; j < S; ++j) t += first[(int64_t)j * B + i];
         acc[i] = t;
     }
     __syncthreads();
@@ -392,8 +428,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_sum_fixed24(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<float>(row_dst_lo, partial, lo_s, pre, k, 0, P,
-                        [&](int32_t d, float x) { atomicAdd(&acc[d], fix24(x)); });
+    stream_block<float, false>(row_dst_lo, partial, lo_s, pre, k, 0, P,
+                               [&](int32_t d, float x) { atomicAdd(&acc[d], fix24(x)); });
     __syncthreads();
     for (int i = threadIdx.x; i < nv; i += kMergeThreads)
         out[vb + i] = (float)((double)(long long)acc[i] * (1.0 / 16777216.0));
@@ -423,7 +459,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *
         __syncthreads();  // LDS reuse across blocks
         const int gi = block_graph[gb];
         const MultiDesc &d = desc[gi];
-        merge_pr_block<false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base), 0, 1,
+        merge_pr_block<false, false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base), 0, 1,
                               d.rank[parity], d.out_degree, d.scalars[parity], damping, d.rank[1 - parity],
                               d.contrib[1 - parity], blk + gb * 4, nullptr, smem);
     }
@@ -515,7 +551,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
     const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<int32_t>(row_dst_lo, partial, lo_s, pre, k, 0, P,
+    stream_block<int32_t, false>(row_dst_lo, partial, lo_s, pre, k, 0, P,
                           [&](int32_t d, int32_t x) { atomicMin(&acc[d], x); });
     __syncthreads();
     int32_t changed = 0;
@@ -612,21 +648,21 @@ cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const fl
     return CAGRA_OK;
 }
 
-template <bool BF16OUT>
+template <bool BF16OUT, bool WIDE>
 static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments *seg, double damping,
                                       const float *rank_in, const double *scalars_in, const float *partial,
                                       float *rank_out, void *contrib_out, double *scalars_out, void *ws,
                                       hipStream_t st) {
     static bool attr = false;
     if (!attr) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<BF16OUT>)) return a_;
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<BF16OUT, WIDE>)) return a_;
         if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr_finish<BF16OUT>)) return a_;
         attr = true;
     }
     double *blk = reinterpret_cast<double *>(ws);
     unsigned long long *slots =
         reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + ws_blk_bytes(seg->V, seg->nb));
-    k_merge_pr<BF16OUT><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
+    k_merge_pr<BF16OUT, WIDE><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
         g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots);
     CAGRA_LAUNCH_CHECK();
@@ -642,11 +678,17 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
 cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
                              const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
                              void *contrib_out, double *scalars_out, void *ws, hipStream_t st) {
+    // mean entries per (subgraph, block) range below one 64-entry step: wide walk
+    const bool wide = seg->Q < (int64_t)kWave * seg->k * seg->nb;
     if (contrib_type == CAGRA_BF16)
-        return launch_merge_pr_t<true>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
-                                       scalars_out, ws, st);
-    return launch_merge_pr_t<false>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
-                                    scalars_out, ws, st);
+        return wide ? launch_merge_pr_t<true, true>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+                                                    contrib_out, scalars_out, ws, st)
+                    : launch_merge_pr_t<true, false>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+                                                     contrib_out, scalars_out, ws, st);
+    return wide ? launch_merge_pr_t<false, true>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
+                                                 scalars_out, ws, st)
+                : launch_merge_pr_t<false, false>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+                                                  contrib_out, scalars_out, ws, st);
 }
 
 cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
