@@ -377,7 +377,39 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
                                   damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
 }
 
-// Vertex update of the split blocks: the sum of the block's item slots.
+// Sum of the item slots of each split block, written into its first slot.
+// kSlotParts workgroups share a block (one part of its vertices each), so the
+// heaviest block's slots are read at the rate of several CUs.
+constexpr int kSlotParts = 8;
+constexpr int kSlotThreads = 256;
+__global__ __launch_bounds__(kSlotThreads) void k_slot_sum(const int32_t *__restrict__ block_items, int32_t V,
+                                                           int32_t B, int32_t parts,
+                                                           unsigned long long *__restrict__ slots) {
+    const int32_t b = blockIdx.x / parts, part = blockIdx.x % parts;
+    const int32_t S = block_items[b + 1] - block_items[b];
+    if (S <= 1) return;  // merged in one piece
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    const int32_t span = (nv + parts - 1) / parts;
+    const int32_t lo = part * span, hi = min(lo + span, nv);
+    unsigned long long *first = slots + split_slot(block_items[b], b, 0) * B;
+    constexpr int kSlotBatch = 8;  // independent loads in flight per thread
+    for (int32_t i = lo + threadIdx.x; i < hi; i += kSlotThreads) {
+        unsigned long long t = first[i];
+        int32_t j = 1;
+        for (; j + kSlotBatch <= S; j += kSlotBatch) {
+            unsigned long long x[kSlotBatch];
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u) x[u] = first[(int64_t)(j + u) * B + i];
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u) t += x[u];
+        }
+        for (; j < S; ++j) t += first[(int64_t)j * B + i];
+        first[i] = t;
+    }
+}
+
+// Vertex update of the split blocks from the summed first slot.
 template <bool BF16OUT>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int32_t *__restrict__ block_items, int32_t V, int32_t B, int32_t nb, const float *__restrict__ rank_in,
@@ -387,26 +419,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ double red[16];
     const int32_t b = blockIdx.x;
-    const int32_t S = block_items[b + 1] - block_items[b];
-    if (S <= 1) return;  // merged in one piece
+    if (block_items[b + 1] - block_items[b] <= 1) return;  // merged in one piece
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     const unsigned long long *first = slots + split_slot(block_items[b], b, 0) * B;
-    constexpr int kSlotBatch = 8;  // independent loads in flight per thread
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
-        unsigned long long t = 0ull;
-        int32_t j = 0;
-        for (; j + kSlotBatch <= S; j += kSlotBatch) {
-            unsigned long long x[kSlotBatch];
-#pragma unroll
-            for (int u = 0; u < kSlotBatch; ++u) x[u] = first[(int64_t)(j + u) * B + i];
-#pragma unroll
-            for (int u = 0; u < kSlotBatch; ++u) t += x[u];
-        }
-        for (; j < S; ++j) t += first[(int64_t)j * B + i];
-        acc[i] = t;
-    }
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = first[i];
     __syncthreads();
     pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out,
                          blk + (int64_t)b * 4, red);
@@ -665,6 +683,10 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
     k_merge_pr<BF16OUT, WIDE><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
         g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots);
+    CAGRA_LAUNCH_CHECK();
+    const int32_t parts = (int64_t)seg->nb * kSlotParts <= INT32_MAX ? kSlotParts : 1;
+    k_slot_sum<<<(unsigned)((int64_t)seg->nb * parts), kSlotThreads, 0, st>>>(seg->block_items, seg->V, seg->B, parts,
+                                                                            slots);
     CAGRA_LAUNCH_CHECK();
     k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
         seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
