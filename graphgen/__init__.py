@@ -49,6 +49,7 @@ def _load():
         lib.gg_csc_both_directions.argtypes = [ctypes.c_int32, p32, p32, p32, p32, ctypes.c_int]
         lib.gg_splitmix_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.gg_splitmix_at.restype = ctypes.c_uint64
+        lib.gg_pair_values.argtypes = [ctypes.c_int32, p32, p32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -156,6 +157,27 @@ class MultiGraphSpec:
     scale: int
     edge_factor: int
     seed: int
+
+
+def bipartite_ratings(user_scale: int, item_scale: int, edge_factor: int, seed: int,
+                      threads: int | None = None):
+    """Synthetic rating graph: 2^user_scale users and 2^item_scale items; R-MAT
+    draws (user, item) pairs (the item is the R-MAT column shifted down to
+    item_scale bits), duplicates removed; every rating is an edge in both
+    directions (users 0..U-1, items U..U+I-1) with value 1..5 from a hash of the
+    pair. Returns (Graph, values[E] in the graph's in-edge order, U, I)."""
+    assert item_scale <= user_scale
+    U, I = 1 << user_scale, 1 << item_scale
+    u, d = rmat_edges(user_scale, edge_factor, seed, threads=threads)
+    it = (d >> (user_scale - item_scale)).astype(np.int32)
+    src = np.concatenate([u, U + it]).astype(np.int32)
+    dst = np.concatenate([U + it, u]).astype(np.int32)
+    del u, d, it
+    g = edges_to_graph(U + I, src, dst, True, threads, name=f"ratings_u{user_scale}_i{item_scale}_ef{edge_factor}_s{seed}")
+    vals = np.empty(max(g.E, 1), dtype=np.float32)
+    _load().gg_pair_values(g.V, _p(g.in_offsets), _p(g.in_sources), (seed * 7919 + 11) & (2**64 - 1),
+                           vals.ctypes.data, threads or default_threads())
+    return g, vals[:g.E], U, I
 
 
 def multigraph_specs(count: int, seed: int, scale_lo: int = 10, scale_hi: int = 20,

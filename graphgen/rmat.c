@@ -196,3 +196,18 @@ void gg_csc_both_directions(int32_t V, const int32_t *in_offsets, const int32_t 
         }
     }
 }
+
+/* Value of every in-edge of a graph whose edges come in both directions: the
+   same value for u -> v and v -> u, 1 + (SplitMix64 output at the unordered
+   pair key) mod 5, as a float (synthetic ratings). */
+void gg_pair_values(int32_t V, const int32_t *in_offsets, const int32_t *in_sources, uint64_t seed,
+                    float *out, int threads) {
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(threads)
+    for (int32_t v = 0; v < V; ++v) {
+        for (int32_t e = in_offsets[v]; e < in_offsets[v + 1]; ++e) {
+            uint64_t a = (uint64_t)(uint32_t)in_sources[e], b = (uint64_t)(uint32_t)v;
+            uint64_t key = a < b ? (a << 32) | b : (b << 32) | a;
+            out[e] = (float)(1 + splitmix_at(seed, key) % 5u);
+        }
+    }
+}
