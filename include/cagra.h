@@ -176,6 +176,39 @@ size_t cagra_cluster_workspace_bytes(int32_t V, int64_t E);
 int cagra_cluster(const cagra_graph *g, int32_t *perm, int32_t *in_offsets, int32_t *in_sources,
                   int32_t *out_degree, int32_t *hot, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Latent factors per vertex of the collaborative-filtering step. */
+#define CAGRA_CF_FACTORS 64
+
+/*
+ * Edge values in the segmented edge order: seg_values[p] = in_values[e] where
+ * p is the position that in-edge e (CSC order, as in g) takes in the
+ * segmented edge array of seg. in_values and seg_values are device float[E],
+ * not aliased. Asynchronous; no workspace.
+ */
+cagra_status cagra_segment_edge_values(const cagra_graph *g, const cagra_segments *seg, const float *in_values,
+                                       float *seg_values, hipStream_t stream);
+
+/* Device workspace of cagra_cf_iter (one FP64 value per gather tile). */
+size_t cagra_cf_workspace_bytes(const cagra_segments *seg);
+
+/*
+ * One collaborative-filtering step on a rating graph (every rating an edge in
+ * both directions; Section 4's update function with access to the old
+ * destination value), as gradient descent on
+ *   F(X) = 1/2 sum_ratings (r - <x_u, x_i>)^2 + lambda/2 sum_v |x_v|^2:
+ *   g_v      = sum over in-edges u -> v of (r_uv - <x_u, x_v>) x_u
+ *   x_out[v] = x_in[v] + gamma * (g_v - lambda * x_in[v])
+ *   sq_out[0] = sum over in-edges of (r_uv - <x_u, x_v>)^2 at x_in (FP64)
+ * x_in, x_out: device float[V][CAGRA_CF_FACTORS] (row-major, not aliased);
+ * seg_values: the ratings in the segmented edge order
+ * (cagra_segment_edge_values); partial: float[Q][CAGRA_CF_FACTORS] scratch.
+ * The merge adds the subgraphs' buffers in ascending order (FP32). Requires
+ * seg->B <= 512.
+ */
+cagra_status cagra_cf_iter(const cagra_graph *g, const cagra_segments *seg, const float *seg_values, double gamma,
+                           double lambda, const float *x_in, float *partial, float *x_out, double *sq_out,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 

@@ -24,6 +24,7 @@ LDS_BYTES = 163840
 STAGE_BYTES = 131072
 TILE_WAVES = 16
 EDGE16_MAX_N = 32768
+CF_FACTORS = 64
 PPR_COLS = 64
 
 _c_i32, _c_i64, _c_size, _c_vp, _c_dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
@@ -44,7 +45,8 @@ class CSegments(ctypes.Structure):
 
 EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
-    "cagra_edge_word_bytes", "cagra_cluster_workspace_bytes", "cagra_cluster", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
+    "cagra_edge_word_bytes", "cagra_cluster_workspace_bytes", "cagra_cluster", "cagra_segment_edge_values",
+    "cagra_cf_workspace_bytes", "cagra_cf_iter", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
@@ -86,6 +88,10 @@ def lib():
             "cagra_edge_word_bytes": ([_c_i32], _c_i32),
             "cagra_cluster_workspace_bytes": ([_c_i32, _c_i64], _c_size),
             "cagra_cluster": ([GP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_segment_edge_values": ([GP, SP, _c_vp, _c_vp, st], ctypes.c_int),
+            "cagra_cf_workspace_bytes": ([SP], _c_size),
+            "cagra_cf_iter": ([GP, SP, _c_vp, _c_dbl, _c_dbl, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st],
+                              ctypes.c_int),
             "cagra_query_workspace_bytes": ([_c_i32, _c_i64, _c_i32], _c_size),
             "cagra_build_segments": ([GP, SP, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_iter_workspace_bytes": ([SP], _c_size),
@@ -542,3 +548,41 @@ class MultiPageRank:
 
     def scalars_of(self, i: int):
         return self.scalars[self.cur][4 * i:4 * i + 4]
+
+
+# --------------------------------------------------------------------------- collaborative filtering
+
+def segment_edge_values(dg: DeviceGraph, seg: Segments, in_values, stream=None):
+    """Edge values (float32, CSC order) permuted into the segmented edge order."""
+    import torch
+    out = torch.empty(max(dg.E, 1), dtype=torch.float32, device=_dev())
+    _check(lib().cagra_segment_edge_values(ctypes.byref(dg.c), ctypes.byref(seg.c), _ptr(in_values), _ptr(out),
+                                           _stream(stream)), "cagra_segment_edge_values")
+    return out
+
+
+class CFState:
+    """Latent vectors [V][64] (double-buffered) and scratch for gradient-descent
+    collaborative filtering on a rating graph through segmenting."""
+
+    def __init__(self, dg: DeviceGraph, seg: Segments, seg_values, x0):
+        import torch
+        dev = _dev()
+        self.dg, self.seg, self.vals = dg, seg, seg_values
+        self.x = [x0.clone(), torch.empty_like(x0)]
+        self.partial = torch.empty(max(seg.Q, 1) * CF_FACTORS, dtype=torch.float32, device=dev)
+        n = lib().cagra_cf_workspace_bytes(ctypes.byref(seg.c))
+        self.ws = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.sq = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.cur = 0
+
+    def step(self, gamma: float, lam: float, stream=None):
+        a, b = self.cur, 1 - self.cur
+        _check(lib().cagra_cf_iter(ctypes.byref(self.dg.c), ctypes.byref(self.seg.c), _ptr(self.vals), gamma, lam,
+                                   _ptr(self.x[a]), _ptr(self.partial), _ptr(self.x[b]), _ptr(self.sq),
+                                   _ptr(self.ws), self.ws.numel(), _stream(stream)), "cagra_cf_iter")
+        self.cur = b
+
+    @property
+    def x_now(self):
+        return self.x[self.cur]

@@ -25,6 +25,11 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
 cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
 bool gather_staged(int32_t N, int32_t value_type);
 cagra_status cluster_workspace_bytes(int32_t V, int64_t E, size_t *bytes);
+cagra_status launch_edge_values(const cagra_graph *g, const cagra_segments *seg, const float *in_values,
+                                 float *seg_values, hipStream_t st);
+cagra_status launch_cf_iter(const cagra_segments *seg, const float *seg_values, double gamma, double lambda,
+                            const float *x_in, float *partial, float *x_out, double *sq_out, double *tile_sq,
+                            hipStream_t st);
 cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offsets_new, int32_t *in_sources_new,
                            int32_t *outdeg_new, int32_t *hot, void *ws, size_t ws_bytes, hipStream_t st);
 cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
@@ -132,6 +137,41 @@ const char *cagra_status_string(int status) {
 const char *cagra_last_error(void) { return g_last_error; }
 
 int32_t cagra_max_merge_block(void) { return kMaxMergeBlock; }
+
+cagra_status cagra_segment_edge_values(const cagra_graph *g, const cagra_segments *seg, const float *in_values,
+                                       float *seg_values, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, false)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (g->E > 0 && (!in_values || !seg_values)) return fail(CAGRA_E_INVALID, "in_values or seg_values is NULL");
+    if (g->E > 0 && (const void *)in_values == (const void *)seg_values)
+        return fail(CAGRA_E_INVALID, "in_values and seg_values must not alias");
+    return launch_edge_values(g, seg, in_values, seg_values, stream);
+}
+
+size_t cagra_cf_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->ntiles < 0) return 0;
+    return (size_t)(seg->ntiles > 0 ? seg->ntiles : 1) * sizeof(double) + 256;
+}
+
+cagra_status cagra_cf_iter(const cagra_graph *g, const cagra_segments *seg, const float *seg_values, double gamma,
+                           double lambda, const float *x_in, float *partial, float *x_out, double *sq_out,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, false)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (seg->B > kMaxPprBlock) return fail(CAGRA_E_CAPACITY, "the CF merge needs B <= %d (got %d)", kMaxPprBlock, seg->B);
+    if (!x_in || !x_out || !sq_out || (seg->Q > 0 && (!partial || !seg_values)))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if ((const void *)x_in == (const void *)x_out) return fail(CAGRA_E_INVALID, "x_in and x_out must not alias");
+    if (!(gamma >= 0.0) || !(lambda >= 0.0)) return fail(CAGRA_E_INVALID, "gamma and lambda must be >= 0");
+    if (!workspace || workspace_bytes < cagra_cf_workspace_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", cagra_cf_workspace_bytes(seg),
+                    workspace_bytes);
+    return launch_cf_iter(seg, seg_values, gamma, lambda, x_in, partial, x_out, sq_out, (double *)workspace, stream);
+}
 
 size_t cagra_cluster_workspace_bytes(int32_t V, int64_t E) {
     if (V < 1 || E < 0 || E > (int64_t)INT32_MAX - 1) return 0;

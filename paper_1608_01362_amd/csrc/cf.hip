@@ -1,0 +1,259 @@
+// Collaborative filtering on a rating graph through segmenting: the edge
+// update reads the source's and the destination's latent vectors (the old
+// destination value of Section 4's interface), EdgeUpdate (r - <x_u, x_v>) x_u,
+// Merge = vector sum, VertexUpdate x_v + gamma (g_v - lambda x_v): gradient
+// descent on 1/2 sum_ratings (r - <x_u, x_i>)^2 + lambda/2 sum |x|^2.
+//
+// Layout as for batched personalized PageRank: [V][64] FP32 vertex vectors,
+// lane j of a wave owns factor j, so each source row is one 256-byte load and
+// each buffer row one 256-byte store; the dot product of an edge is a DPP
+// reduction across the wave. Segments are sized for L2 or the Infinity Cache
+// (256 bytes per vertex). Edge values travel in the segmented edge order,
+// produced once by k_edge_values.
+#include "common.h"
+
+namespace cagra {
+
+constexpr int kCfK = CAGRA_CF_FACTORS;
+constexpr int kCfWaves = CAGRA_TILE_WAVES;
+constexpr int kCfThreads = kCfWaves * kWave;
+constexpr int kCfBatch = 16;         // source rows loaded ahead per wave
+constexpr int kEdgesPerThread = 16;  // edge-value permutation
+
+static_assert(kCfK == kWave, "one factor per lane");
+
+// ---------------------------------------------------------------- edge values
+
+// Last r in [lo, hi) with a[r] <= x (a ascending, a[lo] <= x).
+__device__ __forceinline__ int32_t last_le(const int32_t *a, int32_t lo, int32_t hi, int64_t x) {
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// First r in [lo, hi) with a[r] >= x (hi if none).
+__device__ __forceinline__ int32_t first_ge(const int32_t *a, int32_t lo, int32_t hi, int64_t x) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// seg_values[p] = in_values[e], p = position of in-edge e (CSC order) in the
+// segmented edge order: row r = (subgraph of the source, destination), p =
+// row_ptr[r] + rank of e among the row's edges (sources ascending in both).
+__global__ void k_edge_values(const int32_t *__restrict__ in_offsets, const int32_t *__restrict__ in_sources,
+                              int32_t V, int64_t E, int32_t N, const int32_t *__restrict__ seg_row_begin,
+                              const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ row_dst,
+                              const float *__restrict__ in_values, float *__restrict__ seg_values) {
+    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kEdgesPerThread;
+    if (e0 >= E) return;
+    const int64_t e1 = e0 + kEdgesPerThread < E ? e0 + kEdgesPerThread : E;
+    int32_t v = last_le(in_offsets, 0, V, e0);  // non-empty row holding e0
+    int32_t run_s = -1, run_start = 0, row = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        while ((int64_t)in_offsets[v + 1] <= e) {
+            ++v;
+            run_s = -1;
+        }
+        const int32_t s = in_sources[e] / N;
+        if (s != run_s) {  // first edge of this (segment, destination) run seen by the thread
+            run_s = s;
+            run_start = first_ge(in_sources, in_offsets[v], in_offsets[v + 1], (int64_t)s * N);
+            row = first_ge(row_dst, seg_row_begin[s], seg_row_begin[s + 1], v);
+        }
+        seg_values[(int64_t)row_ptr[row] + (e - run_start)] = in_values[e];
+    }
+}
+
+cagra_status launch_edge_values(const cagra_graph *g, const cagra_segments *seg, const float *in_values,
+                                 float *seg_values, hipStream_t st) {
+    if (g->E == 0) return CAGRA_OK;
+    const int64_t threads = ceil_div(g->E, kEdgesPerThread);
+    k_edge_values<<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(g->in_offsets, g->in_sources, g->V, g->E, seg->N,
+                                                                    seg->seg_row_begin, seg->row_ptr, seg->row_dst,
+                                                                    in_values, seg_values);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// ---------------------------------------------------------------- gather
+
+// Sum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ float wave_sum_all(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, true));  // row_shr:1
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, true));  // row_shr:2
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, true));  // row_shr:4
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, true));  // row_shr:8
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// One tile per workgroup; each wave streams an equal share of the tile's edges.
+// A row's partial gradient is written when the row closes inside the share;
+// rows that continue across shares are completed after a barrier in wave order.
+template <typename W>
+__global__ __launch_bounds__(kCfThreads) void k_cf_gather(
+    const W *__restrict__ edge_src, const float *__restrict__ vals, const int32_t *__restrict__ tile_edge,
+    const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const int32_t *__restrict__ row_dst,
+    const float *__restrict__ X, int32_t N, int32_t ntiles, float *__restrict__ partial,
+    double *__restrict__ tile_sq) {
+    __shared__ float fix_head[kCfWaves][kCfK];
+    __shared__ float fix_last[kCfWaves][kCfK];
+    __shared__ int32_t fix_row[kCfWaves];
+    __shared__ int32_t fix_has[kCfWaves];
+    __shared__ double red_sq[kCfWaves];
+
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t vbase = (int64_t)tile_seg[t] * N;
+    const int64_t sl = (e1 - e0 + kCfWaves - 1) / kCfWaves;
+    int64_t w0 = e0 + w * sl;
+    if (w0 > e1) w0 = e1;
+    int64_t w1 = w0 + sl;
+    if (w1 > e1) w1 = e1;
+    int32_t row = span_row[(int64_t)t * kCfWaves + w] - 1;  // row open at the share's start
+    int32_t seen = 0;
+    float acc = 0.0f, head = 0.0f, xv = 0.0f;
+    double sq = 0.0;
+    // the share starts inside a row (never the case for wave 0: tiles start on rows)
+    if (w0 < w1 && !((uint32_t)edge_src[w0] & EdgeWord<W>::kFlag))
+        xv = X[(int64_t)row_dst[row] * kCfK + lane];
+    const float *xs = X + vbase * kCfK + lane;
+
+    for (int64_t b0 = w0; b0 < w1; b0 += kWave) {
+        const int64_t e = b0 + lane;
+        const uint32_t word = e < w1 ? (uint32_t)edge_src[e] : 0u;
+        const float val = e < w1 ? vals[e] : 0.0f;
+        const int n = (int)(w1 - b0 < kWave ? w1 - b0 : kWave);
+        for (int jb = 0; jb < n; jb += kCfBatch) {
+            uint32_t wv[kCfBatch];
+            float x[kCfBatch];
+#pragma unroll
+            for (int u = 0; u < kCfBatch; ++u) {
+                wv[u] = (uint32_t)__builtin_amdgcn_readlane((int32_t)word, jb + u);
+                x[u] = xs[(int64_t)(wv[u] & EdgeWord<W>::kIndex) * kCfK];
+            }
+#pragma unroll
+            for (int u = 0; u < kCfBatch; ++u) {
+                if (jb + u < n) {
+                    if (wv[u] & EdgeWord<W>::kFlag) {  // a row starts: the open row is complete
+                        if (seen) partial[(int64_t)row * kCfK + lane] = acc;
+                        else head = acc;
+                        seen = 1;
+                        ++row;
+                        acc = 0.0f;
+                        xv = X[(int64_t)row_dst[row] * kCfK + lane];
+                    }
+                    const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), jb + u));
+                    const float err = r - wave_sum_all(x[u] * xv);
+                    acc = fmaf(err, x[u], acc);
+                    sq += (double)err * (double)err;
+                }
+            }
+        }
+    }
+    fix_head[w][lane] = seen ? head : acc;
+    fix_last[w][lane] = acc;
+    if (lane == 0) {
+        fix_row[w] = row;
+        fix_has[w] = seen;
+        red_sq[w] = sq;
+    }
+    __syncthreads();
+    if (fix_has[w]) {
+        float tot = fix_last[w][lane];
+        for (int x2 = w + 1; x2 < kCfWaves; ++x2) {
+            tot += fix_head[x2][lane];
+            if (fix_has[x2]) break;
+        }
+        partial[(int64_t)fix_row[w] * kCfK + lane] = tot;
+    }
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int x2 = 0; x2 < kCfWaves; ++x2) s += red_sq[x2];
+        tile_sq[t] = s;
+    }
+}
+
+// ---------------------------------------------------------------- merge + update
+
+// Paper-order merge of block b (subgraphs ascending; within a subgraph the
+// waves take distinct rows, hence distinct destinations), then
+// x_v' = x_v + gamma * (g_v - lambda * x_v).
+__global__ __launch_bounds__(kCfThreads) void k_merge_cf(const int32_t *__restrict__ row_dst,
+                                                         const int32_t *__restrict__ block_ptr,
+                                                         const float *__restrict__ partial, int32_t V, int32_t k,
+                                                         int32_t B, int32_t nb, float gamma, float lambda,
+                                                         const float *__restrict__ x_in, float *__restrict__ x_out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float *acc = reinterpret_cast<float *>(smem);  // [B][kCfK]
+    const int b = xcd_remap(blockIdx.x, nb);
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < nv * kCfK; i += kCfThreads) acc[i] = 0.0f;
+    __syncthreads();
+    for (int32_t s = 0; s < k; ++s) {
+        const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
+        for (int32_t i = lo + w; i < hi; i += kCfWaves) {
+            const int32_t d = (int32_t)(row_dst[i] - vb);
+            acc[d * kCfK + lane] += partial[(int64_t)i * kCfK + lane];
+        }
+        __syncthreads();
+    }
+    for (int i = w; i < nv; i += kCfWaves) {
+        const int64_t o = (vb + i) * kCfK + lane;
+        const float x = x_in[o];
+        x_out[o] = x + gamma * (acc[i * kCfK + lane] - lambda * x);
+    }
+}
+
+// Fixed-order sum of the tiles' squared errors.
+__global__ __launch_bounds__(256) void k_sum_tiles(const double *__restrict__ tile_sq, int32_t n,
+                                                   double *__restrict__ out) {
+    __shared__ double red[4];
+    double a = 0.0;
+    for (int32_t j = threadIdx.x; j < n; j += 256) a += tile_sq[j];
+    a = block_sum_f64<256>(a, red);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+size_t cf_merge_lds_bytes(int32_t B) { return (size_t)B * kCfK * sizeof(float); }
+
+cagra_status launch_cf_iter(const cagra_segments *seg, const float *seg_values, double gamma, double lambda,
+                            const float *x_in, float *partial, float *x_out, double *sq_out, double *tile_sq,
+                            hipStream_t st) {
+    if (seg->ntiles > 0) {
+        if (edge16(seg->N))
+            k_cf_gather<uint16_t><<<seg->ntiles, kCfThreads, 0, st>>>(
+                static_cast<const uint16_t *>(seg->edge_src), seg_values, seg->tile_edge, seg->tile_seg,
+                seg->tile_span_row, seg->row_dst, x_in, seg->N, seg->ntiles, partial, tile_sq);
+        else
+            k_cf_gather<uint32_t><<<seg->ntiles, kCfThreads, 0, st>>>(
+                static_cast<const uint32_t *>(seg->edge_src), seg_values, seg->tile_edge, seg->tile_seg,
+                seg->tile_span_row, seg->row_dst, x_in, seg->N, seg->ntiles, partial, tile_sq);
+        CAGRA_LAUNCH_CHECK();
+    }
+    static bool attr = false;
+    if (!attr) {
+        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_cf)) return a_;
+        attr = true;
+    }
+    k_merge_cf<<<seg->nb, kCfThreads, cf_merge_lds_bytes(seg->B), st>>>(
+        seg->row_dst, seg->block_ptr, partial, seg->V, seg->k, seg->B, seg->nb, (float)gamma, (float)lambda, x_in,
+        x_out);
+    CAGRA_LAUNCH_CHECK();
+    k_sum_tiles<<<1, 256, 0, st>>>(tile_sq, seg->ntiles, sq_out);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+}  // namespace cagra

@@ -159,3 +159,23 @@ def test_cluster_validation(cagra):
     assert L.cagra_cluster(ctypes.byref(g), 1, 1, 8192, 1, None, 1, 1 << 20, None) == -1  # aliases in_sources
     assert L.cagra_cluster(ctypes.byref(g), 1, 1, 1, 1, None, None, 1 << 20, None) == -4  # no workspace
     assert L.cagra_cluster(ctypes.byref(g), 1, 1, 1, 1, None, 1, 0, None) == -4
+
+
+def test_cf_validation(cagra):
+    """cagra_segment_edge_values and cagra_cf_iter reject bad arguments before any HIP call."""
+    L = cagra.lib()
+    g = _graph(cagra, V=100, E=50)
+    s = _fake_built(cagra)
+    assert L.cagra_segment_edge_values(None, ctypes.byref(s), 1, 2, None) == -1
+    assert L.cagra_segment_edge_values(ctypes.byref(g), ctypes.byref(s), None, 2, None) == -1
+    assert L.cagra_segment_edge_values(ctypes.byref(g), ctypes.byref(s), 8, 8, None) == -1  # aliased
+    assert L.cagra_cf_workspace_bytes(ctypes.byref(s)) >= 8
+    ws = L.cagra_cf_workspace_bytes(ctypes.byref(s))
+    args = lambda **kw: [kw.get(n, d) for n, d in (("vals", 1), ("gamma", 0.01), ("lam", 0.1), ("xi", 2), ("part", 3),
+                                                    ("xo", 4), ("sq", 5), ("ws", 6), ("wsb", ws))]
+    assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(s), *args(xo=2), None) == -1  # x_in aliases x_out
+    assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(s), *args(gamma=-1.0), None) == -1
+    assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(s), *args(sq=None), None) == -1
+    assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(s), *args(wsb=4), None) == -4
+    big = _fake_built(cagra, B=1024)
+    assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(big), *args(), None) == -3  # merge LDS
