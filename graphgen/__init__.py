@@ -138,6 +138,12 @@ def symmetrize(g: Graph, threads: int | None = None) -> Graph:
     return edges_to_graph(g.V, src, dst, True, th, name=g.name + "_sym")
 
 
+def transpose(g: Graph, threads: int | None = None) -> Graph:
+    """The graph with every edge reversed (its in-edges are g's out-edges)."""
+    dst = np.repeat(np.arange(g.V, dtype=np.int32), np.diff(g.in_offsets))
+    return edges_to_graph(g.V, dst, g.in_sources, True, threads, name=g.name + "_T")
+
+
 def from_edge_list(V: int, edges, name: str = "") -> Graph:
     """Small graphs for tests: edges is an iterable of (u, v) meaning u -> v."""
     e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)

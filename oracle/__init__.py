@@ -15,6 +15,7 @@ What each function follows:
   segmented_pagerank_step  the three above composed with the PageRank update of Section 4
   cluster.cluster     Section 5 frequency-based clustering and relabelling (numpy, oracle/cluster.py)
   cf.step / gradient  collaborative filtering as gradient-descent matrix factorization (numpy, oracle/cf.py)
+  bc.betweenness      Brandes' betweenness centrality from sampled starts (numpy, oracle/bc.py)
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
