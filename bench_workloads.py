@@ -18,6 +18,10 @@ cf          collaborative filtering (gradient-descent matrix factorization, 64
             factors) on a Netflix-shaped synthetic rating graph: 2^19 users, 2^14
             items, R-MAT-drawn ratings (edge factor 200 per user, duplicates
             removed), each rating an edge in both directions; segment sizes swept
+bc          betweenness centrality (Brandes) from 12 sampled starts on R-MAT scale
+            25 / ef 32 / seed 3, level-synchronous segmented pulls with the frontier
+            as a mask of active segments (forward on the graph, backward on its
+            reverse)
 cluster     frequency-based clustering (Section 5) then segmenting, R-MAT scale 25
             / ef 32 / seed 3 (the headline graph): clustering time, expansion
             factor q, PageRank iteration time and time to L1 residual < 1e-6,
@@ -310,6 +314,44 @@ def cf(args, log):
             "dtype": "f32", "data": "synthetic"}
 
 
+def bc(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    t0 = time.perf_counter()
+    g = graphgen.rmat_graph(25, 32, 3)
+    gt = graphgen.transpose(g)
+    log(f"graph and reverse in {time.perf_counter() - t0:.1f}s")
+    rng = np.random.default_rng(12)
+    sources = rng.choice(np.flatnonzero(g.out_degree > 0), size=12, replace=False)
+    dg, dgt = cagra.DeviceGraph.from_host(g), cagra.DeviceGraph.from_host(gt)
+    V, E = g.V, g.E
+    del g, gt
+    seg = cagra.build_segments(dg, 32768, 8192, 262144)
+    seg_t = cagra.build_segments(dgt, 32768, 8192, 262144)
+    st = cagra.BCState(seg, seg_t)
+    st.add_source(int(sources[0]))  # warm-up
+    st.bc.zero_()
+    st.levels = []
+    torch.cuda.synchronize()
+    per = []
+    t1 = time.perf_counter()
+    for s_ in sources:
+        a = time.perf_counter()
+        st.add_source(int(s_))
+        torch.cuda.synchronize()
+        per.append(round((time.perf_counter() - a) * 1e3, 2))
+    total = time.perf_counter() - t1
+    log(f"12 starts: {total * 1e3:.1f} ms; per start {per}; BFS levels {st.levels}")
+    passes = sum(2 * lv - 1 for lv in st.levels)  # forward levels + backward levels
+    return {"metric": "seconds for betweenness centrality from 12 starts at R-MAT-25", "value": round(total, 4),
+            "unit": "s", "higher_is_better": False, "ms_per_start": per, "bfs_levels": st.levels,
+            "segmented_passes": passes, "dense_equivalent_GTEPS": round(E * passes / total / 1e9, 2),
+            "config": {"workload": "bc12_rmat25_ef32_seed3", "V": V, "E": E, "N": 32768, "B": 8192,
+                       "sources": [int(x) for x in sources]},
+            "dtype": "f32", "data": "synthetic"}
+
+
 def run(name, args, log):
     return {"labelprop": labelprop, "ppr": ppr, "multigraph": multigraph, "warmstart": warmstart,
-            "cluster": cluster, "cf": cf}[name](args, log)
+            "cluster": cluster, "cf": cf, "bc": bc}[name](args, log)

@@ -209,6 +209,36 @@ cagra_status cagra_cf_iter(const cagra_graph *g, const cagra_segments *seg, cons
                            double lambda, const float *x_in, float *partial, float *x_out, double *sq_out,
                            void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Betweenness centrality from a start vertex (Brandes' algorithm) as
+ * level-synchronous segmented pulls with an active frontier (Section 4
+ * EdgeMap): a forward level adds sigma[u] over in-edges u -> v from the
+ * vertices u at depth d into every unvisited v, which then gets depth d + 1
+ * and that sum as sigma[v]; a backward level, run on the segmentation of the
+ * reverse graph (seg_t), sets delta[u] = sigma[u] * sum over out-edges u -> w
+ * with depth d + 1 of (1 + delta[w]) / sigma[w] for the vertices u at depth d
+ * and adds delta[u] to bc[u] unless u is the start. Segments without a
+ * frontier vertex are skipped in both phases. FP32 values, FP32 merges in
+ * subgraph order.
+ *
+ *   depth  device int32[V]  (-1 = unreached)      sigma, delta, bc  device float[V]
+ *   vals, sums  device float[V] scratch            partial  device float[Q] scratch
+ *   count  device int32[1]: size of the new frontier after a forward level
+ *   workspace: cagra_bc_workspace_bytes(seg) bytes (the frontier's segment bits)
+ * cagra_bc_start sets depth = -1, sigma = delta = 0, then depth[source] = 0 and
+ * sigma[source] = 1. A start's forward levels run for d = 0, 1, ... until the
+ * count is 0; its backward levels then run for d = deepest - 1 down to 0.
+ */
+size_t cagra_bc_workspace_bytes(const cagra_segments *seg);
+cagra_status cagra_bc_start(int32_t V, int32_t source, int32_t *depth, float *sigma, float *delta,
+                            hipStream_t stream);
+cagra_status cagra_bc_forward_level(const cagra_segments *seg, int32_t d, int32_t *depth, float *sigma, float *vals,
+                                    float *partial, float *sums, int32_t *count, void *workspace,
+                                    size_t workspace_bytes, hipStream_t stream);
+cagra_status cagra_bc_backward_level(const cagra_segments *seg_t, int32_t d, int32_t source, const int32_t *depth,
+                                     const float *sigma, float *delta, float *bc, float *vals, float *partial,
+                                     float *sums, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 

@@ -46,7 +46,8 @@ class CSegments(ctypes.Structure):
 EXPORTS = [
     "cagra_abi_version", "cagra_status_string", "cagra_last_error", "cagra_max_merge_block",
     "cagra_edge_word_bytes", "cagra_cluster_workspace_bytes", "cagra_cluster", "cagra_segment_edge_values",
-    "cagra_cf_workspace_bytes", "cagra_cf_iter", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
+    "cagra_cf_workspace_bytes", "cagra_cf_iter", "cagra_bc_workspace_bytes", "cagra_bc_start",
+    "cagra_bc_forward_level", "cagra_bc_backward_level", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
@@ -90,6 +91,12 @@ def lib():
             "cagra_cluster": ([GP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_segment_edge_values": ([GP, SP, _c_vp, _c_vp, st], ctypes.c_int),
             "cagra_cf_workspace_bytes": ([SP], _c_size),
+            "cagra_bc_workspace_bytes": ([SP], _c_size),
+            "cagra_bc_start": ([_c_i32, _c_i32, _c_vp, _c_vp, _c_vp, st], ctypes.c_int),
+            "cagra_bc_forward_level": ([SP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st],
+                                       ctypes.c_int),
+            "cagra_bc_backward_level": ([SP, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                         _c_size, st], ctypes.c_int),
             "cagra_cf_iter": ([GP, SP, _c_vp, _c_dbl, _c_dbl, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st],
                               ctypes.c_int),
             "cagra_query_workspace_bytes": ([_c_i32, _c_i64, _c_i32], _c_size),
@@ -586,3 +593,58 @@ class CFState:
     @property
     def x_now(self):
         return self.x[self.cur]
+
+
+# --------------------------------------------------------------------------- betweenness centrality
+
+class BCState:
+    """Buffers for Brandes' betweenness centrality from sampled starts, with the
+    segmentation of the graph (forward levels) and of its reverse (backward)."""
+
+    def __init__(self, seg: Segments, seg_t: Segments):
+        import torch
+        dev = _dev()
+        V = seg.c.V
+        assert seg_t.c.V == V
+        self.seg, self.seg_t = seg, seg_t
+        self.depth = torch.empty(V, dtype=torch.int32, device=dev)
+        self.sigma = torch.empty(V, dtype=torch.float32, device=dev)
+        self.delta = torch.empty(V, dtype=torch.float32, device=dev)
+        self.bc = torch.zeros(V, dtype=torch.float32, device=dev)
+        self.vals = torch.empty(V, dtype=torch.float32, device=dev)
+        self.sums = torch.empty(V, dtype=torch.float32, device=dev)
+        self.partial = torch.empty(max(seg.Q, seg_t.Q, 1), dtype=torch.float32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        L = lib()
+        self.ws = torch.empty(max(L.cagra_bc_workspace_bytes(ctypes.byref(seg.c)),
+                                  L.cagra_bc_workspace_bytes(ctypes.byref(seg_t.c))), dtype=torch.uint8, device=dev)
+        self.levels = []
+
+    def add_source(self, source: int, stream=None):
+        """Forward levels until the frontier is empty (one count read-back per
+        level), then the backward levels; adds the start's dependencies to bc."""
+        L, st = lib(), _stream(stream)
+        V = self.seg.c.V
+        _check(L.cagra_bc_start(V, source, _ptr(self.depth), _ptr(self.sigma), _ptr(self.delta), st), "cagra_bc_start")
+        d = 0
+        while True:
+            _check(L.cagra_bc_forward_level(ctypes.byref(self.seg.c), d, _ptr(self.depth), _ptr(self.sigma),
+                                            _ptr(self.vals), _ptr(self.partial), _ptr(self.sums), _ptr(self.count),
+                                            _ptr(self.ws), self.ws.numel(), st), "cagra_bc_forward_level")
+            if int(self.count.item()) == 0:
+                break
+            d += 1
+        for dd in range(d - 1, -1, -1):
+            _check(L.cagra_bc_backward_level(ctypes.byref(self.seg_t.c), dd, source, _ptr(self.depth),
+                                             _ptr(self.sigma), _ptr(self.delta), _ptr(self.bc), _ptr(self.vals),
+                                             _ptr(self.partial), _ptr(self.sums), _ptr(self.ws), self.ws.numel(), st),
+                   "cagra_bc_backward_level")
+        self.levels.append(d + 1)
+
+
+def betweenness(seg: Segments, seg_t: Segments, sources):
+    """BC summed over the given starts (FP32 tensor [V])."""
+    st = BCState(seg, seg_t)
+    for s in sources:
+        st.add_source(int(s))
+    return st.bc, st.levels

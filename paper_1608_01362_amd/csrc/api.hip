@@ -25,6 +25,13 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
 cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws, size_t ws_bytes, hipStream_t st);
 bool gather_staged(int32_t N, int32_t value_type);
 cagra_status cluster_workspace_bytes(int32_t V, int64_t E, size_t *bytes);
+size_t bc_mask_words(const cagra_segments *seg);
+cagra_status launch_bc_start(int32_t V, int32_t source, int32_t *depth, float *sigma, float *delta, hipStream_t st);
+cagra_status launch_bc_forward(const cagra_segments *seg, int32_t d, int32_t *depth, float *sigma, float *vals,
+                               float *partial, float *sums, int32_t *count, uint32_t *mask, hipStream_t st);
+cagra_status launch_bc_backward(const cagra_segments *seg_t, int32_t d, int32_t source, const int32_t *depth,
+                                const float *sigma, float *delta, float *bc, float *vals, float *partial,
+                                float *sums, uint32_t *mask, hipStream_t st);
 cagra_status launch_edge_values(const cagra_graph *g, const cagra_segments *seg, const float *in_values,
                                  float *seg_values, hipStream_t st);
 cagra_status launch_cf_iter(const cagra_segments *seg, const float *seg_values, double gamma, double lambda,
@@ -171,6 +178,55 @@ cagra_status cagra_cf_iter(const cagra_graph *g, const cagra_segments *seg, cons
         return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", cagra_cf_workspace_bytes(seg),
                     workspace_bytes);
     return launch_cf_iter(seg, seg_values, gamma, lambda, x_in, partial, x_out, sq_out, (double *)workspace, stream);
+}
+
+size_t cagra_bc_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->k < 1) return 0;
+    return bc_mask_words(seg) * sizeof(uint32_t) + 256;
+}
+
+cagra_status cagra_bc_start(int32_t V, int32_t source, int32_t *depth, float *sigma, float *delta,
+                            hipStream_t stream) {
+    if (V < 1) return fail(CAGRA_E_INVALID, "V must be >= 1 (got %d)", V);
+    if (source < 0 || source >= V) return fail(CAGRA_E_INVALID, "source %d outside [0, %d)", source, V);
+    if (!depth || !sigma || !delta) return fail(CAGRA_E_INVALID, "depth, sigma or delta is NULL");
+    return launch_bc_start(V, source, depth, sigma, delta, stream);
+}
+
+static cagra_status check_bc(const cagra_segments *seg, const void *depth, const void *sigma, const void *vals,
+                             const void *partial, const void *sums, const void *workspace, size_t workspace_bytes) {
+    cagra_status s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (!depth || !sigma || !vals || !sums || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (merge_ordered_lds_bytes(seg->B, CAGRA_SUM_F32) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "merge block B=%d too large", seg->B);
+    if (!workspace || workspace_bytes < cagra_bc_workspace_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", cagra_bc_workspace_bytes(seg),
+                    workspace_bytes);
+    return CAGRA_OK;
+}
+
+cagra_status cagra_bc_forward_level(const cagra_segments *seg, int32_t d, int32_t *depth, float *sigma, float *vals,
+                                    float *partial, float *sums, int32_t *count, void *workspace,
+                                    size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_bc(seg, depth, sigma, vals, partial, sums, workspace, workspace_bytes)) != CAGRA_OK) return s;
+    if (!count) return fail(CAGRA_E_INVALID, "count is NULL");
+    if (d < 0) return fail(CAGRA_E_INVALID, "level %d < 0", d);
+    return launch_bc_forward(seg, d, depth, sigma, vals, partial, sums, count, (uint32_t *)workspace, stream);
+}
+
+cagra_status cagra_bc_backward_level(const cagra_segments *seg_t, int32_t d, int32_t source, const int32_t *depth,
+                                     const float *sigma, float *delta, float *bc, float *vals, float *partial,
+                                     float *sums, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_bc(seg_t, depth, sigma, vals, partial, sums, workspace, workspace_bytes)) != CAGRA_OK) return s;
+    if (!delta || !bc) return fail(CAGRA_E_INVALID, "delta or bc is NULL");
+    if (d < 0) return fail(CAGRA_E_INVALID, "level %d < 0", d);
+    if (source < 0 || source >= seg_t->V) return fail(CAGRA_E_INVALID, "source %d outside [0, %d)", source, seg_t->V);
+    return launch_bc_backward(seg_t, d, source, depth, sigma, delta, bc, vals, partial, sums, (uint32_t *)workspace,
+                              stream);
 }
 
 size_t cagra_cluster_workspace_bytes(int32_t V, int64_t E) {

@@ -268,12 +268,15 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
                                             const int32_t *__restrict__ tile_seg,
                                             const int32_t *__restrict__ span_row, const VT *__restrict__ values,
                                             int32_t V, int32_t N, int t, typename Op::T *__restrict__ partial,
-                                            unsigned char *smem) {
+                                            unsigned char *smem, const uint32_t *__restrict__ seg_active) {
     using T = typename Op::T;
     VT *seg_vals = reinterpret_cast<VT *>(smem + kStageBytes);
     const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
     if (e0 >= e1) return;  // empty tile (uniform over the workgroup)
     const int32_t s = tile_seg[t];
+    // an inactive segment (no source in the frontier) contributes nothing: its
+    // rows are skipped here and by the merge
+    if (seg_active && !((seg_active[s >> 5] >> (s & 31)) & 1u)) return;
     const int64_t vbase = (int64_t)s * N;
     const VT *gvals = values + vbase;
     if (STAGED) {
@@ -357,11 +360,12 @@ template <class Op, typename VT, bool STAGED, typename W>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
     const W *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
     const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
-    int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial) {
+    int32_t V, int32_t N, int32_t ntiles, typename Op::T *__restrict__ partial,
+    const uint32_t *__restrict__ seg_active) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     (void)E;
     gather_tile<Op, VT, STAGED, W>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
-                                xcd_remap(blockIdx.x, ntiles), partial, smem);
+                                   xcd_remap(blockIdx.x, ntiles), partial, smem, seg_active);
 }
 
 // Persistent form over many graphs: workgroups stride over a global tile list.
@@ -374,7 +378,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_multi_gather(const MultiDesc
         const int gi = tile_graph[gt];
         const MultiDesc &d = desc[gi];
         gather_tile<OpSum, float, true, uint16_t>(static_cast<const uint16_t *>(d.edge_src), d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
-                                        d.contrib[parity], d.V, d.N, (int)(gt - d.tile_base), d.partial, smem);
+                                        d.contrib[parity], d.V, d.N, (int)(gt - d.tile_base), d.partial, smem,
+                                        nullptr);
     }
 }
 
@@ -394,7 +399,7 @@ cagra_status launch_multi_gather(const MultiDesc *desc, const int32_t *tile_grap
 
 template <class Op, typename VT, bool STAGED, typename W>
 static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values, typename Op::T *partial,
-                                    hipStream_t st) {
+                                    const uint32_t *seg_active, hipStream_t st) {
     if (seg->ntiles == 0) return CAGRA_OK;
     auto kern = k_gather<Op, VT, STAGED, W>;
     const size_t lds = kStageBytes + (STAGED ? (size_t)seg->N * sizeof(VT) : 0);
@@ -405,7 +410,7 @@ static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values,
     }
     kern<<<seg->ntiles, kGatherThreads, lds, st>>>(static_cast<const W *>(seg->edge_src), seg->E, seg->Q,
                                                   seg->tile_edge, seg->tile_seg, seg->tile_span_row, values, seg->V,
-                                                  seg->N, seg->ntiles, partial);
+                                                  seg->N, seg->ntiles, partial, seg_active);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -414,14 +419,15 @@ static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values,
 // words; larger staged ones (BF16 values) and all unstaged ones use 32-bit words.
 template <class Op, typename VT, bool STAGED>
 static cagra_status launch_gather_t(const cagra_segments *seg, const VT *values, typename Op::T *partial,
-                                    hipStream_t st) {
+                                    const uint32_t *seg_active, hipStream_t st) {
     if constexpr (STAGED) {
-        if (edge16(seg->N)) return launch_gather_w<Op, VT, true, uint16_t>(seg, values, partial, st);
-        if constexpr (sizeof(VT) == 2) return launch_gather_w<Op, VT, true, uint32_t>(seg, values, partial, st);
+        if (edge16(seg->N)) return launch_gather_w<Op, VT, true, uint16_t>(seg, values, partial, seg_active, st);
+        if constexpr (sizeof(VT) == 2)
+            return launch_gather_w<Op, VT, true, uint32_t>(seg, values, partial, seg_active, st);
         return fail(CAGRA_E_INVALID, "internal: staged segment of %d vertices with 32-bit edge words", seg->N);
     } else {
         if (edge16(seg->N)) return fail(CAGRA_E_INVALID, "internal: unstaged segment of %d vertices", seg->N);
-        return launch_gather_w<Op, VT, false, uint32_t>(seg, values, partial, st);
+        return launch_gather_w<Op, VT, false, uint32_t>(seg, values, partial, seg_active, st);
     }
 }
 
@@ -431,22 +437,27 @@ bool gather_staged(int32_t N, int32_t value_type) {
     return (size_t)N * bytes <= CAGRA_STAGE_BYTES;
 }
 
-cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
-                           void *partial, hipStream_t st) {
+cagra_status launch_gather_active(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                                  void *partial, const uint32_t *seg_active, hipStream_t st) {
     const bool staged = gather_staged(seg->N, value_type);
     if (op == CAGRA_SUM_F32 && value_type == CAGRA_F32) {
-        return staged ? launch_gather_t<OpSum, float, true>(seg, (const float *)values, (float *)partial, st)
-                      : launch_gather_t<OpSum, float, false>(seg, (const float *)values, (float *)partial, st);
+        return staged ? launch_gather_t<OpSum, float, true>(seg, (const float *)values, (float *)partial, seg_active, st)
+                      : launch_gather_t<OpSum, float, false>(seg, (const float *)values, (float *)partial, seg_active, st);
     }
     if (op == CAGRA_SUM_F32 && value_type == CAGRA_BF16) {
-        return staged ? launch_gather_t<OpSum, uint16_t, true>(seg, (const uint16_t *)values, (float *)partial, st)
-                      : launch_gather_t<OpSum, uint16_t, false>(seg, (const uint16_t *)values, (float *)partial, st);
+        return staged ? launch_gather_t<OpSum, uint16_t, true>(seg, (const uint16_t *)values, (float *)partial, seg_active, st)
+                      : launch_gather_t<OpSum, uint16_t, false>(seg, (const uint16_t *)values, (float *)partial, seg_active, st);
     }
     if (op == CAGRA_MIN_I32 && value_type == CAGRA_I32) {
-        return staged ? launch_gather_t<OpMin, int32_t, true>(seg, (const int32_t *)values, (int32_t *)partial, st)
-                      : launch_gather_t<OpMin, int32_t, false>(seg, (const int32_t *)values, (int32_t *)partial, st);
+        return staged ? launch_gather_t<OpMin, int32_t, true>(seg, (const int32_t *)values, (int32_t *)partial, seg_active, st)
+                      : launch_gather_t<OpMin, int32_t, false>(seg, (const int32_t *)values, (int32_t *)partial, seg_active, st);
     }
     return fail(CAGRA_E_INVALID, "unsupported gather op %d / value type %d", op, value_type);
+}
+
+cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_type, const void *values,
+                           void *partial, hipStream_t st) {
+    return launch_gather_active(seg, op, value_type, values, partial, nullptr, st);
 }
 
 }  // namespace cagra

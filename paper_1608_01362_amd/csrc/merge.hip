@@ -42,7 +42,8 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict_
                                                       const int32_t *__restrict__ block_ptr,
                                                       const typename Op::T *__restrict__ partial, int32_t V,
                                                       int32_t k, int32_t B, int32_t nb,
-                                                      typename Op::T *__restrict__ out) {
+                                                      typename Op::T *__restrict__ out,
+                                                      const uint32_t *__restrict__ seg_active) {
     using T = typename Op::T;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T *acc = reinterpret_cast<T *>(smem);
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict_
     }
     __builtin_amdgcn_wave_barrier();
     for (int32_t s = 0; s < k; ++s) {
+        if (seg_active && !((seg_active[s >> 5] >> (s & 31)) & 1u)) continue;  // inactive subgraph: no rows
         const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
         for (int32_t i = lo + lane; i < hi; i += 64) {
             const int32_t d = (int32_t)(row_dst[i] - vb);
@@ -78,7 +80,8 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict_
 }
 
 template <class Op, bool COMP>
-static cagra_status launch_ordered(const cagra_segments *seg, const void *partial, void *out, hipStream_t st) {
+static cagra_status launch_ordered(const cagra_segments *seg, const void *partial, void *out,
+                                   const uint32_t *seg_active, hipStream_t st) {
     using T = typename Op::T;
     auto kern = k_merge_ordered<Op, COMP>;
     size_t lds = (size_t)seg->B * sizeof(T) * (COMP ? 2 : 1);
@@ -88,7 +91,7 @@ static cagra_status launch_ordered(const cagra_segments *seg, const void *partia
         attr_set = true;
     }
     kern<<<seg->nb, 64, lds, st>>>(seg->row_dst, seg->block_ptr, (const T *)partial, seg->V, seg->k, seg->B, seg->nb,
-                                   (T *)out);
+                                   (T *)out, seg_active);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -97,14 +100,19 @@ size_t merge_ordered_lds_bytes(int32_t B, int32_t op) {
     return (size_t)B * 4 * (op == CAGRA_SUM_F32_COMP ? 2 : 1);
 }
 
-cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st) {
+cagra_status launch_merge_active(const cagra_segments *seg, int32_t op, const void *partial, void *out,
+                                 const uint32_t *seg_active, hipStream_t st) {
     if (seg->nb == 0) return CAGRA_OK;
     switch (op) {
-        case CAGRA_SUM_F32: return launch_ordered<OpSum, false>(seg, partial, out, st);
-        case CAGRA_SUM_F32_COMP: return launch_ordered<OpSum, true>(seg, partial, out, st);
-        case CAGRA_MIN_I32: return launch_ordered<OpMin, false>(seg, partial, out, st);
+        case CAGRA_SUM_F32: return launch_ordered<OpSum, false>(seg, partial, out, seg_active, st);
+        case CAGRA_SUM_F32_COMP: return launch_ordered<OpSum, true>(seg, partial, out, seg_active, st);
+        case CAGRA_MIN_I32: return launch_ordered<OpMin, false>(seg, partial, out, seg_active, st);
         default: return fail(CAGRA_E_INVALID, "unknown merge op %d", op);
     }
+}
+
+cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st) {
+    return launch_merge_active(seg, op, partial, out, nullptr, st);
 }
 
 // ---------------------------------------------------------------- fused merges
