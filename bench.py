@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--no-clustered-line", action="store_true",
                     help="skip the extra measurement of the same graph after clustering")
     ap.add_argument("--workload", default="pagerank",
-                    choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart", "cluster", "cf", "bc"],
+                    choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart", "cluster", "cf", "bc", "push"],
                     help="pagerank: the headline line (default); the others measure the secondary "
                          "configurations and print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

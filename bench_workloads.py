@@ -22,6 +22,11 @@ bc          betweenness centrality (Brandes) from 12 sampled starts on R-MAT sca
             25 / ef 32 / seed 3, level-synchronous segmented pulls with the frontier
             as a mask of active segments (forward on the graph, backward on its
             reverse)
+push        push-direction segmenting (expand, per-piece LDS scatter, update):
+            PageRank on R-MAT scale 25 / ef 32 / seed 3 through the segmentation
+            of the reverse graph, segment sizes swept, against the pull iteration
+            on the same graph; label propagation on the symmetrized R-MAT 22
+            (push against pull, same segmentation)
 cluster     frequency-based clustering (Section 5) then segmenting, R-MAT scale 25
             / ef 32 / seed 3 (the headline graph): clustering time, expansion
             factor q, PageRank iteration time and time to L1 residual < 1e-6,
@@ -352,6 +357,81 @@ def bc(args, log):
             "dtype": "f32", "data": "synthetic"}
 
 
+def push(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    t0 = time.perf_counter()
+    g = graphgen.rmat_graph(25, 32, 3)
+    gt = graphgen.transpose(g)
+    log(f"graph and reverse in {time.perf_counter() - t0:.1f}s")
+    dg, dgt = cagra.DeviceGraph.from_host(g), cagra.DeviceGraph.from_host(gt)
+    V, E = g.V, g.E
+    del g, gt
+    steps = max(args.steps, 5)
+    sweep = {}
+    best = None
+    for N in (8192, 16384, 20480):
+        seg_t = cagra.build_segments(dgt, N, 8192, 262144)
+        st = cagra.PushPageRankState(dg, seg_t)
+        st.start()
+        ms = _time(st.step, steps)
+        sweep[N] = {"ms_per_iter": round(ms, 4), "GTEPS": round(E / ms / 1e6, 1), "k": seg_t.k,
+                    "q": round(seg_t.q, 3)}
+        log(f"push N={N}: {ms:.3f} ms/iter, q={seg_t.q:.3f}")
+        if best is None or ms < sweep[best]["ms_per_iter"]:
+            best = N
+        del st, seg_t
+        torch.cuda.empty_cache()
+    seg_t = cagra.build_segments(dgt, best, 8192, 262144)
+    r, res, it = cagra.pagerank_push(dg, seg_t, iters=100, tol=1e-6)
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    cagra.pagerank_push(dg, seg_t, iters=it)
+    b.record()
+    torch.cuda.synchronize()
+    conv_ms = a.elapsed_time(b)
+    del seg_t
+    seg = cagra.build_segments(dg, 32768, 8192, 262144)
+    stp = cagra.PageRankState(dg, seg)
+    stp.start()
+    pull_ms = _time(stp.step, steps)
+    log(f"pull N=32768: {pull_ms:.3f} ms/iter; push best N={best}: {sweep[best]['ms_per_iter']:.3f}")
+    del stp, seg, dg, dgt
+    torch.cuda.empty_cache()
+    # label propagation on the symmetrized R-MAT 22: push and pull on one segmentation
+    gs = graphgen.symmetrize(graphgen.rmat_graph(22, 16, 2))
+    dgs = cagra.DeviceGraph.from_host(gs)
+    segs = cagra.build_segments(dgs, 32768, 8192, 262144)
+    lab_push, it_push = cagra.labelprop_push(segs)
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    cagra.labelprop_push(segs)
+    b.record()
+    torch.cuda.synchronize()
+    lp_push_ms = a.elapsed_time(b)
+    a.record()
+    lab_pull, it_pull = cagra.labelprop(segs)
+    b.record()
+    torch.cuda.synchronize()
+    lp_pull_ms = a.elapsed_time(b)
+    assert torch.equal(lab_push, lab_pull) and it_push == it_pull
+    pm = sweep[best]["ms_per_iter"]
+    return {"metric": "GTEPS per push-direction PageRank iteration at R-MAT-25", "value": round(E / pm / 1e6, 1),
+            "unit": "GTEPS", "higher_is_better": True, "ms_per_iter": pm, "best_N": best, "sweep": sweep,
+            "pull_ms_per_iter": round(pull_ms, 4), "push_over_pull_time": round(pm / pull_ms, 3),
+            "iters_to_1e-6": it, "ms_to_1e-6": round(conv_ms, 2),
+            "labelprop_rmat22_sym": {"E_sym": gs.E, "iterations": it_push, "push_ms": round(lp_push_ms, 2),
+                                     "pull_ms": round(lp_pull_ms, 2),
+                                     "push_GTEPS": round(gs.E * it_push / lp_push_ms / 1e6, 1),
+                                     "pull_GTEPS": round(gs.E * it_pull / lp_pull_ms / 1e6, 1)},
+            "config": {"workload": "pagerank_push_rmat25_ef32_seed3", "V": V, "E": E, "B": 8192,
+                       "tile_edges": 262144},
+            "dtype": "f32", "data": "synthetic"}
+
+
 def run(name, args, log):
     return {"labelprop": labelprop, "ppr": ppr, "multigraph": multigraph, "warmstart": warmstart,
-            "cluster": cluster, "cf": cf, "bc": bc}[name](args, log)
+            "cluster": cluster, "cf": cf, "bc": bc, "push": push}[name](args, log)

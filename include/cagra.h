@@ -239,6 +239,49 @@ cagra_status cagra_bc_backward_level(const cagra_segments *seg_t, int32_t d, int
                                      const float *sigma, float *delta, float *bc, float *vals, float *partial,
                                      float *sums, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Push-direction segmenting: the out-edge traversal cut into segments (the
+ * alternative to the in-edge pull that Section 3 mentions and Section 4's
+ * EdgeMap allows). seg_t is the segmentation of the REVERSE graph (built with
+ * cagra_build_segments from the out-edge lists written as a CSC; for an
+ * undirected graph that is the graph itself): its subgraph s holds the edges
+ * u -> v with v in segment s, rows are sources u. An iteration
+ *   1. expands: vals[i] = x[row_dst[i]] for every row i of seg_t, block by
+ *      block of sources (the merge's access pattern run backwards),
+ *   2. scatters: one workgroup per piece (a run of one subgraph's tiles)
+ *      adds each edge's row value to its destination's accumulator in LDS,
+ *      then writes the accumulators to the piece's slot,
+ *   3. updates each vertex from its segment's slots.
+ * Sums are exact (each FP32 value rounded to a multiple of 2^-56, added as
+ * int64; |sums| < 64), minima exact, so results are bit-identical run to run.
+ * Requirements: seg_t->N * 8 <= CAGRA_LDS_BYTES for PageRank (N <= 20,480),
+ * seg_t->N * 4 <= CAGRA_LDS_BYTES for label propagation, and
+ * 4*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES. The workspace (plan, per-block sums
+ * and one slot of N 8-byte accumulators per piece) carries no state between
+ * calls.
+ */
+size_t cagra_push_workspace_bytes(const cagra_segments *seg_t);
+
+/*
+ * One PageRank iteration in the push direction: same formula, scalars and
+ * start (cagra_pagerank_init with CAGRA_F32) as cagra_pagerank_iter; FP32
+ * contributions. g is the graph itself (out_degree), seg_t the segmentation
+ * of its reverse; vals is float[seg_t->Q] scratch.
+ */
+cagra_status cagra_pagerank_push_iter(const cagra_graph *g, const cagra_segments *seg_t, double damping,
+                                      const float *rank_in, const float *contrib_in, const double *scalars_in,
+                                      float *vals, float *rank_out, float *contrib_out, double *scalars_out,
+                                      void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * One min-label propagation step in the push direction (same result as
+ * cagra_labelprop_iter): every edge u -> v offers labels_in[u] to v.
+ * vals is int32[seg_t->Q] scratch; *changed_out = number of labels changed.
+ */
+cagra_status cagra_labelprop_push_iter(const cagra_segments *seg_t, const int32_t *labels_in, int32_t *vals,
+                                       int32_t *labels_out, int32_t *changed_out, void *workspace,
+                                       size_t workspace_bytes, hipStream_t stream);
+
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 

@@ -49,6 +49,7 @@ EXPORTS = [
     "cagra_cf_workspace_bytes", "cagra_cf_iter", "cagra_bc_workspace_bytes", "cagra_bc_start",
     "cagra_bc_forward_level", "cagra_bc_backward_level", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
+    "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
@@ -110,6 +111,10 @@ def lib():
             "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_push_workspace_bytes": ([SP], _c_size),
+            "cagra_pagerank_push_iter": ([GP, SP, _c_dbl, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                          _c_size, st], ctypes.c_int),
+            "cagra_labelprop_push_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_ppr_workspace_bytes": ([SP], _c_size),
             "cagra_features_workspace_bytes": ([SP], _c_size),
             "cagra_degree_features": ([GP, SP, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
@@ -419,6 +424,103 @@ def labelprop(seg: Segments, max_iters: int = 1 << 20):
     cur, it = 0, 0
     while it < max_iters:
         labelprop_iter(seg, lab[cur], partial, lab[1 - cur], changed, ws)
+        cur = 1 - cur
+        it += 1
+        if int(changed.item()) == 0:
+            break
+    return lab[cur], it
+
+
+# --------------------------------------------------------------------------- push direction
+
+def push_workspace(seg_t: Segments):
+    import torch
+    n = lib().cagra_push_workspace_bytes(ctypes.byref(seg_t.c))
+    return torch.empty(n, dtype=torch.uint8, device=_dev())
+
+
+def pagerank_push_iter(dg: DeviceGraph, seg_t: Segments, damping: float, rank_in, contrib_in, scalars_in, vals,
+                       rank_out, contrib_out, scalars_out, workspace, stream=None):
+    _check(lib().cagra_pagerank_push_iter(ctypes.byref(dg.c), ctypes.byref(seg_t.c), damping, _ptr(rank_in),
+                                          _ptr(contrib_in), _ptr(scalars_in), _ptr(vals), _ptr(rank_out),
+                                          _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace), workspace.numel(),
+                                          _stream(stream)), "cagra_pagerank_push_iter")
+
+
+def labelprop_push_iter(seg_t: Segments, labels_in, vals, labels_out, changed_out, workspace, stream=None):
+    _check(lib().cagra_labelprop_push_iter(ctypes.byref(seg_t.c), _ptr(labels_in), _ptr(vals), _ptr(labels_out),
+                                           _ptr(changed_out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "cagra_labelprop_push_iter")
+
+
+class PushPageRankState:
+    """PageRank power iteration in the push direction: dg is the graph, seg_t
+    the segmentation of its reverse (FP32 contributions)."""
+
+    def __init__(self, dg: DeviceGraph, seg_t: Segments):
+        import torch
+        dev = _dev()
+        V = dg.V
+        self.dg, self.seg_t = dg, seg_t
+        self.rank = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.contrib = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.scalars = [torch.zeros(4, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.vals = torch.empty(max(seg_t.Q, 1), dtype=torch.float32, device=dev)
+        self.ws = push_workspace(seg_t)
+        self.cur = 0
+
+    def start(self, rank0=None, stream=None):
+        if rank0 is None:
+            self.rank[0].fill_(1.0 / self.dg.V)
+        else:
+            self.rank[0].copy_(rank0)
+        self.cur = 0
+        pagerank_init(self.dg, F32, self.rank[0], self.contrib[0], self.scalars[0], self.ws, stream)
+
+    def step(self, damping: float = 0.85, stream=None):
+        a, b = self.cur, 1 - self.cur
+        pagerank_push_iter(self.dg, self.seg_t, damping, self.rank[a], self.contrib[a], self.scalars[a], self.vals,
+                           self.rank[b], self.contrib[b], self.scalars[b], self.ws, stream)
+        self.cur = b
+
+    @property
+    def rank_now(self):
+        return self.rank[self.cur]
+
+    @property
+    def scalars_now(self):
+        return self.scalars[self.cur]
+
+
+def pagerank_push(dg: DeviceGraph, seg_t: Segments, iters: int = 20, damping: float = 0.85, tol: float = 0.0):
+    """Push-direction power iteration; returns (rank tensor, residual list or None, steps)."""
+    stt = PushPageRankState(dg, seg_t)
+    stt.start()
+    res, steps = [], 0
+    for _ in range(iters):
+        stt.step(damping)
+        steps += 1
+        if tol > 0:
+            r = float(stt.scalars_now[1].item())
+            res.append(r)
+            if r < tol:
+                break
+    return stt.rank_now.clone(), (res if tol > 0 else None), steps
+
+
+def labelprop_push(seg_t: Segments, max_iters: int = 1 << 20):
+    """Min-label propagation to the fixed point in the push direction (seg_t: the
+    segmentation of the reverse graph, the graph itself when undirected)."""
+    import torch
+    dev = _dev()
+    V = seg_t.c.V
+    lab = [torch.arange(V, dtype=torch.int32, device=dev), torch.empty(V, dtype=torch.int32, device=dev)]
+    vals = torch.empty(max(seg_t.Q, 1), dtype=torch.int32, device=dev)
+    changed = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = push_workspace(seg_t)
+    cur, it = 0, 0
+    while it < max_iters:
+        labelprop_push_iter(seg_t, lab[cur], vals, lab[1 - cur], changed, ws)
         cur = 1 - cur
         it += 1
         if int(changed.item()) == 0:

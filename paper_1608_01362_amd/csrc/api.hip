@@ -77,6 +77,15 @@ cagra_status launch_adam(float *master, uint16_t *wb, float *m, float *v, const 
 size_t softmax_ws_bytes(int32_t V);
 cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st);
 
+size_t push_ws_bytes(const cagra_segments *seg);
+size_t push_expand_lds_total(int32_t B, int32_t k);
+int64_t push_max_pieces(const cagra_segments *seg);
+cagra_status launch_pr_push(const cagra_graph *g, const cagra_segments *seg, double damping, const float *rank_in,
+                            const float *contrib_in, const double *scalars_in, float *vals, float *rank_out,
+                            float *contrib_out, double *scalars_out, void *workspace, hipStream_t st);
+cagra_status launch_lp_push(const cagra_segments *seg, const int32_t *labels_in, int32_t *vals, int32_t *labels_out,
+                            int32_t *changed_out, void *workspace, hipStream_t st);
+
 static constexpr int32_t kMaxSegments = 32768;
 static constexpr int32_t kMaxPprBlock = 512;
 static constexpr int32_t kMaxMergeBlock = 16384;
@@ -472,6 +481,52 @@ cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, dou
                     workspace_bytes);
     return launch_ppr_iter(g, seg, damping, ncols, seeds, rank_in, contrib_in, scalars_in, partial, rank_out,
                            contrib_out, scalars_out, (double *)workspace, stream);
+}
+
+size_t cagra_push_workspace_bytes(const cagra_segments *seg_t) {
+    if (!seg_t || seg_t->V < 1 || seg_t->N < 1 || seg_t->k < 1 || seg_t->E < 0) return 0;
+    return push_ws_bytes(seg_t);
+}
+
+static cagra_status check_push(const cagra_segments *seg, int acc_bytes, const void *vals, size_t workspace_bytes,
+                               const void *workspace) {
+    cagra_status s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if ((int64_t)seg->N * acc_bytes > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "push accumulators of N=%d vertices exceed the LDS (N * %d > %d)", seg->N,
+                    acc_bytes, CAGRA_LDS_BYTES);
+    if (push_expand_lds_total(seg->B, seg->k) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the expand kernel's LDS", seg->B, seg->k);
+    if (push_max_pieces(seg) > INT32_MAX / 2) return fail(CAGRA_E_OVERFLOW, "too many push pieces");
+    if (seg->Q > 0 && !vals) return fail(CAGRA_E_INVALID, "vals is NULL");
+    if (!workspace || workspace_bytes < push_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", push_ws_bytes(seg), workspace_bytes);
+    return CAGRA_OK;
+}
+
+cagra_status cagra_pagerank_push_iter(const cagra_graph *g, const cagra_segments *seg_t, double damping,
+                                      const float *rank_in, const float *contrib_in, const double *scalars_in,
+                                      float *vals, float *rank_out, float *contrib_out, double *scalars_out,
+                                      void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_push(seg_t, 8, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (seg_t->V != g->V || seg_t->E != g->E)
+        return fail(CAGRA_E_INVALID, "segments belong to a graph of another size");
+    if (!(damping >= 0.0 && damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
+    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out)
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    return launch_pr_push(g, seg_t, damping, rank_in, contrib_in, scalars_in, vals, rank_out, contrib_out,
+                          scalars_out, workspace, stream);
+}
+
+cagra_status cagra_labelprop_push_iter(const cagra_segments *seg_t, const int32_t *labels_in, int32_t *vals,
+                                       int32_t *labels_out, int32_t *changed_out, void *workspace,
+                                       size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_push(seg_t, 4, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (!labels_in || !labels_out || !changed_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    return launch_lp_push(seg_t, labels_in, vals, labels_out, changed_out, workspace, stream);
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@
 // wave order. No atomics; the combination order is fixed by the data layout,
 // so results are bit-identical run to run.
 #include "common.h"
+#include "wave.h"
 
 namespace cagra {
 
@@ -90,37 +91,6 @@ __device__ __forceinline__ void stage_segment(const VT *__restrict__ g, int32_t 
     }
 }
 
-// ---- wave-level scans with DPP (row shifts within 16 lanes, then row broadcasts)
-constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
-
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int32_t dpp_i(int32_t old, int32_t x) {
-    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_f(float old, float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWMASK, 0xf,
-                                                      false));
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int32_t dpp_t(int32_t old, int32_t x) { return dpp_i<CTRL, ROWMASK>(old, x); }
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_t(float old, float x) { return dpp_f<CTRL, ROWMASK>(old, x); }
-
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ void add_step(int32_t &x) { x += dpp_i<CTRL, ROWMASK>(0, x); }
-
-__device__ __forceinline__ int32_t wave_incl_sum(int32_t x) {
-    add_step<kDppRowShr1, 0xf>(x);
-    add_step<kDppRowShr2, 0xf>(x);
-    add_step<kDppRowShr4, 0xf>(x);
-    add_step<kDppRowShr8, 0xf>(x);
-    add_step<kDppRowBcast15, 0xa>(x);
-    add_step<kDppRowBcast31, 0xc>(x);
-    return x;
-}
-
 // One step of the segmented scan (flag f, value v): a lane keeps its value if
 // it holds a row start, else prepends the value of the lanes before it.
 template <class Op, int CTRL, int ROWMASK>
@@ -146,10 +116,6 @@ __device__ __forceinline__ int32_t readlane_t(int32_t x, int l) { return __built
 __device__ __forceinline__ float readlane_t(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
-
-constexpr int32_t kBufFlags = 0x00020000;   // raw buffer descriptor word 3 (gfx9)
-constexpr int kNonTemporal = 2;             // cache policy: streaming
-constexpr uint32_t kOutOfRange = 0x80000000u;
 
 // Per-wave state carried from chunk to chunk.
 template <typename T>

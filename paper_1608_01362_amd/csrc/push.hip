@@ -1,0 +1,510 @@
+// Push-direction segmenting: the out-edge traversal cut into segments, the
+// option Section 3 leaves open next to the pull (in-edge) version it builds.
+//
+// The segmentation of the reverse graph is the push layout of the graph:
+// subgraph s holds every edge u -> v whose destination v lies in segment s,
+// in rows of ascending source u (row_dst[i] = u), and each edge word carries
+// the local destination v - s*N. One iteration has three steps:
+//
+//  1. Expand, the mirror image of the cache-aware merge (Section 3.3): every
+//     row takes its source's value, vals[i] = x[row_dst[i]]. Sources are cut
+//     into blocks of B vertices; a block's values are staged in LDS once and
+//     each subgraph's rows of that block are written sequentially, so x is
+//     read once and the random reads hit LDS.
+//  2. Scatter, the mirror image of segment processing (Section 3.2): a
+//     workgroup takes a piece (a run of consecutive tiles of one subgraph) and
+//     keeps the accumulators of that subgraph's destination segment in LDS;
+//     each edge adds its row's value to its destination with an LDS atomic.
+//     Sums are int64 fixed point (every FP32 value rounded to a multiple of
+//     2^-56) and minima are exact, so no result depends on the order of the
+//     atomics. A piece's finished accumulators leave as one sequential slot.
+//  3. Update: each vertex combines the slots of its segment's pieces and
+//     applies the vertex update (PageRank, or label propagation).
+//
+// Pieces: a subgraph with E_s edges is cut into ceil(E_s / cap) runs of its
+// tiles (at most one per tile); cap is twice the mean subgraph size, capped so
+// that a small graph still yields about 1024 pieces. The plan is rebuilt by
+// one small kernel at the start of every call, so the workspace holds no
+// state between calls.
+#include <math.h>
+
+#include "blockwalk.h"
+#include "common.h"
+#include "wave.h"
+
+namespace cagra {
+
+cagra_status launch_reduce4(const double *blk, int32_t n, double *out, hipStream_t st);
+cagra_status launch_reduce_i32(const int32_t *blk, int32_t n, int32_t *out, hipStream_t st);
+
+constexpr int kPushWaves = CAGRA_TILE_WAVES;  // tiles carry one starting row per wave
+constexpr int kPushThreads = kPushWaves * kWave;
+constexpr int kPushEPT = 8;                   // edges per lane per chunk
+constexpr int kPushChunk = kWave * kPushEPT;
+constexpr int kPushStages = 3;                // chunks of edge words in flight per wave
+constexpr int kPlanThreads = 1024;
+constexpr int kUpdSpan = 4096;                // vertices per update workgroup
+constexpr int kUpdThreads = 256;
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ plan
+
+// First tile of subgraph s or later (tile_seg is non-decreasing); ntiles if none.
+__device__ __forceinline__ int32_t first_tile_of(const int32_t *__restrict__ tile_seg, int32_t ntiles, int32_t s) {
+    int32_t lo = 0, hi = ntiles;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (tile_seg[mid] < s) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct PieceRange {
+    int32_t t0, nt, np;
+};
+
+__device__ __forceinline__ PieceRange pieces_of(const int32_t *__restrict__ tile_seg,
+                                                const int32_t *__restrict__ tile_edge, int32_t ntiles, int32_t s,
+                                                int64_t cap) {
+    PieceRange r;
+    r.t0 = first_tile_of(tile_seg, ntiles, s);
+    const int32_t t1 = first_tile_of(tile_seg, ntiles, s + 1);
+    r.nt = t1 - r.t0;
+    r.np = 0;
+    if (r.nt > 0) {
+        const int64_t es = (int64_t)tile_edge[t1] - tile_edge[r.t0];
+        int64_t p = (es + cap - 1) / cap;
+        if (p < 1) p = 1;
+        if (p > r.nt) p = r.nt;
+        r.np = (int32_t)p;
+    }
+    return r;
+}
+
+// One workgroup: pfirst[s] = first piece of subgraph s (pfirst[k] = piece
+// count), and per piece its first tile and subgraph; piece_tile[count] =
+// ntiles closes the last piece. Subgraphs without tiles get no piece.
+__global__ __launch_bounds__(kPlanThreads) void k_push_plan(const int32_t *__restrict__ tile_seg,
+                                                            const int32_t *__restrict__ tile_edge, int32_t ntiles,
+                                                            int32_t k, int64_t cap, int32_t *__restrict__ pfirst,
+                                                            int32_t *__restrict__ piece_tile,
+                                                            int32_t *__restrict__ piece_seg) {
+    __shared__ int32_t tmp[kPlanThreads / kWave];
+    const int32_t per = (k + kPlanThreads - 1) / kPlanThreads;
+    const int32_t lo = threadIdx.x * per, hi = min(lo + per, k);
+    int32_t sum = 0;
+    for (int32_t s = lo; s < hi; ++s) sum += pieces_of(tile_seg, tile_edge, ntiles, s, cap).np;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t incl = sum;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[w] = incl;
+    __syncthreads();
+    int32_t base = incl - sum;
+    for (int i = 0; i < w; ++i) base += tmp[i];
+    for (int32_t s = lo; s < hi; ++s) {
+        const PieceRange r = pieces_of(tile_seg, tile_edge, ntiles, s, cap);
+        pfirst[s] = base;
+        for (int32_t j = 0; j < r.np; ++j) {
+            piece_tile[base + j] = r.t0 + (int32_t)((int64_t)r.nt * j / r.np);
+            piece_seg[base + j] = s;
+        }
+        base += r.np;
+    }
+    if (threadIdx.x == kPlanThreads - 1) {
+        int32_t total = 0;
+        for (int i = 0; i < kPlanThreads / kWave; ++i) total += tmp[i];
+        pfirst[k] = total;
+        piece_tile[total] = ntiles;
+    }
+}
+
+// ------------------------------------------------------------------ expand
+
+// vals[i] = x[row_dst[i]] for the rows of source block b, item j of its S
+// items (the block's rows flattened over subgraphs, cut into S equal parts).
+template <bool WIDE>
+__global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *__restrict__ row_dst_lo,
+                                                               const int32_t *__restrict__ block_ptr,
+                                                               const int32_t *__restrict__ block_items,
+                                                               const uint32_t *__restrict__ x, int32_t V, int32_t k,
+                                                               int32_t B, int32_t nb, uint32_t *__restrict__ vals) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int32_t tmp[16];
+    const int32_t total = block_items[nb];
+    if ((int32_t)blockIdx.x >= total) return;  // the grid is the bound max_items
+    const int32_t it = blockIdx.x;
+    const int32_t b = block_of_item(block_items, nb, it);
+    const int32_t j = it - block_items[b], S = block_items[b + 1] - block_items[b];
+    uint32_t *xs = reinterpret_cast<uint32_t *>(smem);
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
+    int32_t *pre = lo_s + k;
+
+    const int64_t vb = (int64_t)b * B;
+    const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
+    for (int i = threadIdx.x; i < nv; i += kMergeThreads) xs[i] = x[vb + i];
+    // the barrier inside load_block_ranges also publishes the staged values
+    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+    const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
+
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int32_t share = ((((F1 - F0) + 15) / 16) + 63) & ~63;
+    const int32_t fa = min(F0 + w * share, F1), fb = min(fa + share, F1);
+    for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
+        int32_t sl = run_of(pre, k, f0);
+        int32_t idx[kUnroll], d[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t f = f0 + u * kWave + lane;
+            const bool valid = f < fb;
+            const int32_t ff = valid ? f : f0;
+            sl = advance<WIDE>(pre, k, sl, ff);
+            const int32_t i = lo_s[sl] + (ff - pre[sl]);
+            d[u] = (int32_t)row_dst_lo[i];
+            idx[u] = valid ? i : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (idx[u] >= 0) vals[idx[u]] = xs[d[u]];
+    }
+}
+
+// ------------------------------------------------------------------ scatter
+
+struct PushSum {  // float values, exact int64 fixed-point sums
+    using V = float;
+    using A = unsigned long long;
+    static __device__ __forceinline__ A identity() { return 0ull; }
+    static __device__ __forceinline__ void add(A *acc, int32_t d, uint32_t bits) {
+        atomicAdd(&acc[d], fix56(__uint_as_float(bits)));
+    }
+};
+struct PushMin {  // int32 values, minimum
+    using V = int32_t;
+    using A = int32_t;
+    static __device__ __forceinline__ A identity() { return 0x7fffffff; }
+    static __device__ __forceinline__ void add(A *acc, int32_t d, uint32_t bits) { atomicMin(&acc[d], (int32_t)bits); }
+};
+
+template <typename W>
+constexpr int kPushLoads = kPushEPT * (int)sizeof(W) / 16;
+
+template <typename W>
+__device__ __forceinline__ void push_load_chunk(v4i (&r)[kPushLoads<W>], __amdgpu_buffer_rsrc_t ein, uint32_t off) {
+#pragma unroll
+    for (int j = 0; j < kPushLoads<W>; ++j)
+        r[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, off + 16 * j, 0, kNonTemporal);
+}
+
+// One chunk of a wave's share: this lane's kPushEPT consecutive edge words.
+// rel0 = the chunk's first edge relative to the share (negative for a first
+// chunk that starts before it); nfl = row starts seen in earlier chunks. The
+// row of an edge is row_before + (row starts in the share up to and including
+// it); vin is addressed relative to base_row.
+template <class PO, typename W>
+__device__ __forceinline__ void push_chunk(const v4i (&wv)[kPushLoads<W>], int32_t rel0, int32_t share,
+                                           int32_t row_off, __amdgpu_buffer_rsrc_t vin, typename PO::A *acc,
+                                           int32_t &nfl) {
+    const int lane = threadIdx.x & 63;
+    uint32_t wd[kPushEPT];
+    if constexpr (sizeof(W) == 4) {
+#pragma unroll
+        for (int j = 0; j < kPushLoads<W>; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wd[4 * j + c] = (uint32_t)wv[j][c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            wd[2 * c] = (uint32_t)wv[0][c] & 0xffffu;
+            wd[2 * c + 1] = (uint32_t)wv[0][c] >> 16;
+        }
+    }
+    const int32_t rel = rel0 + lane * kPushEPT;
+    bool valid[kPushEPT];
+    int32_t nf = 0;
+#pragma unroll
+    for (int i = 0; i < kPushEPT; ++i) {
+        valid[i] = (uint32_t)(rel + i) < (uint32_t)share;
+        nf += (valid[i] && (wd[i] & EdgeWord<W>::kFlag)) ? 1 : 0;
+    }
+    const int32_t incl = wave_incl_sum(nf);
+    const int32_t chunk_nf = __builtin_amdgcn_readlane(incl, 63);
+    int32_t r = row_off + nfl + (incl - nf);  // row of the edge before this lane's first, relative to base_row
+    uint32_t xv[kPushEPT];
+#pragma unroll
+    for (int i = 0; i < kPushEPT; ++i) {
+        r += (valid[i] && (wd[i] & EdgeWord<W>::kFlag)) ? 1 : 0;
+        const uint32_t off = valid[i] ? (uint32_t)r * 4u : kOutOfRange;
+        xv[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(vin, off, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < kPushEPT; ++i)
+        if (valid[i]) PO::add(acc, (int32_t)(wd[i] & EdgeWord<W>::kIndex), xv[i]);
+    nfl += chunk_nf;
+}
+
+// One workgroup per piece: accumulate the piece's edges into the destination
+// segment's LDS accumulators, then write them to the piece's slot.
+template <class PO, typename W>
+__global__ __launch_bounds__(kPushThreads) void k_push_scatter(
+    const W *__restrict__ edge_src, int64_t Q, const int32_t *__restrict__ tile_edge,
+    const int32_t *__restrict__ span_row, const uint32_t *__restrict__ vals, int32_t V, int32_t N,
+    const int32_t *__restrict__ pfirst, int32_t k, const int32_t *__restrict__ piece_tile,
+    const int32_t *__restrict__ piece_seg, typename PO::A *__restrict__ slots) {
+    using A = typename PO::A;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    A *acc = reinterpret_cast<A *>(smem);
+    const int32_t np = pfirst[k];
+    const int32_t p = blockIdx.x;
+    if (p >= np) return;  // the grid is a bound on the piece count
+    const int32_t s = piece_seg[p], t0 = piece_tile[p], t1 = piece_tile[p + 1];
+    const int64_t vbase = (int64_t)s * N;
+    const int32_t n = (int32_t)((int64_t)V - vbase < N ? (int64_t)V - vbase : N);
+    for (int i = threadIdx.x; i < n; i += kPushThreads) acc[i] = PO::identity();
+    __syncthreads();
+
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    constexpr int kWB = (int)sizeof(W);
+    const uint32_t lane_off = (uint32_t)(lane * kPushEPT * kWB);
+    for (int32_t t = t0; t < t1; ++t) {
+        const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
+        const int64_t sl = (e1 - e0 + kPushWaves - 1) / kPushWaves;
+        int64_t w0 = e0 + w * sl;
+        if (w0 > e1) w0 = e1;
+        int64_t w1 = w0 + sl;
+        if (w1 > e1) w1 = e1;
+        if (w0 >= w1) continue;  // uniform over the wave
+        // the share's edges before its first row start belong to row row_before
+        const int32_t row_before = span_row[(int64_t)t * kPushWaves + w] - 1;
+        const int32_t base_row = row_before > 0 ? row_before : 0;
+        const int32_t share = (int32_t)(w1 - w0);
+        const int64_t ebase = w0 & ~(int64_t)(16 / kWB - 1);
+        const __amdgpu_buffer_rsrc_t ein = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(edge_src + ebase), 0, (int32_t)align_up((size_t)(w1 - ebase) * kWB, 4), kBufFlags);
+        // rows of the share: row_before .. row_before + share
+        int64_t nrows = Q - base_row;
+        if (nrows > (int64_t)share + 1) nrows = (int64_t)share + 1;
+        const __amdgpu_buffer_rsrc_t vin = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(vals + base_row), 0, (int32_t)(nrows * 4), kBufFlags);
+        const int32_t row_off = row_before - base_row;  // -1 or 0
+        const int64_t len = w1 - ebase;
+        int32_t nfl = 0;
+        v4i R[kPushStages][kPushLoads<W>];
+#pragma unroll
+        for (int c = 0; c < kPushStages - 1; ++c)
+            push_load_chunk<W>(R[c], ein, (uint32_t)(c * kPushChunk * kWB) + lane_off);
+        for (int64_t cc = 0; cc < len; cc += kPushStages * kPushChunk) {
+#pragma unroll
+            for (int c = 0; c < kPushStages; ++c) {
+                if (cc + c * kPushChunk >= len) break;  // uniform
+                push_load_chunk<W>(R[(c + kPushStages - 1) % kPushStages], ein,
+                                   (uint32_t)((cc + (c + kPushStages - 1) * kPushChunk) * kWB) + lane_off);
+                const int32_t rel0 = (int32_t)(ebase + cc + c * kPushChunk - w0);
+                push_chunk<PO, W>(R[c], rel0, share, row_off, vin, acc, nfl);
+            }
+        }
+    }
+    __syncthreads();
+    A *out = slots + (int64_t)p * N;
+    for (int i = threadIdx.x; i < n; i += kPushThreads) out[i] = acc[i];
+}
+
+// ------------------------------------------------------------------ update
+
+__global__ __launch_bounds__(kUpdThreads) void k_push_pr_update(
+    const unsigned long long *__restrict__ slots, const int32_t *__restrict__ pfirst, int32_t V, int32_t N,
+    const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
+    double damping, float *__restrict__ rank_out, float *__restrict__ contrib_out, double *__restrict__ blk) {
+    __shared__ double red[kUpdThreads / kWave];
+    const double dd = damping;
+    const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
+    const int64_t lo = (int64_t)blockIdx.x * kUpdSpan;
+    const int64_t hi = lo + kUpdSpan < V ? lo + kUpdSpan : V;
+    double dang = 0.0, res = 0.0, mass = 0.0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kUpdThreads) {
+        const int32_t s = (int32_t)(v / N);
+        const int64_t i = v - (int64_t)s * N;
+        unsigned long long a = 0ull;
+        for (int32_t p = pfirst[s]; p < pfirst[s + 1]; ++p) a += slots[(int64_t)p * N + i];
+        const double sum = (double)(long long)a * kFixInv;
+        const float r = (float)(base + dd * sum);
+        rank_out[v] = r;
+        const int32_t od = outdeg[v];
+        contrib_out[v] = od > 0 ? r / (float)od : 0.0f;
+        if (od == 0) dang += (double)r;
+        res += fabs((double)r - (double)rank_in[v]);
+        mass += (double)r;
+    }
+    dang = block_sum_f64<kUpdThreads>(dang, red);
+    res = block_sum_f64<kUpdThreads>(res, red);
+    mass = block_sum_f64<kUpdThreads>(mass, red);
+    if (threadIdx.x == 0) {
+        blk[(int64_t)blockIdx.x * 4 + 0] = dang;
+        blk[(int64_t)blockIdx.x * 4 + 1] = res;
+        blk[(int64_t)blockIdx.x * 4 + 2] = mass;
+        blk[(int64_t)blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kUpdThreads) void k_push_lp_update(const int32_t *__restrict__ slots,
+                                                                const int32_t *__restrict__ pfirst, int32_t V,
+                                                                int32_t N, const int32_t *__restrict__ labels_in,
+                                                                int32_t *__restrict__ labels_out,
+                                                                int32_t *__restrict__ blk) {
+    __shared__ int32_t red[kUpdThreads / kWave];
+    const int64_t lo = (int64_t)blockIdx.x * kUpdSpan;
+    const int64_t hi = lo + kUpdSpan < V ? lo + kUpdSpan : V;
+    int32_t changed = 0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kUpdThreads) {
+        const int32_t s = (int32_t)(v / N);
+        const int64_t i = v - (int64_t)s * N;
+        const int32_t old = labels_in[v];
+        int32_t m = old;
+        for (int32_t p = pfirst[s]; p < pfirst[s + 1]; ++p) m = min(m, slots[(int64_t)p * N + i]);
+        labels_out[v] = m;
+        changed += m != old ? 1 : 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) changed += __shfl_down(changed, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = changed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int i = 0; i < kUpdThreads / kWave; ++i) t += red[i];
+        blk[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+int64_t push_piece_cap(const cagra_segments *seg) {
+    int64_t cap = ceil_div(2 * seg->E, seg->k);
+    const int64_t fill = ceil_div(seg->E, 1024);
+    if (fill < cap) cap = fill;
+    if (cap < 4096) cap = 4096;
+    return cap;
+}
+int64_t push_max_pieces(const cagra_segments *seg) { return (int64_t)seg->k + ceil_div(seg->E, push_piece_cap(seg)); }
+int32_t push_update_blocks(int32_t V) { return (int32_t)ceil_div(V, kUpdSpan); }
+
+// LDS of the expand kernel: staged block values and the block's range starts
+// and prefix (plus the static scan scratch).
+size_t push_expand_lds_bytes(int32_t B, int32_t k) {
+    return align_up((size_t)B * 4, 16) + (size_t)(2 * (int64_t)k + 2) * sizeof(int32_t) + 64;
+}
+size_t push_expand_lds_total(int32_t B, int32_t k) { return push_expand_lds_bytes(B, k) + 256; }
+
+// Workspace: plan (pfirst, piece_tile, piece_seg), per-block partials of the
+// update, then the piece slots (8 bytes per vertex of a piece's segment).
+struct PushWs {
+    int32_t *pfirst, *piece_tile, *piece_seg;
+    void *blk;
+    void *slots;
+};
+
+static size_t push_layout(const cagra_segments *seg, char *base, PushWs *ws) {
+    const int64_t maxp = push_max_pieces(seg);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return base ? (void *)(base + o) : nullptr;
+    };
+    void *pf = take((size_t)(seg->k + 1) * 4);
+    void *pt = take((size_t)(maxp + 1) * 4);
+    void *ps = take((size_t)maxp * 4);
+    void *bk = take((size_t)push_update_blocks(seg->V) * 4 * sizeof(double));
+    void *sl = take((size_t)maxp * (size_t)seg->N * 8);
+    if (ws) *ws = PushWs{(int32_t *)pf, (int32_t *)pt, (int32_t *)ps, bk, sl};
+    return off + 256;
+}
+size_t push_ws_bytes(const cagra_segments *seg) { return push_layout(seg, nullptr, nullptr); }
+
+template <class PO>
+static cagra_status launch_scatter(const cagra_segments *seg, const void *vals, const PushWs &ws, hipStream_t st) {
+    const size_t lds = (size_t)seg->N * sizeof(typename PO::A);
+    const unsigned grid = (unsigned)push_max_pieces(seg);
+    if (edge16(seg->N)) {
+        static bool attr = false;
+        if (!attr) {
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_scatter<PO, uint16_t>)) return a_;
+            attr = true;
+        }
+        k_push_scatter<PO, uint16_t><<<grid, kPushThreads, lds, st>>>(
+            static_cast<const uint16_t *>(seg->edge_src), seg->Q, seg->tile_edge, seg->tile_span_row,
+            static_cast<const uint32_t *>(vals), seg->V, seg->N, ws.pfirst, seg->k, ws.piece_tile, ws.piece_seg,
+            static_cast<typename PO::A *>(ws.slots));
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_scatter<PO, uint32_t>)) return a_;
+            attr = true;
+        }
+        k_push_scatter<PO, uint32_t><<<grid, kPushThreads, lds, st>>>(
+            static_cast<const uint32_t *>(seg->edge_src), seg->Q, seg->tile_edge, seg->tile_span_row,
+            static_cast<const uint32_t *>(vals), seg->V, seg->N, ws.pfirst, seg->k, ws.piece_tile, ws.piece_seg,
+            static_cast<typename PO::A *>(ws.slots));
+    }
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// Plan, expand and scatter: the common part of both push iterations.
+template <class PO>
+static cagra_status push_edges(const cagra_segments *seg, const void *x, void *vals, const PushWs &ws,
+                               hipStream_t st) {
+    k_push_plan<<<1, kPlanThreads, 0, st>>>(seg->tile_seg, seg->tile_edge, seg->ntiles, seg->k, push_piece_cap(seg),
+                                           ws.pfirst, ws.piece_tile, ws.piece_seg);
+    CAGRA_LAUNCH_CHECK();
+    if (seg->Q > 0) {
+        const size_t lds = push_expand_lds_bytes(seg->B, seg->k);
+        const bool wide = seg->Q < (int64_t)kWave * seg->k * seg->nb;
+        static bool attr = false;
+        if (!attr) {
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_expand<true>)) return a_;
+            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_expand<false>)) return a_;
+            attr = true;
+        }
+        if (wide)
+            k_push_expand<true><<<seg->max_items, kMergeThreads, lds, st>>>(
+                seg->row_dst_lo, seg->block_ptr, seg->block_items, static_cast<const uint32_t *>(x), seg->V, seg->k,
+                seg->B, seg->nb, static_cast<uint32_t *>(vals));
+        else
+            k_push_expand<false><<<seg->max_items, kMergeThreads, lds, st>>>(
+                seg->row_dst_lo, seg->block_ptr, seg->block_items, static_cast<const uint32_t *>(x), seg->V, seg->k,
+                seg->B, seg->nb, static_cast<uint32_t *>(vals));
+        CAGRA_LAUNCH_CHECK();
+    }
+    return launch_scatter<PO>(seg, vals, ws, st);
+}
+
+cagra_status launch_pr_push(const cagra_graph *g, const cagra_segments *seg, double damping, const float *rank_in,
+                            const float *contrib_in, const double *scalars_in, float *vals, float *rank_out,
+                            float *contrib_out, double *scalars_out, void *workspace, hipStream_t st) {
+    PushWs ws;
+    push_layout(seg, static_cast<char *>(workspace), &ws);
+    if (cagra_status s = push_edges<PushSum>(seg, contrib_in, vals, ws, st)) return s;
+    const int32_t nblk = push_update_blocks(seg->V);
+    k_push_pr_update<<<nblk, kUpdThreads, 0, st>>>(static_cast<const unsigned long long *>(ws.slots), ws.pfirst,
+                                                   seg->V, seg->N, rank_in, g->out_degree, scalars_in, damping,
+                                                   rank_out, contrib_out, static_cast<double *>(ws.blk));
+    CAGRA_LAUNCH_CHECK();
+    return launch_reduce4(static_cast<const double *>(ws.blk), nblk, scalars_out, st);
+}
+
+cagra_status launch_lp_push(const cagra_segments *seg, const int32_t *labels_in, int32_t *vals, int32_t *labels_out,
+                            int32_t *changed_out, void *workspace, hipStream_t st) {
+    PushWs ws;
+    push_layout(seg, static_cast<char *>(workspace), &ws);
+    if (cagra_status s = push_edges<PushMin>(seg, labels_in, vals, ws, st)) return s;
+    const int32_t nblk = push_update_blocks(seg->V);
+    k_push_lp_update<<<nblk, kUpdThreads, 0, st>>>(static_cast<const int32_t *>(ws.slots), ws.pfirst, seg->V, seg->N,
+                                                   labels_in, labels_out, static_cast<int32_t *>(ws.blk));
+    CAGRA_LAUNCH_CHECK();
+    return launch_reduce_i32(static_cast<const int32_t *>(ws.blk), nblk, changed_out, st);
+}
+
+}  // namespace cagra

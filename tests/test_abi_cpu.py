@@ -179,3 +179,32 @@ def test_cf_validation(cagra):
     assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(s), *args(wsb=4), None) == -4
     big = _fake_built(cagra, B=1024)
     assert L.cagra_cf_iter(ctypes.byref(g), ctypes.byref(big), *args(), None) == -3  # merge LDS
+
+
+def test_push_validation(cagra):
+    """The push-direction calls reject bad arguments before any HIP call."""
+    L = cagra.lib()
+    assert L.cagra_push_workspace_bytes(None) == 0
+    s = _fake_built(cagra)
+    ws = L.cagra_push_workspace_bytes(ctypes.byref(s))
+    # plan (k+1, pieces+1, pieces ints), 4 FP64 sums per 4096 vertices, one 8-byte slot of N per piece
+    assert ws >= (s.k + 1 + 2 * s.k) * 4 + 32 + s.k * s.N * 8
+    g = _graph(cagra, V=100, E=50)
+    pr = lambda **kw: [kw.get(n, d) for n, d in (("d", 0.85), ("ri", 1), ("ci", 2), ("si", 3), ("vals", 4),
+                                                  ("ro", 5), ("co", 6), ("so", 7), ("ws", 8), ("wsb", ws))]
+    assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(_seg(cagra)), *pr(), None) == -1  # unbuilt
+    assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(s), *pr(d=1.5), None) == -1
+    assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(s), *pr(vals=None), None) == -1
+    assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(s), *pr(so=None), None) == -1
+    assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(s), *pr(wsb=ws - 1), None) == -4
+    other = _graph(cagra, V=100, E=49)
+    assert L.cagra_pagerank_push_iter(ctypes.byref(other), ctypes.byref(s), *pr(), None) == -1
+    # LDS capacity: 8-byte accumulators for N = 20481 vertices exceed 160 KiB; 4-byte ones fit
+    big = _fake_built(cagra, V=40962, N=20481, B=4096)
+    wsb = L.cagra_push_workspace_bytes(ctypes.byref(big))
+    gb = _graph(cagra, V=40962, E=50)
+    assert L.cagra_pagerank_push_iter(ctypes.byref(gb), ctypes.byref(big), *pr(wsb=wsb), None) == -3
+    assert L.cagra_labelprop_push_iter(ctypes.byref(big), 1, 2, 3, 4, 5, wsb - 1, None) == -4
+    huge = _fake_built(cagra, V=81924, N=40962, B=4096)
+    assert L.cagra_labelprop_push_iter(ctypes.byref(huge), 1, 2, 3, 4, 5, 1 << 40, None) == -3
+    assert L.cagra_labelprop_push_iter(ctypes.byref(s), None, 2, 3, 4, 5, ws, None) == -1
