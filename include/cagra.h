@@ -252,11 +252,11 @@ cagra_status cagra_bc_backward_level(const cagra_segments *seg_t, int32_t d, int
  *      adds each edge's row value to its destination's accumulator in LDS,
  *      then writes the accumulators to the piece's slot,
  *   3. updates each vertex from its segment's slots.
- * Sums are exact (each FP32 value rounded to a multiple of 2^-56, added as
- * int64; |sums| < 64), minima exact, so results are bit-identical run to run.
- * Requirements: seg_t->N * 8 <= CAGRA_LDS_BYTES for PageRank (N <= 20,480),
- * seg_t->N * 4 <= CAGRA_LDS_BYTES for label propagation, and
- * 4*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES. The workspace (plan, per-block sums
+ * Sums are exact (each FP32 value truncated toward zero to a multiple of
+ * 2^-56, added as int64; |values| and |sums| < 64), minima exact, so results are bit-identical run to run.
+ * Requirements: the scatter keeps N accumulators in LDS, 8 bytes each for
+ * PageRank (N <= 20,480) and 4 for label propagation (N <= 40,960); and
+ * 4*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES for the expand. The workspace (plan, per-block sums
  * and one slot of N 8-byte accumulators per piece) carries no state between
  * calls.
  */

@@ -79,6 +79,7 @@ cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, 
 
 size_t push_ws_bytes(const cagra_segments *seg);
 size_t push_expand_lds_total(int32_t B, int32_t k);
+size_t push_scatter_lds_bytes(int32_t N, int acc_bytes);
 int64_t push_max_pieces(const cagra_segments *seg);
 cagra_status launch_pr_push(const cagra_graph *g, const cagra_segments *seg, double damping, const float *rank_in,
                             const float *contrib_in, const double *scalars_in, float *vals, float *rank_out,
@@ -492,9 +493,9 @@ static cagra_status check_push(const cagra_segments *seg, int acc_bytes, const v
                                const void *workspace) {
     cagra_status s;
     if ((s = check_built(seg)) != CAGRA_OK) return s;
-    if ((int64_t)seg->N * acc_bytes > CAGRA_LDS_BYTES)
-        return fail(CAGRA_E_CAPACITY, "push accumulators of N=%d vertices exceed the LDS (N * %d > %d)", seg->N,
-                    acc_bytes, CAGRA_LDS_BYTES);
+    if (seg->N > CAGRA_LDS_BYTES || push_scatter_lds_bytes(seg->N, acc_bytes) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "push accumulators of N=%d vertices (%d bytes each) exceed the LDS", seg->N,
+                    acc_bytes);
     if (push_expand_lds_total(seg->B, seg->k) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the expand kernel's LDS", seg->B, seg->k);
     if (push_max_pieces(seg) > INT32_MAX / 2) return fail(CAGRA_E_OVERFLOW, "too many push pieces");

@@ -122,4 +122,16 @@ __device__ __forceinline__ int32_t block_of_item(const int32_t *__restrict__ ite
     return lo;
 }
 
+// Groups of g consecutive work items share an XCD (workgroup id mod 8), and
+// the groups cycle over the XCDs: neighbouring blocks still meet in one L2,
+// while the heavy blocks at the front (high in-degree destinations after
+// clustering) spread over all XCDs. Bijective on [0, n): ids past the last
+// whole round of 8 g keep their place.
+__device__ __forceinline__ int32_t xcd_group_map(int32_t id, int32_t n, int32_t g) {
+    const int32_t round = 8 * g;
+    if (id >= n / round * round) return id;
+    const int32_t x = id & 7, q = id >> 3;
+    return (q / g) * round + x * g + (q % g);
+}
+
 }  // namespace cagra

@@ -240,17 +240,6 @@ __device__ __forceinline__ int64_t split_slot(int32_t items_b, int32_t b, int32_
     return 2 * (int64_t)(items_b - b) + j;
 }
 
-// Groups of g consecutive work items share an XCD (workgroup id mod 8), and
-// the groups cycle over the XCDs: neighbouring blocks still meet in one L2,
-// while the heavy blocks at the front (high in-degree destinations after
-// clustering) spread over all XCDs. Bijective on [0, n): ids past the last
-// whole round of 8 g keep their place.
-__device__ __forceinline__ int32_t xcd_group_map(int32_t id, int32_t n, int32_t g) {
-    const int32_t round = 8 * g;
-    if (id >= n / round * round) return id;
-    const int32_t x = id & 7, q = id >> 3;
-    return (q / g) * round + x * g + (q % g);
-}
 constexpr int32_t kItemGroup = 4;  // work items per XCD group (1, 2, 4 and 16 time alike; contiguous is slower)
 
 template <bool BF16OUT, bool WIDE>

@@ -15,8 +15,8 @@
 //     workgroup takes a piece (a run of consecutive tiles of one subgraph) and
 //     keeps the accumulators of that subgraph's destination segment in LDS;
 //     each edge adds its row's value to its destination with an LDS atomic.
-//     Sums are int64 fixed point (every FP32 value rounded to a multiple of
-//     2^-56) and minima are exact, so no result depends on the order of the
+//     Sums are int64 fixed point (every FP32 value truncated toward zero to a
+//     multiple of 2^-56) and minima are exact, so no result depends on the order of the
 //     atomics. A piece's finished accumulators leave as one sequential slot.
 //  3. Update: each vertex combines the slots of its segment's pieces and
 //     applies the vertex update (PageRank, or label propagation).
@@ -41,10 +41,11 @@ constexpr int kPushWaves = CAGRA_TILE_WAVES;  // tiles carry one starting row pe
 constexpr int kPushThreads = kPushWaves * kWave;
 constexpr int kPushEPT = 8;                   // edges per lane per chunk
 constexpr int kPushChunk = kWave * kPushEPT;
-constexpr int kPushStages = 3;                // chunks of edge words in flight per wave
+constexpr int kPushStages = 4;                // chunk buffers of edge words per wave (even: value sets alternate)
 constexpr int kPlanThreads = 1024;
 constexpr int kUpdSpan = 4096;                // vertices per update workgroup
 constexpr int kUpdThreads = 256;
+constexpr int32_t kExpandGroup = 4;           // expand items per XCD group
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
@@ -137,7 +138,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
     __shared__ int32_t tmp[16];
     const int32_t total = block_items[nb];
     if ((int32_t)blockIdx.x >= total) return;  // the grid is the bound max_items
-    const int32_t it = blockIdx.x;
+    // neighbouring blocks share the cache lines at the ends of their row ranges:
+    // groups of them run on one XCD at once, so partial lines meet in its L2
+    const int32_t it = xcd_group_map(blockIdx.x, total, kExpandGroup);
     const int32_t b = block_of_item(block_items, nb, it);
     const int32_t j = it - block_items[b], S = block_items[b + 1] - block_items[b];
     uint32_t *xs = reinterpret_cast<uint32_t *>(smem);
@@ -175,19 +178,28 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
 
 // ------------------------------------------------------------------ scatter
 
-struct PushSum {  // float values, exact int64 fixed-point sums
-    using V = float;
+// Sums: every FP32 value x becomes trunc(x * 2^56) as a two's-complement
+// int64 (exact for |x| < 64; the truncation error is below 2^-56 per term) and
+// the int64 adds are exact, so the order of the atomics does not matter.
+struct PushSum {
     using A = unsigned long long;
+    static constexpr bool kSum = true;
     static __device__ __forceinline__ A identity() { return 0ull; }
-    static __device__ __forceinline__ void add(A *acc, int32_t d, uint32_t bits) {
-        atomicAdd(&acc[d], fix56(__uint_as_float(bits)));
+    // |x| * 2^56 = m * 2^(e - 94) for the 24-bit significand m and biased
+    // exponent e: the 64-bit word (m << 40) shifted right by 134 - e. The high
+    // dword of m << 40 is the float's bits shifted left by 8 with the leading
+    // one set; shifts of 64 or more (|x| < 2^-56, zero, denormals) give 0.
+    static __device__ __forceinline__ uint64_t magnitude(uint32_t u) {
+        const uint32_t amt = 134u - ((u >> 23) & 0xffu);
+        const uint32_t hi = amt < 64u ? (u << 8) | 0x80000000u : 0u;
+        return ((uint64_t)hi << 32) >> (amt & 63u);
     }
 };
-struct PushMin {  // int32 values, minimum
-    using V = int32_t;
+// Minima of int32 values.
+struct PushMin {
     using A = int32_t;
+    static constexpr bool kSum = false;
     static __device__ __forceinline__ A identity() { return 0x7fffffff; }
-    static __device__ __forceinline__ void add(A *acc, int32_t d, uint32_t bits) { atomicMin(&acc[d], (int32_t)bits); }
 };
 
 template <typename W>
@@ -200,15 +212,25 @@ __device__ __forceinline__ void push_load_chunk(v4i (&r)[kPushLoads<W>], __amdgp
         r[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, off + 16 * j, 0, kNonTemporal);
 }
 
-// One chunk of a wave's share: this lane's kPushEPT consecutive edge words.
-// rel0 = the chunk's first edge relative to the share (negative for a first
-// chunk that starts before it); nfl = row starts seen in earlier chunks. The
-// row of an edge is row_before + (row starts in the share up to and including
-// it); vin is addressed relative to base_row.
-template <class PO, typename W>
-__device__ __forceinline__ void push_chunk(const v4i (&wv)[kPushLoads<W>], int32_t rel0, int32_t share,
-                                           int32_t row_off, __amdgpu_buffer_rsrc_t vin, typename PO::A *acc,
-                                           int32_t &nfl) {
+// Values of one chunk in flight: loaded per edge, applied one chunk later so
+// that the loads overlap the previous chunk's atomics.
+struct PushPend {
+    uint32_t xv[kPushEPT];  // the edge's row value (0 outside the share)
+    int32_t d[kPushEPT];    // local destination (0 outside the share)
+    uint32_t valid;         // bit i: edge i lies in the share
+};
+
+// Issue step of one chunk (this lane: kPushEPT consecutive edge words). rel0 =
+// the chunk's first edge relative to the share (negative for a first chunk
+// that starts before it); FULL chunks lie entirely inside the share. nfl = row
+// starts seen in earlier chunks. The row of an edge is row_before + (row
+// starts in the share up to and including it); vin is addressed relative to
+// base_row (row_off = row_before - base_row). Edges outside the share read 0
+// (buffer bounds) and target accumulator 0, so the apply step needs no branch.
+template <typename W, bool FULL>
+__device__ __forceinline__ void push_issue(const v4i (&wv)[kPushLoads<W>], int32_t rel0, int32_t share,
+                                           int32_t row_off, __amdgpu_buffer_rsrc_t vin, int32_t &nfl, PushPend &P) {
+    constexpr int kFlagShift = (int)sizeof(W) * 8 - 1;
     const int lane = threadIdx.x & 63;
     uint32_t wd[kPushEPT];
     if constexpr (sizeof(W) == 4) {
@@ -225,26 +247,58 @@ __device__ __forceinline__ void push_chunk(const v4i (&wv)[kPushLoads<W>], int32
     }
     const int32_t rel = rel0 + lane * kPushEPT;
     bool valid[kPushEPT];
-    int32_t nf = 0;
+    int32_t f[kPushEPT], nf = 0;
+    P.valid = 0u;
 #pragma unroll
     for (int i = 0; i < kPushEPT; ++i) {
-        valid[i] = (uint32_t)(rel + i) < (uint32_t)share;
-        nf += (valid[i] && (wd[i] & EdgeWord<W>::kFlag)) ? 1 : 0;
+        valid[i] = FULL || (uint32_t)(rel + i) < (uint32_t)share;
+        f[i] = valid[i] ? (int32_t)(wd[i] >> kFlagShift) : 0;
+        nf += f[i];
+        P.valid |= valid[i] ? (1u << i) : 0u;
     }
     const int32_t incl = wave_incl_sum(nf);
     const int32_t chunk_nf = __builtin_amdgcn_readlane(incl, 63);
     int32_t r = row_off + nfl + (incl - nf);  // row of the edge before this lane's first, relative to base_row
-    uint32_t xv[kPushEPT];
 #pragma unroll
     for (int i = 0; i < kPushEPT; ++i) {
-        r += (valid[i] && (wd[i] & EdgeWord<W>::kFlag)) ? 1 : 0;
+        r += f[i];
         const uint32_t off = valid[i] ? (uint32_t)r * 4u : kOutOfRange;
-        xv[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(vin, off, 0, 0);
+        P.xv[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(vin, off, 0, 0);
+        P.d[i] = valid[i] ? (int32_t)(wd[i] & EdgeWord<W>::kIndex) : 0;
     }
-#pragma unroll
-    for (int i = 0; i < kPushEPT; ++i)
-        if (valid[i]) PO::add(acc, (int32_t)(wd[i] & EdgeWord<W>::kIndex), xv[i]);
     nfl += chunk_nf;
+}
+
+// Apply step: the chunk's atomics into the segment's LDS accumulators.
+template <class PO>
+__device__ __forceinline__ void push_apply(const PushPend &P, typename PO::A *acc) {
+    if constexpr (PO::kSum) {
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < kPushEPT; ++i) any |= P.xv[i];
+        if (__ballot((int32_t)any < 0)) {  // uniform: a negative value in the wave
+#pragma unroll
+            for (int i = 0; i < kPushEPT; ++i) {
+                const uint64_t m = PushSum::magnitude(P.xv[i]);
+                atomicAdd(&acc[P.d[i]], (P.xv[i] >> 31) ? (unsigned long long)(-(int64_t)m) : (unsigned long long)m);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kPushEPT; ++i) atomicAdd(&acc[P.d[i]], (unsigned long long)PushSum::magnitude(P.xv[i]));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPushEPT; ++i)
+            atomicMin(&acc[P.d[i]], ((P.valid >> i) & 1u) ? (int32_t)P.xv[i] : PO::identity());
+    }
+}
+
+template <typename W>
+__device__ __forceinline__ void push_issue_any(const v4i (&wv)[kPushLoads<W>], int32_t rel0, int32_t share,
+                                               int32_t row_off, __amdgpu_buffer_rsrc_t vin, int32_t &nfl,
+                                               PushPend &P) {
+    if (rel0 >= 0 && rel0 + kPushChunk <= share) push_issue<W, true>(wv, rel0, share, row_off, vin, nfl, P);
+    else push_issue<W, false>(wv, rel0, share, row_off, vin, nfl, P);
 }
 
 // One workgroup per piece: accumulate the piece's edges into the destination
@@ -293,18 +347,25 @@ __global__ __launch_bounds__(kPushThreads) void k_push_scatter(
         const int32_t row_off = row_before - base_row;  // -1 or 0
         const int64_t len = w1 - ebase;
         int32_t nfl = 0;
+        // edge words kPushStages - 1 chunks ahead of the chunk whose loads are
+        // issued, which runs one chunk ahead of the chunk applied
         v4i R[kPushStages][kPushLoads<W>];
+        PushPend P[2];
 #pragma unroll
         for (int c = 0; c < kPushStages - 1; ++c)
             push_load_chunk<W>(R[c], ein, (uint32_t)(c * kPushChunk * kWB) + lane_off);
+        push_issue_any<W>(R[0], (int32_t)(ebase - w0), share, row_off, vin, nfl, P[0]);
         for (int64_t cc = 0; cc < len; cc += kPushStages * kPushChunk) {
 #pragma unroll
             for (int c = 0; c < kPushStages; ++c) {
-                if (cc + c * kPushChunk >= len) break;  // uniform
+                const int64_t ci = cc + c * kPushChunk;
+                if (ci >= len) break;  // uniform
                 push_load_chunk<W>(R[(c + kPushStages - 1) % kPushStages], ein,
-                                   (uint32_t)((cc + (c + kPushStages - 1) * kPushChunk) * kWB) + lane_off);
-                const int32_t rel0 = (int32_t)(ebase + cc + c * kPushChunk - w0);
-                push_chunk<PO, W>(R[c], rel0, share, row_off, vin, acc, nfl);
+                                   (uint32_t)((ci + (kPushStages - 1) * kPushChunk) * kWB) + lane_off);
+                if (ci + kPushChunk < len)
+                    push_issue_any<W>(R[(c + 1) % kPushStages], (int32_t)(ebase + ci + kPushChunk - w0), share,
+                                      row_off, vin, nfl, P[(c + 1) & 1]);
+                push_apply<PO>(P[c & 1], acc);
             }
         }
     }
@@ -423,9 +484,12 @@ static size_t push_layout(const cagra_segments *seg, char *base, PushWs *ws) {
 }
 size_t push_ws_bytes(const cagra_segments *seg) { return push_layout(seg, nullptr, nullptr); }
 
+// LDS of the scatter kernel: the segment's accumulators.
+size_t push_scatter_lds_bytes(int32_t N, int acc_bytes) { return (size_t)N * (size_t)acc_bytes; }
+
 template <class PO>
 static cagra_status launch_scatter(const cagra_segments *seg, const void *vals, const PushWs &ws, hipStream_t st) {
-    const size_t lds = (size_t)seg->N * sizeof(typename PO::A);
+    const size_t lds = push_scatter_lds_bytes(seg->N, (int)sizeof(typename PO::A));
     const unsigned grid = (unsigned)push_max_pieces(seg);
     if (edge16(seg->N)) {
         static bool attr = false;

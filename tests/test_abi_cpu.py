@@ -199,12 +199,16 @@ def test_push_validation(cagra):
     assert L.cagra_pagerank_push_iter(ctypes.byref(g), ctypes.byref(s), *pr(wsb=ws - 1), None) == -4
     other = _graph(cagra, V=100, E=49)
     assert L.cagra_pagerank_push_iter(ctypes.byref(other), ctypes.byref(s), *pr(), None) == -1
-    # LDS capacity: 8-byte accumulators for N = 20481 vertices exceed 160 KiB; 4-byte ones fit
-    big = _fake_built(cagra, V=40962, N=20481, B=4096)
-    wsb = L.cagra_push_workspace_bytes(ctypes.byref(big))
-    gb = _graph(cagra, V=40962, E=50)
-    assert L.cagra_pagerank_push_iter(ctypes.byref(gb), ctypes.byref(big), *pr(wsb=wsb), None) == -3
-    assert L.cagra_labelprop_push_iter(ctypes.byref(big), 1, 2, 3, 4, 5, wsb - 1, None) == -4
-    huge = _fake_built(cagra, V=81924, N=40962, B=4096)
-    assert L.cagra_labelprop_push_iter(ctypes.byref(huge), 1, 2, 3, 4, 5, 1 << 40, None) == -3
+    # LDS capacity (accumulators in 160 KiB): 8-byte accumulators fit up to
+    # N = 20480, 4-byte ones up to N = 40960
+    for N, ok in ((20480, True), (20481, False)):
+        seg = _fake_built(cagra, V=2 * N, N=N, B=4096)
+        wsb = L.cagra_push_workspace_bytes(ctypes.byref(seg))
+        gb = _graph(cagra, V=2 * N, E=50)
+        assert L.cagra_pagerank_push_iter(ctypes.byref(gb), ctypes.byref(seg), *pr(wsb=wsb - 1), None) == \
+            (-4 if ok else -3)
+    for N, ok in ((40960, True), (40961, False)):
+        seg = _fake_built(cagra, V=2 * N, N=N, B=4096)
+        wsb = L.cagra_push_workspace_bytes(ctypes.byref(seg))
+        assert L.cagra_labelprop_push_iter(ctypes.byref(seg), 1, 2, 3, 4, 5, wsb - 1, None) == (-4 if ok else -3)
     assert L.cagra_labelprop_push_iter(ctypes.byref(s), None, 2, 3, 4, 5, ws, None) == -1

@@ -6,8 +6,8 @@ PageRank step vertex by vertex within the FP32 bound (contributions rounded
 once to FP32, sums exact up to 2^-56 per term, result rounded to FP32:
 |err| <= 2^-22 * value + indeg * 2^-56); 20 iterations within L1 <= 1e-6 of the
 FP64 oracle, as for the pull path. Sizes span many tiles, split subgraphs
-(several pieces), ragged last segments, 16- and 32-bit edge words, k = 1 and
-N = 1, and graphs without edges."""
+(several pieces), ragged last segments, the largest segments the LDS holds
+(16- and 32-bit edge words), k = 1 and N = 1, and graphs without edges."""
 import numpy as np
 import pytest
 
@@ -59,7 +59,7 @@ def step_bound(g, want):
     (10, 8, 1, 1, 64, 64),          # N = 1: every destination its own segment
     (12, 8, 2, 100, 256, 64),       # ragged last segment, many small tiles
     (13, 8, 3, 4096, 1024, 1024),   # few subgraphs, several pieces each
-    (14, 16, 4, 16384, 8192, 65536),
+    (14, 16, 4, 20480, 8192, 65536),  # the largest PageRank segment, ragged last segment
     (13, 4, 5, 8192, 4096, 512),    # k = 1: one segment holds every vertex
 ])
 def test_pagerank_push_step_vertexwise(cagra, scale, ef, seed, N, B, T):
@@ -124,7 +124,7 @@ def test_pagerank_push_edge_cases(cagra, name):
 def test_capacity_and_argument_errors(cagra):
     import torch
     g = graphgen.rmat_graph(16, 4, 1)
-    dg, dgt, seg_t = push_segs(cagra, g, 40000, 4096, 65536)  # 32-bit words, N*8 > LDS
+    dg, dgt, seg_t = push_segs(cagra, g, 20481, 4096, 65536)  # N * 8 > LDS
     st_ws = cagra.push_workspace(seg_t)
     x = torch.zeros(g.V, dtype=torch.float32, device="cuda")
     sc = torch.zeros(4, dtype=torch.float64, device="cuda")
@@ -141,7 +141,7 @@ def test_capacity_and_argument_errors(cagra):
     (10, 4, 1, 1, 64, 64),
     (12, 8, 2, 100, 1024, 256),
     (14, 16, 3, 4096, 4096, 2048),
-    (16, 4, 6, 40000, 8192, 65536),   # 32-bit edge words, ragged second segment
+    (16, 4, 6, 40960, 8192, 65536),   # the largest label segment: 32-bit edge words, ragged
     (14, 4, 7, 1 << 20, 8192, 4096),  # one segment
 ])
 def test_labelprop_push_bit_exact(cagra, scale, ef, seed, N, B, T):
