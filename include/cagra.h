@@ -343,7 +343,7 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
  *   scalars_out[0] = dangling mass of rank_out, scalars_out[1] = ||rank_out - rank_in||_1,
  *   scalars_out[2] = sum of rank_out, scalars_out[3] = 0   (all FP64)
  * partial is float[Q] scratch for the per-subgraph buffers. The merge adds the
- * FP32 buffer values exactly (each rounded to a multiple of 2^-56 and summed
+ * FP32 buffer values exactly (each truncated toward zero to a multiple of 2^-56 and summed
  * as int64), so its result does not depend on the order of the additions;
  * buffer sums must stay below 64 in magnitude (true for rank vectors that sum
  * to at most 1). contrib_in is read with contrib_type, contrib_out written with

@@ -42,20 +42,48 @@ __device__ inline int32_t block_excl_scan_lds(int32_t *a, int32_t n, int32_t *tm
     return total;
 }
 
-// Loads the block's range bounds per subgraph into LDS and turns the lengths
-// into an exclusive prefix; returns the block's entry count.
-__device__ inline int32_t load_block_ranges(const int32_t *__restrict__ block_ptr, int b, int32_t k, int32_t *lo_s,
-                                     int32_t *pre, int32_t *tmp) {
+// Loads the block's range bounds per subgraph into LDS: pre = exclusive prefix
+// of the range lengths, ofs[s] = (first entry of subgraph s's range) - pre[s],
+// so that flattened entry f of subgraph s is entry ofs[s] + f. Returns the
+// block's entry count.
+__device__ inline int32_t load_block_ranges(const int32_t *__restrict__ block_ptr, int b, int32_t k, int32_t *ofs,
+                                            int32_t *pre, int32_t *tmp) {
     for (int s = threadIdx.x; s < k; s += kMergeThreads) {
         int32_t a = block_ptr[(int64_t)b * k + s], e = block_ptr[(int64_t)(b + 1) * k + s];
-        lo_s[s] = a;
+        ofs[s] = a;
         pre[s] = e - a;
     }
     __syncthreads();
     int32_t P = block_excl_scan_lds(pre, k, tmp);
     if (threadIdx.x == 0) pre[k] = P;
+    for (int s = threadIdx.x; s < k; s += kMergeThreads) ofs[s] -= pre[s];
     __syncthreads();
     return P;
+}
+
+// Entry index of flattened entry f = fs + lane in a window of 64 entries that
+// starts at fs (wave-uniform); entries up to wend (< pre[k], wave-uniform) are
+// in the share. sl, wave-uniform, is moved to the subgraph of fs. The whole
+// wave then steps over the range starts inside the window together, each lane
+// keeping the offset of the last subgraph that starts at or before its entry,
+// so a window costs one compare and one select per lane and range start
+// instead of a search per lane.
+__device__ __forceinline__ int32_t window_index(const int32_t *ofs, const int32_t *pre, int32_t &sl, int32_t fs,
+                                                int32_t wend, int32_t f) {
+    int32_t nxt = __builtin_amdgcn_readfirstlane(pre[sl + 1]);
+    while (nxt <= fs) {
+        ++sl;
+        nxt = __builtin_amdgcn_readfirstlane(pre[sl + 1]);
+    }
+    int32_t o = __builtin_amdgcn_readfirstlane(ofs[sl]);
+    int32_t s2 = sl;
+    while (nxt <= wend) {
+        ++s2;
+        const int32_t o2 = __builtin_amdgcn_readfirstlane(ofs[s2]);
+        o = f >= nxt ? o2 : o;
+        nxt = __builtin_amdgcn_readfirstlane(pre[s2 + 1]);
+    }
+    return o + f;
 }
 
 // Last subgraph s with pre[s] <= f (pre is non-decreasing; empty ranges skipped).
@@ -69,17 +97,23 @@ __device__ __forceinline__ int32_t run_of(const int32_t *pre, int32_t k, int32_t
     return lo;
 }
 
-// round(x * 2^56) as a two's-complement int64, computed from the float's bits
-// (exact for |x| < 64; halves round up in magnitude).
+// |x| * 2^56 truncated toward zero, from the float's bits: |x| * 2^56 =
+// m * 2^(e - 94) for the 24-bit significand m and biased exponent e, i.e. the
+// 64-bit word m << 40 shifted right by 134 - e. The high dword of m << 40 is
+// the float's bits shifted left by 8 with the leading one set; shifts of 64
+// or more (|x| < 2^-56, zeros, denormals) give 0. Exact for |x| < 64.
+__device__ __forceinline__ uint64_t fix56_magnitude(uint32_t u) {
+    const uint32_t amt = 134u - ((u >> 23) & 0xffu);
+    const uint32_t hi = amt < 64u ? (u << 8) | 0x80000000u : 0u;
+    return ((uint64_t)hi << 32) >> (amt & 63u);
+}
+
+// trunc(x * 2^56) as a two's-complement int64: sums of these are exact, so
+// they do not depend on the order of the additions (error below 2^-56 per term).
 __device__ __forceinline__ unsigned long long fix56(float x) {
     const uint32_t u = __float_as_uint(x);
-    const int e = (int)((u >> 23) & 0xffu);
-    const uint64_t m = (uint64_t)((u & 0x7fffffu) | (e ? 0x800000u : 0u));
-    const int sh = (e ? e : 1) - 94;
-    uint64_t r = 0;
-    if (sh >= 0) r = m << (sh & 63);
-    else if (sh > -26) r = ((m >> (-sh - 1)) + 1) >> 1;
-    return (u >> 31) ? (unsigned long long)(-(int64_t)r) : (unsigned long long)r;
+    const uint64_t m = fix56_magnitude(u);
+    return (u >> 31) ? (unsigned long long)(-(int64_t)m) : (unsigned long long)m;
 }
 
 constexpr int kUnroll = 8;

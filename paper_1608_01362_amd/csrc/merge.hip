@@ -15,7 +15,7 @@
 //    entries at once (flattened over subgraphs), updating shared LDS
 //    accumulators with atomics whose result does not depend on their order:
 //    int32 minimum for labels, and for PageRank an int64 fixed-point sum
-//    (each FP32 buffer value scaled by 2^56 and rounded), which adds the buffer
+//    (each FP32 buffer value scaled by 2^56 and truncated), which adds the buffer
 //    values exactly. The epilogue then applies the vertex update.
 #include <math.h>
 
@@ -128,31 +128,46 @@ __device__ __forceinline__ unsigned long long fix24(float x) {
 }
 
 // Streams block b's buffer entries (the ranges of all subgraphs, flattened).
-// Each wave takes a contiguous share; per pass a lane handles kUnroll entries
-// 64 apart, finding its subgraph by searching forward from the previous one.
-// All loads are issued unconditionally (clamped index) so that many are in
-// flight; apply(d, x) updates the LDS accumulator of block offset d. The loads
-// keep the default cache policy: the cache line at each end of a (subgraph,
-// block) range is shared with the neighbouring block, which is merged at the
-// same time on the same XCD and finds the line in L2.
+// Each wave takes a contiguous share and walks it in windows of 64 entries,
+// kUnroll windows per pass so that many loads are in flight. With long ranges
+// (WIDE = false) the wave steps over each window's range starts together
+// (window_index); with short ranges each lane searches forward from the
+// previous window's subgraph. apply(d, x) updates the LDS accumulator of
+// block offset d. The loads keep the default cache policy: the cache line at
+// each end of a (subgraph, block) range is shared with the neighbouring
+// block, which is merged at the same time on the same XCD and finds the line
+// in L2.
 template <typename PT, bool WIDE, class Apply>
 __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, const PT *__restrict__ partial,
-                                             const int32_t *lo_s, const int32_t *pre, int32_t k, int32_t F0,
+                                             const int32_t *ofs, const int32_t *pre, int32_t k, int32_t F0,
                                              int32_t F1, Apply apply) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int32_t share = ((((F1 - F0) + 15) / 16) + 63) & ~63;
     const int32_t fa = min(F0 + w * share, F1), fb = min(fa + share, F1);
+    if (fa >= fb) return;  // uniform over the wave
+    int32_t sw = __builtin_amdgcn_readfirstlane(run_of(pre, k, fa));
+    int32_t i_safe = __builtin_amdgcn_readfirstlane(ofs[sw]) + fa;  // an entry of the share, for idle lanes
     for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
-        int32_t sl = run_of(pre, k, f0);
         int32_t d[kUnroll];
         PT x[kUnroll];
+        int32_t sl = WIDE ? run_of(pre, k, f0) : 0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + u * kWave + lane;
+            const int32_t fs = f0 + u * kWave;
+            const int32_t f = fs + lane;
             const bool valid = f < fb;
-            const int32_t ff = valid ? f : f0;
-            sl = advance<WIDE>(pre, k, sl, ff);
-            const int32_t i = lo_s[sl] + (ff - pre[sl]);
+            int32_t i;
+            if (WIDE) {
+                const int32_t ff = valid ? f : f0;
+                sl = advance<true>(pre, k, sl, ff);
+                i = ofs[sl] + ff;
+            } else if (fs < fb) {  // uniform
+                const int32_t ii = window_index(ofs, pre, sw, fs, min(fs + kWave - 1, fb - 1), f);
+                i_safe = __builtin_amdgcn_readfirstlane(ii);  // lane 0's entry is in the share
+                i = valid ? ii : i_safe;
+            } else {
+                i = i_safe;  // a window past the share: loads of an entry already read, results dropped
+            }
             const int32_t dd = (int32_t)dlo[i];
             x[u] = partial[i];
             d[u] = valid ? dd : -1;
@@ -212,17 +227,17 @@ __device__ __forceinline__ void merge_pr_block(
     double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
     unsigned long long *__restrict__ slot, unsigned char *smem) {
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
-    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
-    int32_t *pre = lo_s + k;
+    int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
+    int32_t *pre = ofs + k;
     __shared__ int32_t tmp[16];
     __shared__ double red[16];
 
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
-    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+    const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
     const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
-    stream_block<float, WIDE>(row_dst_lo, partial, lo_s, pre, k, F0, F1,
+    stream_block<float, WIDE>(row_dst_lo, partial, ofs, pre, k, F0, F1,
                               [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
     __syncthreads();
     if (S > 1) {
@@ -323,15 +338,15 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_sum_fixed24(
     const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int32_t nb, float *__restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
-    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
-    int32_t *pre = lo_s + k;
+    int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
+    int32_t *pre = ofs + k;
     __shared__ int32_t tmp[16];
     const int b = xcd_remap(blockIdx.x, nb);
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
-    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<float, false>(row_dst_lo, partial, lo_s, pre, k, 0, P,
+    const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
+    stream_block<float, false>(row_dst_lo, partial, ofs, pre, k, 0, P,
                                [&](int32_t d, float x) { atomicAdd(&acc[d], fix24(x)); });
     __syncthreads();
     for (int i = threadIdx.x; i < nv; i += kMergeThreads)
@@ -444,8 +459,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int32_t *__restrict__ labels_in, int32_t *__restrict__ labels_out, int32_t *__restrict__ blk_changed) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int32_t *acc = reinterpret_cast<int32_t *>(smem);
-    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
-    int32_t *pre = lo_s + k;
+    int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
+    int32_t *pre = ofs + k;
     __shared__ int32_t tmp[16];
     __shared__ int32_t cnt[16];
 
@@ -453,8 +468,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
-    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
-    stream_block<int32_t, false>(row_dst_lo, partial, lo_s, pre, k, 0, P,
+    const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
+    stream_block<int32_t, false>(row_dst_lo, partial, ofs, pre, k, 0, P,
                           [&](int32_t d, int32_t x) { atomicMin(&acc[d], x); });
     __syncthreads();
     int32_t changed = 0;

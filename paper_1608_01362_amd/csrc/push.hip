@@ -144,29 +144,43 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
     const int32_t b = block_of_item(block_items, nb, it);
     const int32_t j = it - block_items[b], S = block_items[b + 1] - block_items[b];
     uint32_t *xs = reinterpret_cast<uint32_t *>(smem);
-    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
-    int32_t *pre = lo_s + k;
+    int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
+    int32_t *pre = ofs + k;
 
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) xs[i] = x[vb + i];
     // the barrier inside load_block_ranges also publishes the staged values
-    const int32_t P = load_block_ranges(block_ptr, b, k, lo_s, pre, tmp);
+    const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
     const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
 
+    // the wave's share, walked in windows of 64 rows as in the merge
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int32_t share = ((((F1 - F0) + 15) / 16) + 63) & ~63;
     const int32_t fa = min(F0 + w * share, F1), fb = min(fa + share, F1);
+    if (fa >= fb) return;  // uniform over the wave
+    int32_t sw = __builtin_amdgcn_readfirstlane(run_of(pre, k, fa));
+    int32_t i_safe = __builtin_amdgcn_readfirstlane(ofs[sw]) + fa;
     for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
-        int32_t sl = run_of(pre, k, f0);
         int32_t idx[kUnroll], d[kUnroll];
+        int32_t sl = WIDE ? run_of(pre, k, f0) : 0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int32_t f = f0 + u * kWave + lane;
+            const int32_t fs = f0 + u * kWave;
+            const int32_t f = fs + lane;
             const bool valid = f < fb;
-            const int32_t ff = valid ? f : f0;
-            sl = advance<WIDE>(pre, k, sl, ff);
-            const int32_t i = lo_s[sl] + (ff - pre[sl]);
+            int32_t i;
+            if (WIDE) {
+                const int32_t ff = valid ? f : f0;
+                sl = advance<true>(pre, k, sl, ff);
+                i = ofs[sl] + ff;
+            } else if (fs < fb) {  // uniform
+                const int32_t ii = window_index(ofs, pre, sw, fs, min(fs + kWave - 1, fb - 1), f);
+                i_safe = __builtin_amdgcn_readfirstlane(ii);
+                i = valid ? ii : i_safe;
+            } else {
+                i = i_safe;
+            }
             d[u] = (int32_t)row_dst_lo[i];
             idx[u] = valid ? i : -1;
         }
@@ -185,15 +199,7 @@ struct PushSum {
     using A = unsigned long long;
     static constexpr bool kSum = true;
     static __device__ __forceinline__ A identity() { return 0ull; }
-    // |x| * 2^56 = m * 2^(e - 94) for the 24-bit significand m and biased
-    // exponent e: the 64-bit word (m << 40) shifted right by 134 - e. The high
-    // dword of m << 40 is the float's bits shifted left by 8 with the leading
-    // one set; shifts of 64 or more (|x| < 2^-56, zero, denormals) give 0.
-    static __device__ __forceinline__ uint64_t magnitude(uint32_t u) {
-        const uint32_t amt = 134u - ((u >> 23) & 0xffu);
-        const uint32_t hi = amt < 64u ? (u << 8) | 0x80000000u : 0u;
-        return ((uint64_t)hi << 32) >> (amt & 63u);
-    }
+    static __device__ __forceinline__ uint64_t magnitude(uint32_t u) { return fix56_magnitude(u); }
 };
 // Minima of int32 values.
 struct PushMin {
