@@ -72,6 +72,65 @@ def measured_traffic(kernel, workload, args):
     return int(k["hbm_bytes_per_launch"])
 
 
+TRAFFIC_SOURCES = {
+    "k_gather": ["paper_1608_01362_amd/csrc/gather.hip", "paper_1608_01362_amd/csrc/common.h",
+                 "paper_1608_01362_amd/csrc/wave.h"],
+    "k_merge_pr": ["paper_1608_01362_amd/csrc/merge.hip", "paper_1608_01362_amd/csrc/common.h",
+                   "paper_1608_01362_amd/csrc/blockwalk.h"],
+}
+
+
+def _pmc_means(dirn, counter):
+    """Mean per dispatch of `counter` (summed over its instances) for each kernel
+    name prefix in a rocprofv3 --pmc output directory."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(dirn, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 database under {dirn}")
+    con = sqlite3.connect(dbs[0])
+    rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                       "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
+    per = {}
+    for name, _, v in rows:
+        short = name.split("(")[0].replace("void ", "").split("<")[0].replace("cagra::", "")
+        per.setdefault(short, []).append(float(v))
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def record_traffic(args, fetch_dir, write_dir, copyf_dir, copyw_dir):
+    import hashlib
+    fetch, write = _pmc_means(fetch_dir, "FETCH_SIZE"), _pmc_means(write_dir, "WRITE_SIZE")
+    cf, cw = _pmc_means(copyf_dir, "FETCH_SIZE"), _pmc_means(copyw_dir, "WRITE_SIZE")
+    copy_bytes = 1024 << 20
+    # the copy kernel is the one whose counters are largest in the calibration run
+    cfk, cwk = max(cf.values()), max(cw.values())
+    ff, wf = copy_bytes / (cfk * 1024), copy_bytes / (cwk * 1024)
+    rec = {"workload": "pagerank_rmat25_ef32_seed3", "N": 32768, "B": 8192, "tile_edges": 262144,
+           "contrib": "f32",
+           "calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": round(cfk), "WRITE_SIZE_KiB": round(cwk),
+                           "fetch_factor": round(ff, 5), "write_factor": round(wf, 5)},
+           "kernels": {}}
+    for kern, srcs in TRAFFIC_SOURCES.items():
+        h = hashlib.sha256()
+        for f in srcs:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        fk, wk = fetch[kern], write[kern]
+        rec["kernels"][kern] = {"sources": srcs, "source_sha256_16": h.hexdigest()[:16],
+                                "FETCH_SIZE_KiB": round(fk), "WRITE_SIZE_KiB": round(wk),
+                                "hbm_bytes_per_launch": round(fk * 1024 * ff + wk * 1024 * wf)}
+    cmd = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-converge --no-clustered-line"
+    rec["commands"] = [f"rocprofv3 --pmc FETCH_SIZE -d <out> -o fetch -- {cmd}",
+                       f"rocprofv3 --pmc WRITE_SIZE -d <out> -o write -- {cmd}",
+                       "rocprofv3 --pmc FETCH_SIZE -d <out> -o copyf -- python3 bench.py --copy-calibration 1024",
+                       "rocprofv3 --pmc WRITE_SIZE -d <out> -o copyw -- python3 bench.py --copy-calibration 1024",
+                       "python3 bench.py --record-traffic <fetch> <write> <copyf> <copyw>"]
+    out = os.path.join(ROOT, "profiles", "traffic_rmat25_ef32.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec["kernels"], indent=1))
+
+
 def cpu_baseline(g, budget_s=12.0):
     import oracle
     cores = max(1, min(len(os.sched_getaffinity(0)), 16))
@@ -113,7 +172,17 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (to calibrate the HBM "
                          "byte counters of a profiler against a known size) and exit")
+    ap.add_argument("--push-n", type=int, default=0,
+                    help="push workload: time this segment size only (no sweep)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
+                    help="CPU only: write profiles/traffic_rmat25_ef32.json from four rocprofv3 --pmc output "
+                         "directories (FETCH_SIZE and WRITE_SIZE of the default bench command, then of "
+                         "--copy-calibration 1024) and exit")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        record_traffic(args, *args.record_traffic)
+        return
 
     if args.copy_calibration:
         import torch

@@ -371,7 +371,7 @@ def push(args, log):
     steps = max(args.steps, 5)
     sweep = {}
     best = None
-    for N in (8192, 16384, 20480):
+    for N in ((args.push_n,) if args.push_n else (8192, 16384, 20480)):
         seg_t = cagra.build_segments(dgt, N, 8192, 262144)
         st = cagra.PushPageRankState(dg, seg_t)
         st.start()
@@ -383,16 +383,18 @@ def push(args, log):
             best = N
         del st, seg_t
         torch.cuda.empty_cache()
-    seg_t = cagra.build_segments(dgt, best, 8192, 262144)
-    r, res, it = cagra.pagerank_push(dg, seg_t, iters=100, tol=1e-6)
-    torch.cuda.synchronize()
-    a, b = _events()
-    a.record()
-    cagra.pagerank_push(dg, seg_t, iters=it)
-    b.record()
-    torch.cuda.synchronize()
-    conv_ms = a.elapsed_time(b)
-    del seg_t
+    it, conv_ms = None, None
+    if not args.no_converge:
+        seg_t = cagra.build_segments(dgt, best, 8192, 262144)
+        r, res, it = cagra.pagerank_push(dg, seg_t, iters=100, tol=1e-6)
+        torch.cuda.synchronize()
+        a, b = _events()
+        a.record()
+        cagra.pagerank_push(dg, seg_t, iters=it)
+        b.record()
+        torch.cuda.synchronize()
+        conv_ms = round(a.elapsed_time(b), 2)
+        del seg_t
     seg = cagra.build_segments(dg, 32768, 8192, 262144)
     stp = cagra.PageRankState(dg, seg)
     stp.start()
@@ -422,7 +424,7 @@ def push(args, log):
     return {"metric": "GTEPS per push-direction PageRank iteration at R-MAT-25", "value": round(E / pm / 1e6, 1),
             "unit": "GTEPS", "higher_is_better": True, "ms_per_iter": pm, "best_N": best, "sweep": sweep,
             "pull_ms_per_iter": round(pull_ms, 4), "push_over_pull_time": round(pm / pull_ms, 3),
-            "iters_to_1e-6": it, "ms_to_1e-6": round(conv_ms, 2),
+            "iters_to_1e-6": it, "ms_to_1e-6": conv_ms,
             "labelprop_rmat22_sym": {"E_sym": gs.E, "iterations": it_push, "push_ms": round(lp_push_ms, 2),
                                      "pull_ms": round(lp_pull_ms, 2),
                                      "push_GTEPS": round(gs.E * it_push / lp_push_ms / 1e6, 1),
