@@ -35,8 +35,38 @@ size_t merge_fused_lds_total(int32_t B, int32_t k, int acc_bytes) {
 
 // ---------------------------------------------------------------- ordered (paper) merge
 
+// One wave per block, subgraphs strictly in ascending order. The block's range
+// bounds are staged in LDS first (when they fit), and the entries of the next
+// non-empty subgraph (up to kOrdBatch per range) are loaded while the current
+// one is applied, so the wave does not wait on memory once per subgraph.
+// Entries of one subgraph have distinct destinations, so the lanes of a batch
+// never collide; the order across subgraphs is the program order of the wave.
+constexpr int kOrdLoads = 4;                    // entries per lane per batch
+constexpr int kOrdBatch = kOrdLoads * kWave;    // entries of a range loaded ahead
+
+template <typename T>
+struct OrdBatch {
+    T x[kOrdLoads];
+    int32_t d[kOrdLoads];  // -1: no entry
+};
+
 template <class Op, bool COMP>
-__global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict__ row_dst,
+__device__ __forceinline__ void ord_apply(typename Op::T *acc, typename Op::T *cmp, int32_t d,
+                                          typename Op::T x) {
+    if (COMP) {
+        // Neumaier (1974) compensated summation
+        float sacc = acc[d];
+        float tsum = sacc + x;
+        if (fabsf(sacc) >= fabsf(x)) cmp[d] += (sacc - tsum) + x;
+        else cmp[d] += (x - tsum) + sacc;
+        acc[d] = tsum;
+    } else {
+        acc[d] = Op::apply(acc[d], x);
+    }
+}
+
+template <class Op, bool COMP, bool STAGED>
+__global__ __launch_bounds__(64) void k_merge_ordered(const uint16_t *__restrict__ row_dst_lo,
                                                       const int32_t *__restrict__ block_ptr,
                                                       const typename Op::T *__restrict__ partial, int32_t V,
                                                       int32_t k, int32_t B, int32_t nb,
@@ -46,6 +76,8 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict_
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T *acc = reinterpret_cast<T *>(smem);
     T *cmp = acc + B;  // Neumaier compensation terms (COMP only)
+    int32_t *lo_s = reinterpret_cast<int32_t *>(smem + (size_t)B * sizeof(T) * (COMP ? 2 : 1));
+    int32_t *hi_s = lo_s + k;
     const int b = xcd_remap(blockIdx.x, nb);
     const int64_t vb = (int64_t)b * B;
     int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
@@ -54,44 +86,95 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const int32_t *__restrict_
         acc[i] = Op::identity();
         if (COMP) cmp[i] = Op::identity();
     }
-    __builtin_amdgcn_wave_barrier();
-    for (int32_t s = 0; s < k; ++s) {
-        if (seg_active && !((seg_active[s >> 5] >> (s & 31)) & 1u)) continue;  // inactive subgraph: no rows
-        const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
-        for (int32_t i = lo + lane; i < hi; i += 64) {
-            const int32_t d = (int32_t)(row_dst[i] - vb);
-            const T x = partial[i];
-            if (COMP) {
-                // Neumaier (1974) compensated summation
-                float sacc = acc[d];
-                float tsum = sacc + x;
-                if (fabsf(sacc) >= fabsf(x)) cmp[d] += (sacc - tsum) + x;
-                else cmp[d] += (x - tsum) + sacc;
-                acc[d] = tsum;
-            } else {
-                acc[d] = Op::apply(acc[d], x);
-            }
+    // range of subgraph s in this block; inactive subgraphs (no rows written) are empty
+    auto range = [&](int32_t s, int32_t &lo, int32_t &hi) {
+        if (STAGED) {
+            lo = lo_s[s];
+            hi = hi_s[s];
+        } else {
+            lo = block_ptr[(int64_t)b * k + s];
+            hi = block_ptr[(int64_t)(b + 1) * k + s];
+            if (seg_active && !((seg_active[s >> 5] >> (s & 31)) & 1u)) hi = lo;
         }
-        __builtin_amdgcn_wave_barrier();
+    };
+    if (STAGED) {
+        for (int32_t s = lane; s < k; s += 64) {
+            const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
+            const bool act = !seg_active || ((seg_active[s >> 5] >> (s & 31)) & 1u);
+            lo_s[s] = lo;
+            hi_s[s] = act ? hi : lo;
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+    // next subgraph at or after s with entries in this block (k if none); uniform
+    auto next = [&](int32_t s, int32_t &lo, int32_t &hi) {
+        for (; s < k; ++s) {
+            range(s, lo, hi);
+            if (hi > lo) break;
+        }
+        return s;
+    };
+    auto issue = [&](int32_t lo, int32_t hi, OrdBatch<T> &q) {
+#pragma unroll
+        for (int j = 0; j < kOrdLoads; ++j) {
+            const int32_t i = lo + j * kWave + lane;
+            const bool ok = i < hi;
+            const int32_t ii = ok ? i : lo;
+            q.x[j] = partial[ii];
+            const int32_t dd = (int32_t)row_dst_lo[ii];
+            q.d[j] = ok ? dd : -1;
+        }
+    };
+    int32_t lo, hi, lo2 = 0, hi2 = 0;
+    int32_t s = next(0, lo, hi);
+    OrdBatch<T> cur, nxt;
+    if (s < k) issue(lo, hi, cur);
+    while (s < k) {
+        const int32_t s2 = next(s + 1, lo2, hi2);
+        if (s2 < k) issue(lo2, hi2, nxt);
+#pragma unroll
+        for (int j = 0; j < kOrdLoads; ++j)
+            if (cur.d[j] >= 0) ord_apply<Op, COMP>(acc, cmp, cur.d[j], cur.x[j]);
+        // the rest of a long range, still before the next subgraph
+        for (int32_t i = lo + kOrdBatch + lane; i < hi; i += 64) ord_apply<Op, COMP>(acc, cmp, row_dst_lo[i], partial[i]);
+        __builtin_amdgcn_wave_barrier();
+        s = s2;
+        lo = lo2;
+        hi = hi2;
+        cur = nxt;
+    }
+    __builtin_amdgcn_wave_barrier();
     for (int i = lane; i < nv; i += 64) out[vb + i] = COMP ? (T)(acc[i] + cmp[i]) : acc[i];
 }
 
-template <class Op, bool COMP>
-static cagra_status launch_ordered(const cagra_segments *seg, const void *partial, void *out,
-                                   const uint32_t *seg_active, hipStream_t st) {
+// Staged range bounds fit next to the accumulators.
+static bool ordered_ranges_staged(int32_t B, int32_t k, bool comp) {
+    return (size_t)B * 4 * (comp ? 2 : 1) + (size_t)k * 8 <= CAGRA_LDS_BYTES - 1024;
+}
+
+template <class Op, bool COMP, bool STAGED>
+static cagra_status launch_ordered_t(const cagra_segments *seg, const void *partial, void *out,
+                                     const uint32_t *seg_active, hipStream_t st) {
     using T = typename Op::T;
-    auto kern = k_merge_ordered<Op, COMP>;
-    size_t lds = (size_t)seg->B * sizeof(T) * (COMP ? 2 : 1);
+    auto kern = k_merge_ordered<Op, COMP, STAGED>;
+    size_t lds = (size_t)seg->B * sizeof(T) * (COMP ? 2 : 1) + (STAGED ? (size_t)seg->k * 8 : 0);
     static bool attr_set = false;
     if (!attr_set) {
         if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
         attr_set = true;
     }
-    kern<<<seg->nb, 64, lds, st>>>(seg->row_dst, seg->block_ptr, (const T *)partial, seg->V, seg->k, seg->B, seg->nb,
-                                   (T *)out, seg_active);
+    kern<<<seg->nb, 64, lds, st>>>(seg->row_dst_lo, seg->block_ptr, (const T *)partial, seg->V, seg->k, seg->B,
+                                   seg->nb, (T *)out, seg_active);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
+}
+
+template <class Op, bool COMP>
+static cagra_status launch_ordered(const cagra_segments *seg, const void *partial, void *out,
+                                   const uint32_t *seg_active, hipStream_t st) {
+    if (ordered_ranges_staged(seg->B, seg->k, COMP))
+        return launch_ordered_t<Op, COMP, true>(seg, partial, out, seg_active, st);
+    return launch_ordered_t<Op, COMP, false>(seg, partial, out, seg_active, st);
 }
 
 size_t merge_ordered_lds_bytes(int32_t B, int32_t op) {
