@@ -271,6 +271,7 @@ def main():
     V, E, Q, k, nb = g.V, g.E, seg.Q, seg.k, seg.c.nb
     we = 2 if args.N <= cagra.EDGE16_MAX_N else 4
     gb, mb = byte_model(V, E, Q, k, nb, wc, we)
+    wide_model = E * we + 16 * Q + 4 * k * (nb + 1) + V * (12 + 2 * wc)
     g_avg, m_avg = sum(gather_ms) / K, sum(merge_ms) / K
     if g_avg >= m_avg:
         dom, dbytes, dms = "k_gather", gb, g_avg
@@ -361,6 +362,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                      "kernel_ms": round(dms, 4), "algorithmic_bytes": dbytes},
         "step_roofline_frac": round((gb + mb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the wider byte model that also prices a row pointer and a 4-byte destination
+        # per buffer row (16Q instead of the 10Q this layout moves)
+        "step_roofline_frac_16q_model": round(wide_model / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bytes_per_step_16q_model": wide_model,
         "kernels_ms": {"k_gather": round(g_avg, 4), "k_merge_pr+reduce": round(m_avg, 4)},
         "bytes_per_step": {"gather": gb, "merge": mb},
         "segment_build_ms": round(build_ms, 2),

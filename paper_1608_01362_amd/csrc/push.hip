@@ -41,7 +41,8 @@ constexpr int kPushWaves = CAGRA_TILE_WAVES;  // tiles carry one starting row pe
 constexpr int kPushThreads = kPushWaves * kWave;
 constexpr int kPushEPT = 8;                   // edges per lane per chunk
 constexpr int kPushChunk = kWave * kPushEPT;
-constexpr int kPushStages = 4;                // chunk buffers of edge words per wave (even: value sets alternate)
+constexpr int kPushStages = 4;                // chunk buffers of edge words per wave
+static_assert(kPushStages % 2 == 0, "the two value sets alternate with the chunk index inside one ring pass");
 constexpr int kPlanThreads = 1024;
 constexpr int kUpdSpan = 4096;                // vertices per update workgroup
 constexpr int kUpdThreads = 256;
