@@ -5,15 +5,22 @@
 // Every run is one row (s, v) of subgraph s. The builder
 //   1. flags run starts and labels every edge with its run and destination
 //      (two device-wide scans),
-//   2. stable-sorts the runs by segment id with a chunked counting sort (the
-//      runs arrive in (v, s) order; segment-major order with v ascending inside
-//      each segment is the paper's "sortByDestination" per subgraph),
-//   3. scatters the edges into the concatenated subgraph CSRs,
+//   2. stable-sorts the runs by segment id (the runs arrive in (v, s) order;
+//      segment-major order with v ascending inside each segment is the paper's
+//      "sortByDestination" per subgraph), carrying each run's destination and
+//      length, and stable-sorts the edges by the segment of their source,
+//      carrying the finished edge word (local index + row-start flag): both
+//      are device radix sorts (rocPRIM), whose block-local ranking keeps the
+//      writes coalesced where a direct scatter of runs and edges writes a few
+//      bytes per cache line,
+//   3. writes the rows and their offsets from the sorted runs,
 //   4. builds the merge block index (Section 3.3) and the gather tile table.
 // Everything is integer work; the result is unique and bit-identical run to run.
 #include <limits.h>
 
 #include <vector>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 
@@ -228,82 +235,57 @@ __global__ void k_runs(const int32_t *__restrict__ src, const int32_t *__restric
     if (e == E - 1) run_first[ri] = (int32_t)E;
 }
 
-// counts[s*nchunks + c] = number of runs of segment s in chunk c.
-__global__ __launch_bounds__(256) void k_sort_count(const int32_t *__restrict__ key, int64_t Q, int32_t C, int32_t k,
-                                                    int32_t nchunks, int32_t *__restrict__ counts) {
-    extern __shared__ int32_t hist[];
-    for (int s = threadIdx.x; s < k; s += blockDim.x) hist[s] = 0;
-    __syncthreads();
-    int64_t c = blockIdx.x;
-    int64_t lo = c * C, hi = lo + C < Q ? lo + C : Q;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&hist[key[j]], 1);
-    __syncthreads();
-    for (int s = threadIdx.x; s < k; s += blockDim.x) counts[(int64_t)s * nchunks + c] = hist[s];
-}
-
-// Stable ranks: one wave walks its chunk in order, 64 items per round; lanes
-// with equal keys are matched with one ballot per key bit.
-__global__ __launch_bounds__(64) void k_sort_rank(const int32_t *__restrict__ key, int64_t Q, int32_t C, int32_t k,
-                                                  int32_t nchunks, int32_t nbits,
-                                                  const int32_t *__restrict__ offsets, int32_t *__restrict__ pos) {
-    extern __shared__ int32_t cnt[];
-    int64_t c = blockIdx.x;
-    for (int s = threadIdx.x; s < k; s += 64) cnt[s] = offsets[(int64_t)s * nchunks + c];
-    __syncthreads();
-    int64_t lo = c * C, hi = lo + C < Q ? lo + C : Q;
-    const uint64_t lt = lanemask_lt();
-    for (int64_t j0 = lo; j0 < hi; j0 += 64) {
-        int64_t j = j0 + threadIdx.x;
-        bool valid = j < hi;
-        int32_t kk = valid ? key[j] : 0;
-        uint64_t m = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            bool bit = (kk >> b) & 1;
-            uint64_t bb = __ballot(valid && bit);
-            m &= bit ? bb : ~bb;
-        }
-        int32_t base = valid ? cnt[kk] : 0;
-        __builtin_amdgcn_wave_barrier();
-        if (valid) {
-            pos[j] = base + __popcll(m & lt);
-            if ((m & lt) == 0) cnt[kk] = base + __popcll(m);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
-__global__ void k_seg_begin(const int32_t *__restrict__ offsets, int32_t k, int32_t nchunks, int64_t Q,
-                            int32_t *__restrict__ seg_row_begin) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < k) seg_row_begin[s] = offsets[s * nchunks];
-    if (s == k) seg_row_begin[k] = (int32_t)Q;
-}
-
-__global__ void k_rows(const int32_t *__restrict__ run_first, const int32_t *__restrict__ run_dst,
-                       const int32_t *__restrict__ pos, int64_t Q, int32_t B, int32_t *__restrict__ row_dst,
-                       uint16_t *__restrict__ row_dst_lo, int32_t *__restrict__ row_len) {
+// Sort inputs of the runs: key = segment, value = destination << 32 | length.
+__global__ void k_run_kv(const int32_t *__restrict__ run_first, const int32_t *__restrict__ run_seg,
+                         const int32_t *__restrict__ run_dst, int64_t Q, uint16_t *__restrict__ key,
+                         unsigned long long *__restrict__ val) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < Q) {
-        int32_t p = pos[r];
-        int32_t d = run_dst[r];
-        row_dst[p] = d;
-        row_dst_lo[p] = (uint16_t)(d % B);
-        row_len[p] = run_first[r + 1] - run_first[r];
-    }
-    if (r == Q) row_len[Q] = 0;
+    if (r >= Q) return;
+    key[r] = (uint16_t)run_seg[r];
+    val[r] = ((unsigned long long)(uint32_t)run_dst[r] << 32) | (uint32_t)(run_first[r + 1] - run_first[r]);
 }
 
+// Sort inputs of the edges: key = segment of the source, value = the edge word
+// (local source index, row-start flag on the first edge of each run).
 template <typename W>
-__global__ void k_edges(const int32_t *__restrict__ src, const int32_t *__restrict__ runincl,
-                        const int32_t *__restrict__ run_first, const int32_t *__restrict__ pos,
-                        const int32_t *__restrict__ row_ptr, int64_t E, int32_t N, W *__restrict__ edge_src) {
+__global__ void k_edge_kv(const int32_t *__restrict__ src, const int32_t *__restrict__ runincl, int64_t E,
+                          int32_t N, uint16_t *__restrict__ key, W *__restrict__ val) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
-    int32_t r = runincl[e] - 1;
-    int32_t off = (int32_t)e - run_first[r];
-    int32_t u = src[e];
-    uint32_t local = (uint32_t)(u - (u / N) * N);
-    edge_src[row_ptr[pos[r]] + off] = (W)(off == 0 ? (local | EdgeWord<W>::kFlag) : local);
+    const int32_t u = src[e], s = u / N;
+    const uint32_t local = (uint32_t)(u - s * N);
+    const bool start = e == 0 || runincl[e - 1] != runincl[e];
+    key[e] = (uint16_t)s;
+    val[e] = (W)(start ? (local | EdgeWord<W>::kFlag) : local);
+}
+
+// Rows from the sorted runs; row_len[Q] = 0 closes the offsets' scan.
+__global__ void k_rows_sorted(const unsigned long long *__restrict__ val, int64_t Q, int32_t B,
+                              int32_t *__restrict__ row_dst, uint16_t *__restrict__ row_dst_lo,
+                              int32_t *__restrict__ row_len) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < Q) {
+        const unsigned long long x = val[p];
+        const int32_t d = (int32_t)(x >> 32);
+        row_dst[p] = d;
+        row_dst_lo[p] = (uint16_t)(d % B);
+        row_len[p] = (int32_t)(uint32_t)x;
+    }
+    if (p == Q) row_len[Q] = 0;
+}
+
+// seg_row_begin[s] = first sorted run of segment s or later.
+__global__ void k_seg_begin_sorted(const uint16_t *__restrict__ key, int64_t Q, int32_t k,
+                                   int32_t *__restrict__ seg_row_begin) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > k) return;
+    int64_t lo = 0, hi = Q;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)key[mid] < s) lo = mid + 1;
+        else hi = mid;
+    }
+    seg_row_begin[s] = (int32_t)lo;
 }
 
 // Merge work items (see block_items in cagra.h): a block whose entries exceed
@@ -398,13 +380,6 @@ __global__ void k_spans(const int32_t *__restrict__ row_ptr, const int32_t *__re
 
 // ------------------------------------------------------------------ host orchestration
 
-static int32_t sort_chunk(int32_t k) {
-    int64_t c = 64LL * k;
-    if (c < 4096) c = 4096;
-    if (c > (1 << 22)) c = 1 << 22;
-    return (int32_t)c;
-}
-
 static int nbits_for(int32_t k) {
     int b = 1;
     while ((1LL << b) < k) ++b;
@@ -420,23 +395,46 @@ size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
     return a.used + 256;
 }
 
-// Layout of the build workspace (mirrors build_segments below).
-static size_t build_workspace_size(int64_t E, int64_t Q, int32_t k, int32_t nb) {
-    int32_t C = sort_chunk(k);
-    int64_t nchunks = ceil_div(Q, C);
+// Temporary storage of the two radix sorts (size queries only, no launches).
+struct SortTemps {
+    size_t rows = 0, edges = 0;
+};
+
+static cagra_status sort_temps(int64_t E, int64_t Q, int32_t k, bool w16, SortTemps &t) {
+    const int bits = nbits_for(k);
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, t.rows, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                             (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                                             (size_t)Q, 0, bits);
+    if (e != hipSuccess) return fail(CAGRA_E_HIP, "run sort size query failed: %s", hipGetErrorString(e));
+    e = w16 ? rocprim::radix_sort_pairs(nullptr, t.edges, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                        (uint16_t *)nullptr, (uint16_t *)nullptr, (size_t)E, 0, bits)
+            : rocprim::radix_sort_pairs(nullptr, t.edges, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                        (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)E, 0, bits);
+    if (e != hipSuccess) return fail(CAGRA_E_HIP, "edge sort size query failed: %s", hipGetErrorString(e));
+    return CAGRA_OK;
+}
+
+// Layout of the build workspace (mirrors build_segments below). Arrays that
+// are dead by the time a later one is written share its memory:
+//   mark (dstp1)       -> edge keys and, for 16-bit words, the unsorted edge words
+//   flag (runincl)     -> sorted edge keys
+//   run_first          -> sorted run keys
+//   run_seg + run_dst  -> sorted run values
+static size_t build_layout(int64_t E, int64_t Q, int32_t k, int32_t nb, int wbytes, const SortTemps &t) {
     ArenaSize a;
-    a.take<int32_t>(E);           // mark / dstp1
-    a.take<int32_t>(E);           // flags / runincl
-    a.take<int32_t>(Q + 1);       // run_first
-    a.take<int32_t>(Q);           // run_seg
-    a.take<int32_t>(Q);           // run_dst
-    a.take<int32_t>(Q);           // pos
-    a.take<int32_t>(k * nchunks); // sort counts
-    a.take<int32_t>(k + 1);       // tile counts
+    a.take<char>(4 * E + 512);            // mark / dstp1; then edge keys (+ 16-bit edge words)
+    a.take<int32_t>(E);                   // flags / runincl; then sorted edge keys
+    a.take<int32_t>(Q + 1);               // run_first; then sorted run keys
+    a.take<int32_t>(2 * Q);               // run_seg, run_dst; then sorted run values
+    a.take<uint16_t>(Q);                  // run keys
+    a.take<unsigned long long>(Q);        // run values
+    if (wbytes == 4) a.take<uint32_t>(E); // 32-bit edge words before sorting
+    a.take<int32_t>(k + 1);               // tile counts
+    a.take<char>((int64_t)(t.rows > t.edges ? t.rows : t.edges));  // sort temporaries
     int64_t mx = E;
-    if (k * nchunks > mx) mx = k * nchunks;
     if (Q + 1 > mx) mx = Q + 1;
     if ((int64_t)nb + 1 > mx) mx = (int64_t)nb + 1;
+    if ((int64_t)k + 1 > mx) mx = (int64_t)k + 1;
     return a.used + scan_ws_bytes(mx) + 256;
 }
 
@@ -489,7 +487,9 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     const int64_t items = (int64_t)seg->nb + ceil_div(Q, merge_split_entries(Q, seg->nb)) + 1;
     if (items > INT32_MAX) return fail(CAGRA_E_OVERFLOW, "too many merge work items");
     seg->max_items = (int32_t)items;
-    seg->build_workspace_bytes = build_workspace_size(E, Q, k, seg->nb);
+    SortTemps t;
+    if (cagra_status e = sort_temps(E, Q, k, edge16(N), t)) return e;
+    seg->build_workspace_bytes = build_layout(E, Q, k, seg->nb, edge16(N) ? 2 : 4, t);
     return CAGRA_OK;
 }
 
@@ -497,8 +497,6 @@ static cagra_status allow_big_lds_impl() {
     static bool done = false;
     if (!done) {
         if (cagra_status a_ = allow_dynamic_lds((const void *)k_count)) return a_;
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_sort_count)) return a_;
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_sort_rank)) return a_;
         done = true;
     }
     return CAGRA_OK;
@@ -517,19 +515,30 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     const int32_t V = g->V, N = seg->N, B = seg->B, T = seg->tile_edges, k = seg->k, nb = seg->nb;
     const int64_t E = g->E, Q = seg->Q;
     const int32_t ntiles = seg->ntiles;
-    const int32_t C = sort_chunk(k);
-    const int64_t nchunks = ceil_div(Q, C);
+    const bool w16 = edge16(N);
+    SortTemps tmp;
+    if (cagra_status e = sort_temps(E, Q, k, w16, tmp)) return e;
     Arena ar{(char *)ws, ws_bytes, 0};
-    int32_t *mark = ar.take<int32_t>(E);
+    char *mreg = ar.take<char>(4 * E + 512);
     int32_t *flag = ar.take<int32_t>(E);
     int32_t *run_first = ar.take<int32_t>(Q + 1);
-    int32_t *run_seg = ar.take<int32_t>(Q);
-    int32_t *run_dst = ar.take<int32_t>(Q);
-    int32_t *pos = ar.take<int32_t>(Q);
-    int32_t *counts = ar.take<int32_t>(k * nchunks);
+    int32_t *run_sd = ar.take<int32_t>(2 * Q);
+    uint16_t *rkey = ar.take<uint16_t>(Q);
+    unsigned long long *rval = ar.take<unsigned long long>(Q);
+    char *eval32 = w16 ? nullptr : ar.take<char>(4 * E);
     int32_t *tcount = ar.take<int32_t>(k + 1);
-    if (!mark || !flag || !run_first || !run_seg || !run_dst || !pos || !counts || !tcount)
+    const size_t tmp_bytes = tmp.rows > tmp.edges ? tmp.rows : tmp.edges;
+    char *stmp = ar.take<char>((int64_t)tmp_bytes);
+    if (!mreg || !flag || !run_first || !run_sd || !rkey || !rval || (!w16 && !eval32) || !tcount || !stmp)
         return fail(CAGRA_E_BUFFER, "build workspace smaller than %zu bytes", seg->build_workspace_bytes);
+    int32_t *mark = reinterpret_cast<int32_t *>(mreg);
+    int32_t *run_seg = run_sd, *run_dst = run_sd + Q;
+    // reuses of dead arrays (see build_layout)
+    uint16_t *ekey = reinterpret_cast<uint16_t *>(mreg);
+    char *eval = w16 ? mreg + align_up((size_t)E * 2, 256) : eval32;
+    uint16_t *ekey_s = reinterpret_cast<uint16_t *>(flag);
+    uint16_t *rkey_s = reinterpret_cast<uint16_t *>(run_first);
+    unsigned long long *rval_s = reinterpret_cast<unsigned long long *>(run_sd);
     cagra_status s;
     if (E == 0) {
         k_fill_i32<<<grid_for(k + 1, 256), 256, 0, st>>>(seg->seg_row_begin, k + 1, 0);
@@ -553,27 +562,31 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     if ((s = scan_i32<ScanAdd>(flag, flag, E, true, ar, st)) != CAGRA_OK) return s;
     k_runs<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, mark, flag, E, N, run_first, run_seg, run_dst);
     CAGRA_LAUNCH_CHECK();
-    // 2. stable counting sort of runs by segment
-    size_t lds_k = (size_t)k * sizeof(int32_t);
-    k_sort_count<<<(unsigned)nchunks, 256, lds_k, st>>>(run_seg, Q, C, k, (int32_t)nchunks, counts);
+    // 2. stable radix sorts by segment: runs (with destination and length) and edges (with their words)
+    const int bits = nbits_for(k);
+    k_run_kv<<<grid_for(Q, 256), 256, 0, st>>>(run_first, run_seg, run_dst, Q, rkey, rval);
     CAGRA_LAUNCH_CHECK();
-    if ((s = scan_i32<ScanAdd>(counts, counts, k * nchunks, false, ar, st)) != CAGRA_OK) return s;
-    k_sort_rank<<<(unsigned)nchunks, 64, lds_k, st>>>(run_seg, Q, C, k, (int32_t)nchunks, nbits_for(k), counts, pos);
+    size_t tb = tmp.rows;
+    CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, rkey, rkey_s, rval, rval_s, (size_t)Q, 0, bits, st));
+    if (w16) {
+        k_edge_kv<uint16_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint16_t *)eval);
+        CAGRA_LAUNCH_CHECK();
+        tb = tmp.edges;
+        CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, ekey, ekey_s, (uint16_t *)eval,
+                                                  (uint16_t *)seg->edge_src, (size_t)E, 0, bits, st));
+    } else {
+        k_edge_kv<uint32_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint32_t *)eval);
+        CAGRA_LAUNCH_CHECK();
+        tb = tmp.edges;
+        CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, ekey, ekey_s, (uint32_t *)eval,
+                                                  (uint32_t *)seg->edge_src, (size_t)E, 0, bits, st));
+    }
+    k_seg_begin_sorted<<<grid_for(k + 1, 256), 256, 0, st>>>(rkey_s, Q, k, seg->seg_row_begin);
     CAGRA_LAUNCH_CHECK();
-    k_seg_begin<<<grid_for(k + 1, 256), 256, 0, st>>>(counts, k, (int32_t)nchunks, Q, seg->seg_row_begin);
-    CAGRA_LAUNCH_CHECK();
-    // 3. rows and edges
-    k_rows<<<grid_for(Q + 1, 256), 256, 0, st>>>(run_first, run_dst, pos, Q, B, seg->row_dst, seg->row_dst_lo,
-                                                 seg->row_ptr);
+    // 3. rows and their edge offsets
+    k_rows_sorted<<<grid_for(Q + 1, 256), 256, 0, st>>>(rval_s, Q, B, seg->row_dst, seg->row_dst_lo, seg->row_ptr);
     CAGRA_LAUNCH_CHECK();
     if ((s = scan_i32<ScanAdd>(seg->row_ptr, seg->row_ptr, Q + 1, false, ar, st)) != CAGRA_OK) return s;
-    if (edge16(N))
-        k_edges<uint16_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N,
-                                                             (uint16_t *)seg->edge_src);
-    else
-        k_edges<uint32_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, run_first, pos, seg->row_ptr, E, N,
-                                                             (uint32_t *)seg->edge_src);
-    CAGRA_LAUNCH_CHECK();
     // 4. merge block index and gather tiles
     k_block_ptr<<<grid_for((int64_t)(nb + 1) * k, 256), 256, 0, st>>>(seg->row_dst, seg->seg_row_begin, k, nb, B,
                                                                        seg->block_ptr);
