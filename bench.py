@@ -119,7 +119,7 @@ def record_traffic(args, fetch_dir, write_dir, copyf_dir, copyw_dir):
         rec["kernels"][kern] = {"sources": srcs, "source_sha256_16": h.hexdigest()[:16],
                                 "FETCH_SIZE_KiB": round(fk), "WRITE_SIZE_KiB": round(wk),
                                 "hbm_bytes_per_launch": round(fk * 1024 * ff + wk * 1024 * wf)}
-    cmd = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-converge --no-clustered-line"
+    cmd = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-converge --no-clustered-line --no-plain-line"
     rec["commands"] = [f"rocprofv3 --pmc FETCH_SIZE -d <out> -o fetch -- {cmd}",
                        f"rocprofv3 --pmc WRITE_SIZE -d <out> -o write -- {cmd}",
                        "rocprofv3 --pmc FETCH_SIZE -d <out> -o copyf -- python3 bench.py --copy-calibration 1024",
@@ -163,6 +163,8 @@ def main():
                          "time is preprocessing, reported like the segment build")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-plain-line", action="store_true",
+                    help="skip the measurement of the plain (unsegmented, one-segment) pull on the same graph")
     ap.add_argument("--no-clustered-line", action="store_true",
                     help="skip the extra measurement of the same graph after clustering")
     ap.add_argument("--workload", default="pagerank",
@@ -299,6 +301,44 @@ def main():
                 "contrib": args.contrib}
         log(f"converged to L1 residual {res:.2e} in {it} iterations, {conv_ms:.1f} ms")
 
+    plain = None
+    if not args.no_plain_line:
+        # the plain (unsegmented) pull on the same GPU: one segment holding every
+        # vertex, gathers through the cache hierarchy; same iteration otherwise
+        pseg = cagra.build_segments(dg, V, args.B, args.tile_edges)
+        pst = cagra.PageRankState(dg, pseg, ct)
+        pst.start()
+        pst.step()
+        torch.cuda.synchronize()
+        p0e, p1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pk = 5
+        p0e.record()
+        for _ in range(pk):
+            pst.step()
+        p1e.record()
+        torch.cuda.synchronize()
+        p_ms = p0e.elapsed_time(p1e) / pk
+        plain = {"ms_per_step": round(p_ms, 4), "GTEPS": round(E / (p_ms * 1e-3) / 1e9, 3), "k": 1,
+                 "segmented_speedup_per_iteration": round(p_ms / ms_per_step, 3)}
+        if not args.no_converge:
+            pst.start()
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            it_p, res_p = 0, float("inf")
+            while it_p < 100:
+                pst.step()
+                it_p += 1
+                res_p = float(pst.scalars_now[1].item())
+                if res_p < 1e-6:
+                    break
+            p_conv = (time.perf_counter() - c0) * 1e3
+            plain["time_to_l1_1e-6"] = {"iterations": it_p, "ms": round(p_conv, 3)}
+            if conv:
+                plain["segmented_speedup_to_l1_1e-6"] = round(p_conv / conv["ms"], 3)
+        log(f"plain (one segment): {p_ms:.3f} ms/step")
+        del pst, pseg
+        torch.cuda.empty_cache()
+
     clustered = None
     if not args.cluster and not args.no_clustered_line:
         # the same graph after frequency-based clustering (Section 5): the
@@ -372,6 +412,7 @@ def main():
         "clustering": cluster_info,
         "after_clustering": clustered,
         "time_to_l1_1e-6": conv,
+        "plain_unsegmented": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
