@@ -314,10 +314,12 @@ cagra_status cagra_segment_gather(const cagra_segments *seg, int32_t op, int32_t
                                   void *partial, hipStream_t stream);
 
 /*
- * Cache-aware merge (Section 3.3): out[v] = op over subgraphs s (ascending
- * within fixed groups of subgraphs) of the buffer entries whose row_dst is v;
+ * Cache-aware merge (Section 3.3): out[v] = op over subgraphs s, strictly in
+ * ascending order, of the buffer entries whose row_dst is v (FP32 sums are
+ * rounded after every addition in that order, as the paper's merge loop does);
  * vertices without entries get the identity. op CAGRA_SUM_F32 or
- * CAGRA_SUM_F32_COMP (partial/out float) or CAGRA_MIN_I32 (int32).
+ * CAGRA_SUM_F32_COMP (Neumaier-compensated; partial/out float) or
+ * CAGRA_MIN_I32 (int32).
  */
 cagra_status cagra_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out,
                          hipStream_t stream);
