@@ -282,6 +282,20 @@ cagra_status cagra_labelprop_push_iter(const cagra_segments *seg_t, const int32_
                                        int32_t *labels_out, int32_t *changed_out, void *workspace,
                                        size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Device check of a graph against the CSC rules at the top of this file:
+ * in_offsets[0] == 0, in_offsets[V] == E, offsets non-decreasing; every source
+ * in [0, V); sources strictly ascending within each row (no duplicates); no
+ * self-loops. The offsets are checked first and the edges only when the
+ * offsets are sound, so a corrupt graph is never read out of bounds. Returns
+ * CAGRA_OK, or CAGRA_E_INVALID naming the first offending vertex or edge of
+ * the first violated rule in cagra_last_error(). SYNCHRONIZES the stream.
+ * workspace: device memory of cagra_validate_workspace_bytes() bytes.
+ */
+size_t cagra_validate_workspace_bytes(void);
+cagra_status cagra_validate_graph(const cagra_graph *g, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream);
+
 /* Device workspace needed by the query call of cagra_build_segments. */
 size_t cagra_query_workspace_bytes(int32_t V, int64_t E, int32_t N);
 

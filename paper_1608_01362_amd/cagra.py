@@ -50,6 +50,7 @@ EXPORTS = [
     "cagra_bc_forward_level", "cagra_bc_backward_level", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
+    "cagra_validate_workspace_bytes", "cagra_validate_graph",
     "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
@@ -112,6 +113,8 @@ def lib():
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_push_workspace_bytes": ([SP], _c_size),
+            "cagra_validate_workspace_bytes": ([], _c_size),
+            "cagra_validate_graph": ([GP, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_pagerank_push_iter": ([GP, SP, _c_dbl, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                           _c_size, st], ctypes.c_int),
             "cagra_labelprop_push_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
@@ -186,6 +189,16 @@ class DeviceGraph:
         dg = DeviceGraph(g.V, g.E, off, src, od)
         dg.c = CGraph(g.V, g.E, off.data_ptr(), src.data_ptr(), od.data_ptr())
         return dg
+
+
+def validate_graph(dg: "DeviceGraph", stream=None):
+    """Check the device CSC (offsets, source range, strictly ascending rows, no
+    self-loops); raises CagraError naming the first violation."""
+    import torch
+    L = lib()
+    n = L.cagra_validate_workspace_bytes()
+    ws = torch.empty(n, dtype=torch.uint8, device=_dev())
+    _check(L.cagra_validate_graph(ctypes.byref(dg.c), _ptr(ws), n, _stream(stream)), "cagra_validate_graph")
 
 
 def cluster(dg: "DeviceGraph", stream=None):

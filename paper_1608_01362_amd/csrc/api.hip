@@ -78,6 +78,8 @@ size_t softmax_ws_bytes(int32_t V);
 cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st);
 
 size_t push_ws_bytes(const cagra_segments *seg);
+size_t validate_ws_bytes();
+cagra_status validate_graph(const cagra_graph *g, void *ws, hipStream_t st);
 size_t push_expand_lds_total(int32_t B, int32_t k);
 size_t push_scatter_lds_bytes(int32_t N, int acc_bytes);
 int64_t push_max_pieces(const cagra_segments *seg);
@@ -528,6 +530,17 @@ cagra_status cagra_labelprop_push_iter(const cagra_segments *seg_t, const int32_
     if ((s = check_push(seg_t, 4, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
     if (!labels_in || !labels_out || !changed_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     return launch_lp_push(seg_t, labels_in, vals, labels_out, changed_out, workspace, stream);
+}
+
+size_t cagra_validate_workspace_bytes(void) { return validate_ws_bytes(); }
+
+cagra_status cagra_validate_graph(const cagra_graph *g, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, false)) != CAGRA_OK) return s;
+    if (!workspace || workspace_bytes < validate_ws_bytes())
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", validate_ws_bytes(), workspace_bytes);
+    return validate_graph(g, workspace, stream);
 }
 
 }  // extern "C"

@@ -212,3 +212,16 @@ def test_push_validation(cagra):
         wsb = L.cagra_push_workspace_bytes(ctypes.byref(seg))
         assert L.cagra_labelprop_push_iter(ctypes.byref(seg), 1, 2, 3, 4, 5, wsb - 1, None) == (-4 if ok else -3)
     assert L.cagra_labelprop_push_iter(ctypes.byref(s), None, 2, 3, 4, 5, ws, None) == -1
+
+
+def test_validate_graph_arguments(cagra):
+    """cagra_validate_graph rejects bad arguments before any HIP call."""
+    L = cagra.lib()
+    n = L.cagra_validate_workspace_bytes()
+    assert n >= 56
+    assert L.cagra_validate_graph(None, 1, n, None) == -1
+    assert L.cagra_validate_graph(ctypes.byref(_graph(cagra, V=0)), 1, n, None) == -1
+    assert L.cagra_validate_graph(ctypes.byref(_graph(cagra, E=2 ** 31)), 1, n, None) == -2
+    assert L.cagra_validate_graph(ctypes.byref(_graph(cagra, src=None)), 1, n, None) == -1
+    assert L.cagra_validate_graph(ctypes.byref(_graph(cagra)), None, n, None) == -4
+    assert L.cagra_validate_graph(ctypes.byref(_graph(cagra)), 1, n - 1, None) == -4
