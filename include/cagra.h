@@ -125,7 +125,9 @@ typedef struct {
     int32_t V, k, nb, ntiles;
     int64_t E, Q;
     size_t build_workspace_bytes;
-    int32_t max_items;    /* bound on block_items[nb] */
+    int32_t max_items;    /* bound on block_items[nb]; a caller may lower it to
+                             block_items[nb] once the build has run (no split
+                             block then saves the merge's slot pass) */
     /* device arrays */
     int32_t *seg_row_begin;
     int32_t *row_ptr;

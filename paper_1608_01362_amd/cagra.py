@@ -292,6 +292,9 @@ def build_segments(dg: DeviceGraph, N: int, B: int, tile_edges: int | None = Non
            "cagra_build_segments(build)")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     del ws
+    # tighten the work-item bound to the actual count (lets the merge skip its
+    # slot pass when no block is split)
+    c.max_items = int(arrays["block_items"][nb].item())
     arrays["row_dst"] = arrays["row_dst"][:Q]
     arrays["edge_src"] = arrays["edge_src"][:E]
     arrays["tile_seg"] = arrays["tile_seg"][:nt]

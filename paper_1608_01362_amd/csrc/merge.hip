@@ -606,7 +606,20 @@ __global__ __launch_bounds__(256) void k_reduce4(const double *__restrict__ blk,
                                                  double *__restrict__ out) {
     __shared__ double red[4];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t j = threadIdx.x; j < n; j += 256)
+    // four rows per thread and pass, loaded before they are added (same order)
+    int32_t j = threadIdx.x;
+    for (; j + 3 * 256 < n; j += 4 * 256) {
+        double x[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[r][c] = blk[(int64_t)(j + r * 256) * 4 + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) a[c] += x[r][c];
+    }
+    for (; j < n; j += 256)
         for (int c = 0; c < 4; ++c) a[c] += blk[(int64_t)j * 4 + c];
     for (int c = 0; c < 4; ++c) {
         double t = block_sum_f64<256>(a[c], red);
@@ -679,14 +692,19 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
         g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots);
     CAGRA_LAUNCH_CHECK();
-    const int32_t parts = (int64_t)seg->nb * kSlotParts <= INT32_MAX ? kSlotParts : 1;
-    k_slot_sum<<<(unsigned)((int64_t)seg->nb * parts), kSlotThreads, 0, st>>>(seg->block_items, seg->V, seg->B, parts,
-                                                                            slots);
-    CAGRA_LAUNCH_CHECK();
-    k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
-        seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
-        contrib_out, blk, slots);
-    CAGRA_LAUNCH_CHECK();
+    // max_items is a bound on the item count; when it equals nb (a caller that
+    // read block_items[nb] after the build may tighten it so) no block is split
+    // and the slot pass has nothing to do
+    if (seg->max_items > seg->nb) {
+        const int32_t parts = (int64_t)seg->nb * kSlotParts <= INT32_MAX ? kSlotParts : 1;
+        k_slot_sum<<<(unsigned)((int64_t)seg->nb * parts), kSlotThreads, 0, st>>>(seg->block_items, seg->V, seg->B,
+                                                                                parts, slots);
+        CAGRA_LAUNCH_CHECK();
+        k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
+            seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
+            contrib_out, blk, slots);
+        CAGRA_LAUNCH_CHECK();
+    }
     k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
