@@ -338,6 +338,29 @@ def main():
         log(f"plain (one segment): {p_ms:.3f} ms/step")
         del pst, pseg
         torch.cuda.empty_cache()
+        # the paper's lower-bound control (Section 1, figure of PageRank times on
+        # RMAT27, last bar): the same plain pull with every read sent to vertex
+        # 0, so no gather reaches DRAM at random (results not meaningful)
+        src0 = torch.zeros_like(dg.in_sources)
+        dg0 = cagra.DeviceGraph(V, E, dg.in_offsets, src0, dg.out_degree,
+                                cagra.CGraph(V, E, dg.in_offsets.data_ptr(), src0.data_ptr(),
+                                             dg.out_degree.data_ptr()))
+        zseg = cagra.build_segments(dg0, V, args.B, args.tile_edges)
+        zst = cagra.PageRankState(dg0, zseg, ct)
+        zst.start()
+        zst.step()
+        torch.cuda.synchronize()
+        p0e.record()
+        for _ in range(pk):
+            zst.step()
+        p1e.record()
+        torch.cuda.synchronize()
+        z_ms = p0e.elapsed_time(p1e) / pk
+        plain["all_reads_vertex0"] = {"ms_per_step": round(z_ms, 4),
+                                      "segmented_over_lower_bound": round(ms_per_step / z_ms, 3)}
+        log(f"plain with every read of vertex 0 (lower bound): {z_ms:.3f} ms/step")
+        del zst, zseg, dg0, src0
+        torch.cuda.empty_cache()
 
     clustered = None
     if not args.cluster and not args.no_clustered_line:
