@@ -141,9 +141,21 @@ def cpu_baseline(g, budget_s=12.0):
     t0 = time.perf_counter()
     oracle.pagerank(g, iters=n, threads=cores)
     tn = time.perf_counter() - t0
+    # one iteration on one thread, for the parallel speedup of the oracle itself
+    t0 = time.perf_counter()
+    oracle.pagerank(g, iters=1, threads=1)
+    t_one = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": g.E * n / tn / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
             "sample": f"{n} FP64 pull PageRank iterations of the plain CPU oracle on the full graph "
-                      f"(V={g.V}, E={g.E}), OpenMP over destinations; {tn / n * 1e3:.0f} ms per iteration"}
+                      f"(V={g.V}, E={g.E}), OpenMP over destinations; {tn / n * 1e3:.0f} ms per iteration",
+            "one_thread": {"value": round(g.E / t_one / 1e9, 4), "ms_per_iteration": round(t_one * 1e3, 1)},
+            "cpu_model": model, "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
 def main():
