@@ -156,6 +156,20 @@ __device__ __forceinline__ int32_t block_of_item(const int32_t *__restrict__ ite
     return lo;
 }
 
+// Block b of work item it, and the item's index j among the S items of b.
+// Every block has at least one item, so a total of nb items means one item per
+// block and item it is block it: no search (a chain of dependent global loads)
+// before the block's work starts.
+struct ItemPlace {
+    int32_t b, j, S;
+};
+__device__ __forceinline__ ItemPlace place_item(const int32_t *__restrict__ items, int32_t nb, int32_t total,
+                                                int32_t it) {
+    if (total == nb) return {it, 0, 1};
+    const int32_t b = block_of_item(items, nb, it);
+    return {b, it - items[b], items[b + 1] - items[b]};
+}
+
 // Groups of g consecutive work items share an XCD (workgroup id mod 8), and
 // the groups cycle over the XCDs: neighbouring blocks still meet in one L2,
 // while the heavy blocks at the front (high in-degree destinations after

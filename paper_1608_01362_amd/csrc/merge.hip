@@ -261,9 +261,11 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
     }
 }
 
+constexpr int kEpiBatch = 8;  // vertices per thread whose loads are in flight together
+
 // PageRank vertex update of block b from its exact sums acc (LDS, int64 fixed
 // point); writes the block's FP64 partial sums to blk_out[0..3].
-template <bool BF16OUT>
+template <bool BF16OUT, int EPI = kEpiBatch>
 __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32_t V, int64_t vb, int32_t nv,
                                             const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
                                             const double *__restrict__ scalars_in, double damping,
@@ -272,18 +274,33 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
     const double dd = damping;
     const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
     double dang = 0.0, res = 0.0, mass = 0.0;
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
-        const int64_t v = vb + i;
-        const double sum = (double)(long long)acc[i] * kFixInv;
-        const float r = (float)(base + dd * sum);
-        rank_out[v] = r;
-        const int32_t od = outdeg[v];
-        const float c = od > 0 ? r / (float)od : 0.0f;
-        if (BF16OUT) reinterpret_cast<uint16_t *>(contrib_out)[v] = f32_to_bf16(c);
-        else reinterpret_cast<float *>(contrib_out)[v] = c;
-        if (od == 0) dang += (double)r;
-        res += fabs((double)r - (double)rank_in[v]);
-        mass += (double)r;
+    // EPI vertices per thread per pass, their loads issued together (one memory
+    // round trip per pass, not per vertex); sums keep the vertex order
+    for (int i0 = threadIdx.x; i0 < nv; i0 += kMergeThreads * EPI) {
+        float rin[EPI];
+        int32_t odv[EPI];
+#pragma unroll
+        for (int u = 0; u < EPI; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            rin[u] = i < nv ? rank_in[vb + i] : 0.0f;
+            odv[u] = i < nv ? outdeg[vb + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < EPI; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            if (i >= nv) break;
+            const int64_t v = vb + i;
+            const double sum = (double)(long long)acc[i] * kFixInv;
+            const float r = (float)(base + dd * sum);
+            rank_out[v] = r;
+            const int32_t od = odv[u];
+            const float c = od > 0 ? r / (float)od : 0.0f;
+            if (BF16OUT) reinterpret_cast<uint16_t *>(contrib_out)[v] = f32_to_bf16(c);
+            else reinterpret_cast<float *>(contrib_out)[v] = c;
+            if (od == 0) dang += (double)r;
+            res += fabs((double)r - (double)rin[u]);
+            mass += (double)r;
+        }
     }
     dang = block_sum_f64<kMergeThreads>(dang, red);
     res = block_sum_f64<kMergeThreads>(res, red);
@@ -302,7 +319,7 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
 // sums in its own slot of the workspace, and k_merge_pr_finish adds the S
 // slots of the block (exactly, so the split does not change any result) and
 // applies the update.
-template <bool BF16OUT, bool WIDE>
+template <bool BF16OUT, bool WIDE, int EPI = kEpiBatch>
 __device__ __forceinline__ void merge_pr_block(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b, int32_t j, int32_t S,
@@ -327,7 +344,8 @@ __device__ __forceinline__ void merge_pr_block(
         for (int i = threadIdx.x; i < nv; i += kMergeThreads) slot[i] = acc[i];
         return;
     }
-    pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out, blk_out, red);
+    pr_epilogue<BF16OUT, EPI>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out, blk_out,
+                              red);
 }
 
 // Slot of item j of a split block b whose first item is items_b: 2*(items_b - b)
@@ -352,9 +370,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     // and the XCD remap spreads the actual items (not the bound) over the XCDs
     const int32_t total = block_items[nb];
     if ((int32_t)blockIdx.x >= total) return;  // uniform over the workgroup
-    const int32_t i = xcd_group_map(blockIdx.x, total, kItemGroup);
-    const int32_t b = block_of_item(block_items, nb, i);
-    const int32_t j = i - block_items[b], S = block_items[b + 1] - block_items[b];
+    const ItemPlace ip = place_item(block_items, nb, total, xcd_group_map(blockIdx.x, total, kItemGroup));
+    const int32_t b = ip.b, j = ip.j, S = ip.S;
     unsigned long long *slot = S > 1 ? slots + split_slot(block_items[b], b, j) * B : nullptr;
     merge_pr_block<BF16OUT, WIDE>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in,
                                   damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
@@ -460,9 +477,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *
         __syncthreads();  // LDS reuse across blocks
         const int gi = block_graph[gb];
         const MultiDesc &d = desc[gi];
-        merge_pr_block<false, false>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B, (int)(gb - d.block_base), 0, 1,
-                              d.rank[parity], d.out_degree, d.scalars[parity], damping, d.rank[1 - parity],
-                              d.contrib[1 - parity], blk + gb * 4, nullptr, smem);
+        // one vertex per pass in the update keeps this kernel within 64 VGPRs
+        // (two workgroups per CU)
+        merge_pr_block<false, false, 1>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B,
+                                        (int)(gb - d.block_base), 0, 1, d.rank[parity], d.out_degree,
+                                        d.scalars[parity], damping, d.rank[1 - parity], d.contrib[1 - parity],
+                                        blk + gb * 4, nullptr, smem);
     }
 }
 

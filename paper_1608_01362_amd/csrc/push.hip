@@ -141,9 +141,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
     if ((int32_t)blockIdx.x >= total) return;  // the grid is the bound max_items
     // neighbouring blocks share the cache lines at the ends of their row ranges:
     // groups of them run on one XCD at once, so partial lines meet in its L2
-    const int32_t it = xcd_group_map(blockIdx.x, total, kExpandGroup);
-    const int32_t b = block_of_item(block_items, nb, it);
-    const int32_t j = it - block_items[b], S = block_items[b + 1] - block_items[b];
+    const ItemPlace ip = place_item(block_items, nb, total, xcd_group_map(blockIdx.x, total, kExpandGroup));
+    const int32_t b = ip.b, j = ip.j, S = ip.S;
     uint32_t *xs = reinterpret_cast<uint32_t *>(smem);
     int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 4, 16));
     int32_t *pre = ofs + k;
