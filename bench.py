@@ -162,7 +162,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed iterations first (the GPU's clocks settle within a few tens of them)")
     ap.add_argument("--scale", type=int, default=25)
     ap.add_argument("--edge-factor", type=int, default=32)
     ap.add_argument("--seed", type=int, default=3)
@@ -180,7 +181,8 @@ def main():
     ap.add_argument("--no-clustered-line", action="store_true",
                     help="skip the extra measurement of the same graph after clustering")
     ap.add_argument("--workload", default="pagerank",
-                    choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart", "cluster", "cf", "bc", "push"],
+                    choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart", "cluster", "cf", "bc", "push",
+                             "nsweep"],
                     help="pagerank: the headline line (default); the others measure the secondary "
                          "configurations and print their own JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -27,6 +27,10 @@ push        push-direction segmenting (expand, per-piece LDS scatter, update):
             of the reverse graph, segment sizes swept, against the pull iteration
             on the same graph; label propagation on the symmetrized R-MAT 22
             (push against pull, same segmentation)
+nsweep      PageRank iteration time, Q and q per segment size N on R-MAT scale 25 /
+            ef 32 / seed 3 (the headline graph): LDS-sized N (8,192 ... 40,960),
+            an L2-sized N (2^20 vertices, 4 MB of FP32 values), an
+            Infinity-Cache-sized N (2^24) and one segment (the plain pull)
 cluster     frequency-based clustering (Section 5) then segmenting, R-MAT scale 25
             / ef 32 / seed 3 (the headline graph): clustering time, expansion
             factor q, PageRank iteration time and time to L1 residual < 1e-6,
@@ -434,6 +438,28 @@ def push(args, log):
             "dtype": "f32", "data": "synthetic"}
 
 
+def nsweep(args, log):
+    import torch
+    import graphgen
+    from paper_1608_01362_amd import cagra
+    g = graphgen.rmat_graph(args.scale, args.edge_factor, args.seed)
+    dg = cagra.DeviceGraph.from_host(g)
+    rows = []
+    for N in (8192, 16384, 24576, 32768, 40960, 1 << 20, 1 << 24, g.V):
+        seg = cagra.build_segments(dg, N, args.B, args.tile_edges)
+        total, g_ms, m_ms = _pagerank_timing(cagra, dg, seg, 10, 2)
+        rows.append({"N": N, "k": seg.k, "Q": seg.Q, "q": round(seg.q, 3),
+                     "edge_word_bytes": 2 if N <= cagra.EDGE16_MAX_N else 4,
+                     "ms_per_iteration": round(total, 4), "gather_ms": round(g_ms, 4), "merge_ms": round(m_ms, 4),
+                     "GTEPS": round(g.E / (total * 1e-3) / 1e9, 2)})
+        log(f"N={N}: k={seg.k} q={seg.q:.3f} {total:.3f} ms/iter (gather {g_ms:.3f}, merge {m_ms:.3f})")
+        del seg
+        torch.cuda.empty_cache()
+    return {"metric": "PageRank ms per iteration by segment size", "unit": "ms", "data": "synthetic",
+            "config": {"workload": f"pagerank_rmat{args.scale}_ef{args.edge_factor}_seed{args.seed}",
+                       "V": g.V, "E": g.E, "B": args.B, "tile_edges": args.tile_edges}, "rows": rows}
+
+
 def run(name, args, log):
     return {"labelprop": labelprop, "ppr": ppr, "multigraph": multigraph, "warmstart": warmstart,
-            "cluster": cluster, "cf": cf, "bc": bc, "push": push}[name](args, log)
+            "cluster": cluster, "cf": cf, "bc": bc, "push": push, "nsweep": nsweep}[name](args, log)
