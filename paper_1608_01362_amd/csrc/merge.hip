@@ -369,6 +369,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     // the grid is the bound max_items; slots past the actual item count exit,
     // and the XCD remap spreads the actual items (not the bound) over the XCDs
     const int32_t total = block_items[nb];
+    if (total > (int32_t)gridDim.x) {
+        // a bound below the item count (an invalid max_items): the slot
+        // workspace may be too small, so nothing is merged and the scalars
+        // become NaN (block 0's partial sums feed the reduction)
+        if (blockIdx.x == 0 && threadIdx.x < 4) blk[threadIdx.x] = __builtin_nan("");
+        return;
+    }
     if ((int32_t)blockIdx.x >= total) return;  // uniform over the workgroup
     const ItemPlace ip = place_item(block_items, nb, total, xcd_group_map(blockIdx.x, total, kItemGroup));
     const int32_t b = ip.b, j = ip.j, S = ip.S;
@@ -383,8 +390,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
 constexpr int kSlotParts = 8;
 constexpr int kSlotThreads = 256;
 __global__ __launch_bounds__(kSlotThreads) void k_slot_sum(const int32_t *__restrict__ block_items, int32_t V,
-                                                           int32_t B, int32_t parts,
+                                                           int32_t B, int32_t nb, int32_t max_items, int32_t parts,
                                                            unsigned long long *__restrict__ slots) {
+    if (block_items[nb] > max_items) return;  // invalid bound: slots not written (see k_merge_pr)
     const int32_t b = blockIdx.x / parts, part = blockIdx.x % parts;
     const int32_t S = block_items[b + 1] - block_items[b];
     if (S <= 1) return;  // merged in one piece
@@ -415,10 +423,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int32_t *__restrict__ block_items, int32_t V, int32_t B, int32_t nb, const float *__restrict__ rank_in,
     const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
     float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk,
-    const unsigned long long *__restrict__ slots) {
+    const unsigned long long *__restrict__ slots, int32_t max_items) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ double red[16];
     const int32_t b = blockIdx.x;
+    if (block_items[nb] > max_items) return;  // invalid bound: slots not written (see k_merge_pr)
     if (block_items[b + 1] - block_items[b] <= 1) return;  // merged in one piece
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     const int64_t vb = (int64_t)b * B;
@@ -717,12 +726,12 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
     // and the slot pass has nothing to do
     if (seg->max_items > seg->nb) {
         const int32_t parts = (int64_t)seg->nb * kSlotParts <= INT32_MAX ? kSlotParts : 1;
-        k_slot_sum<<<(unsigned)((int64_t)seg->nb * parts), kSlotThreads, 0, st>>>(seg->block_items, seg->V, seg->B,
-                                                                                parts, slots);
+        k_slot_sum<<<(unsigned)((int64_t)seg->nb * parts), kSlotThreads, 0, st>>>(
+            seg->block_items, seg->V, seg->B, seg->nb, seg->max_items, parts, slots);
         CAGRA_LAUNCH_CHECK();
         k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
             seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
-            contrib_out, blk, slots);
+            contrib_out, blk, slots, seg->max_items);
         CAGRA_LAUNCH_CHECK();
     }
     k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out);

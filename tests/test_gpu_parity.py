@@ -292,6 +292,30 @@ def test_abi_errors_on_device(cagra):
     del ctypes
 
 
+def test_merge_item_bound_below_count(cagra):
+    """max_items below the built item count is invalid: the workspace sized
+    from it has no room for the slots of split blocks, so the merge touches no
+    slot, merges nothing and turns the scalars into NaN; the exact count (what
+    the binding sets after the build) gives the normal result."""
+    g = graphgen.from_edge_list(5001, [(i, 0) for i in range(1, 5001)] + [(0, 1), (2, 3)])
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 64, 256, 4096)
+    total, nb = int(_host(seg.arrays["block_items"])[-1]), int(seg.c.nb)
+    assert total > nb and seg.c.max_items == total  # a split block; bound lowered to the count
+    st = cagra.PageRankState(dg, seg)
+    st.start()
+    st.step()
+    assert np.isfinite(_host(st.scalars_now)).all()
+    seg.c.max_items = nb
+    try:
+        bad = cagra.PageRankState(dg, seg)  # its workspace holds no slots
+        bad.start()
+        bad.step()
+        assert np.isnan(_host(bad.scalars_now)).all()
+    finally:
+        seg.c.max_items = total
+
+
 @pytest.mark.parametrize("name", ["instar", "clustered_rmat14"])
 def test_fused_merge_split_blocks(cagra, name):
     """Merge blocks with far more entries than the mean are split into several
