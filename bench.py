@@ -353,9 +353,17 @@ def main():
         del pst, pseg
         torch.cuda.empty_cache()
         # the paper's lower-bound control (Section 1, figure of PageRank times on
-        # RMAT27, last bar): the same plain pull with every read sent to vertex
-        # 0, so no gather reaches DRAM at random (results not meaningful)
-        src0 = torch.zeros_like(dg.in_sources)
+        # RMAT27, last bar): the same plain pull with its reads sent to the
+        # lowest vertex ids, so no gather reaches DRAM at random (results not
+        # meaningful). The paper sends every read to vertex 0; to keep the
+        # graph a valid CSC (ascending, distinct sources, no self-loops) row v
+        # of in-degree d reads vertices 0..d-1, skipping v, a prefix of a few
+        # hundred KB that stays in cache.
+        off = dg.in_offsets.long()
+        row = torch.repeat_interleave(torch.arange(V, device="cuda"), off[1:] - off[:-1])
+        pos = torch.arange(E, device="cuda") - off[:-1][row]
+        src0 = (pos + (pos >= row).long()).int()
+        del off, row, pos
         dg0 = cagra.DeviceGraph(V, E, dg.in_offsets, src0, dg.out_degree,
                                 cagra.CGraph(V, E, dg.in_offsets.data_ptr(), src0.data_ptr(),
                                              dg.out_degree.data_ptr()))
@@ -370,9 +378,9 @@ def main():
         p1e.record()
         torch.cuda.synchronize()
         z_ms = p0e.elapsed_time(p1e) / pk
-        plain["all_reads_vertex0"] = {"ms_per_step": round(z_ms, 4),
+        plain["reads_of_lowest_ids_only"] = {"ms_per_step": round(z_ms, 4), "max_source": int(src0.max().item()),
                                       "segmented_over_lower_bound": round(ms_per_step / z_ms, 3)}
-        log(f"plain with every read of vertex 0 (lower bound): {z_ms:.3f} ms/step")
+        log(f"plain with reads of the lowest vertex ids only (lower bound): {z_ms:.3f} ms/step")
         del zst, zseg, dg0, src0
         torch.cuda.empty_cache()
 
