@@ -127,9 +127,11 @@ typedef struct {
     size_t build_workspace_bytes;
     int32_t max_items;    /* bound on block_items[nb]; a caller may lower it to
                              block_items[nb] once the build has run (no split
-                             block then saves the merge's slot pass). Below
-                             block_items[nb] it is invalid: the PageRank merge
-                             then merges nothing and its scalars come out NaN */
+                             block then saves the merge's slot pass). Set to
+                             nb, every block is merged whole by one work item.
+                             Between nb and block_items[nb] it is invalid: the
+                             PageRank merge then merges nothing and its scalars
+                             come out NaN */
     /* device arrays */
     int32_t *seg_row_begin;
     int32_t *row_ptr;

@@ -364,11 +364,15 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const int32_t *__restrict__ block_items, const float *__restrict__ partial, int32_t V, int32_t k, int32_t B,
     int32_t nb, const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
     const double *__restrict__ scalars_in, double damping, float *__restrict__ rank_out,
-    void *__restrict__ contrib_out, double *__restrict__ blk, unsigned long long *__restrict__ slots) {
+    void *__restrict__ contrib_out, double *__restrict__ blk, unsigned long long *__restrict__ slots,
+    int32_t one_item) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // the grid is the bound max_items; slots past the actual item count exit,
-    // and the XCD remap spreads the actual items (not the bound) over the XCDs
-    const int32_t total = block_items[nb];
+    // and the XCD remap spreads the actual items (not the bound) over the XCDs.
+    // one_item (the bound equals nb): every block is one item, known without
+    // reading the item table; each block is then merged whole, which is right
+    // whatever the table holds
+    const int32_t total = one_item ? nb : block_items[nb];
     if (total > (int32_t)gridDim.x) {
         // a bound below the item count (an invalid max_items): the slot
         // workspace may be too small, so nothing is merged and the scalars
@@ -719,7 +723,8 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
         reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + ws_blk_bytes(seg->V, seg->nb));
     k_merge_pr<BF16OUT, WIDE><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
-        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots);
+        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots,
+        seg->max_items == seg->nb ? 1 : 0);
     CAGRA_LAUNCH_CHECK();
     // max_items is a bound on the item count; when it equals nb (a caller that
     // read block_items[nb] after the build may tighten it so) no block is split

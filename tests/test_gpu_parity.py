@@ -293,22 +293,29 @@ def test_abi_errors_on_device(cagra):
 
 
 def test_merge_item_bound_below_count(cagra):
-    """max_items below the built item count is invalid: the workspace sized
-    from it has no room for the slots of split blocks, so the merge touches no
-    slot, merges nothing and turns the scalars into NaN; the exact count (what
-    the binding sets after the build) gives the normal result."""
+    """max_items equal to nb makes the merge take every block whole (one work
+    item, no slots): the same ranks bit for bit as the split merge. A bound
+    between nb and the built item count is invalid: the workspace sized from it
+    has no room for the slots of split blocks, so the merge touches no slot,
+    merges nothing and turns the scalars into NaN."""
     g = graphgen.from_edge_list(5001, [(i, 0) for i in range(1, 5001)] + [(0, 1), (2, 3)])
     dg = cagra.DeviceGraph.from_host(g)
     seg = cagra.build_segments(dg, 64, 256, 4096)
     total, nb = int(_host(seg.arrays["block_items"])[-1]), int(seg.c.nb)
-    assert total > nb and seg.c.max_items == total  # a split block; bound lowered to the count
+    assert total >= nb + 2 and seg.c.max_items == total  # split blocks; bound lowered to the count
     st = cagra.PageRankState(dg, seg)
     st.start()
     st.step()
+    want = _host(st.rank_now).copy()
     assert np.isfinite(_host(st.scalars_now)).all()
-    seg.c.max_items = nb
     try:
-        bad = cagra.PageRankState(dg, seg)  # its workspace holds no slots
+        seg.c.max_items = nb
+        whole = cagra.PageRankState(dg, seg)  # no slots in its workspace
+        whole.start()
+        whole.step()
+        assert np.array_equal(_host(whole.rank_now), want)
+        seg.c.max_items = nb + 1
+        bad = cagra.PageRankState(dg, seg)  # room for two slots only
         bad.start()
         bad.step()
         assert np.isnan(_host(bad.scalars_now)).all()
