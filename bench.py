@@ -131,6 +131,18 @@ def record_traffic(args, fetch_dir, write_dir, copyf_dir, copyw_dir):
     print(json.dumps(rec["kernels"], indent=1))
 
 
+def lowest_id_sources(in_offsets):
+    """In-edge sources for the lower-bound control: row v of in-degree d reads
+    vertices 0..d-1, skipping v (so the rows stay strictly ascending, distinct
+    and free of self-loops). int32 tensor on in_offsets' device."""
+    import torch
+    off = in_offsets.long()
+    V, E = off.numel() - 1, int(off[-1].item())
+    row = torch.repeat_interleave(torch.arange(V, device=off.device), off[1:] - off[:-1])
+    pos = torch.arange(E, device=off.device) - off[:-1][row]
+    return (pos + (pos >= row).long()).int()
+
+
 def cpu_baseline(g, budget_s=12.0):
     import oracle
     cores = max(1, min(len(os.sched_getaffinity(0)), 16))
@@ -359,11 +371,7 @@ def main():
         # graph a valid CSC (ascending, distinct sources, no self-loops) row v
         # of in-degree d reads vertices 0..d-1, skipping v, a prefix of a few
         # hundred KB that stays in cache.
-        off = dg.in_offsets.long()
-        row = torch.repeat_interleave(torch.arange(V, device="cuda"), off[1:] - off[:-1])
-        pos = torch.arange(E, device="cuda") - off[:-1][row]
-        src0 = (pos + (pos >= row).long()).int()
-        del off, row, pos
+        src0 = lowest_id_sources(dg.in_offsets)
         dg0 = cagra.DeviceGraph(V, E, dg.in_offsets, src0, dg.out_degree,
                                 cagra.CGraph(V, E, dg.in_offsets.data_ptr(), src0.data_ptr(),
                                              dg.out_degree.data_ptr()))
