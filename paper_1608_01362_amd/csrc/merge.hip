@@ -583,16 +583,41 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int b = xcd_remap(blockIdx.x, nb);
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = labels_in[vb + i];
+    // kEpiBatch labels per thread and pass, loaded together (one memory round
+    // trip per pass) before the accumulators take them
+    for (int i0 = threadIdx.x; i0 < nv; i0 += kMergeThreads * kEpiBatch) {
+        int32_t l[kEpiBatch];
+#pragma unroll
+        for (int u = 0; u < kEpiBatch; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            l[u] = i < nv ? labels_in[vb + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kEpiBatch; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            if (i < nv) acc[i] = l[u];
+        }
+    }
     const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
     stream_block<int32_t, false>(row_dst_lo, partial, ofs, pre, k, 0, P,
                           [&](int32_t d, int32_t x) { atomicMin(&acc[d], x); });
     __syncthreads();
     int32_t changed = 0;
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) {
-        const int32_t l = acc[i];
-        labels_out[vb + i] = l;
-        changed += (l != labels_in[vb + i]) ? 1 : 0;
+    for (int i0 = threadIdx.x; i0 < nv; i0 += kMergeThreads * kEpiBatch) {
+        int32_t old[kEpiBatch];
+#pragma unroll
+        for (int u = 0; u < kEpiBatch; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            old[u] = i < nv ? labels_in[vb + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kEpiBatch; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            if (i >= nv) break;
+            const int32_t l = acc[i];
+            labels_out[vb + i] = l;
+            changed += (l != old[u]) ? 1 : 0;
+        }
     }
     for (int dd = 32; dd >= 1; dd >>= 1) changed += __shfl_down(changed, dd, 64);
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = changed;
