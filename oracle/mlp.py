@@ -72,22 +72,12 @@ def gelu_grad(x):
     return 0.5 * (1.0 + _erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
-def round_bf16(x):
-    """Round to the nearest BF16 value (ties to even), via the FP32 value."""
-    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def forward(p, X, mean, std, bf16_hidden=False):
-    """bf16_hidden: the first layer's outputs are rounded to BF16 before the
-    64 x 64 product (as when that product runs with BF16 inputs)."""
+def forward(p, X, mean, std):
+    """y for each row of X; also returns the intermediates (Z, z1, h1, z2, h2)."""
     W1, b1, W2, b2, w3, b3 = unpack(p)
     Z = (np.asarray(X, dtype=np.float64) - mean) / std
     z1 = Z @ W1.T + b1
     h1 = gelu(z1)
-    if bf16_hidden:
-        h1 = round_bf16(h1)
     z2 = h1 @ W2.T + b2
     h2 = gelu(z2)
     y = h2 @ w3 + b3

@@ -100,7 +100,11 @@ __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bi
 // u = 32s + 8(l/16) + t of row l%16 directly in the A-operand layout, holds the
 // BF16 weights of W2 as B operands for the whole kernel, and receives
 // z2[4(l/16) + r][16c + l%16] in the accumulators; the output layer is a
-// 16-lane butterfly sum.
+// 16-lane butterfly sum. The weights are BF16 by definition; the FP32
+// activations are not, so each one enters the product as two BF16 operands,
+// hi = bf16(h) and lo = bf16(h - hi) (|h - hi - lo| <= 2^-18 |h|), and both
+// halves are accumulated: the hidden product keeps FP32-level accuracy for
+// twice the (cheap) matrix instructions.
 __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__restrict__ feats, int64_t n,
                                                              const uint16_t *__restrict__ wb,
                                                              const float *__restrict__ norm,
@@ -141,18 +145,23 @@ __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__rest
         const float x0 = live ? (feats[r * 3 + 0] - m0) * s0 : 0.0f;
         const float x1 = live ? (feats[r * 3 + 1] - m1) * s1 : 0.0f;
         const float x2 = live ? (feats[r * 3 + 2] - m2) * s2 : 0.0f;
-        bf16x8 A[2];
+        bf16x8 A[2], Alo[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int q = 8 * s + t;
-                A[s][t] = (__bf16)gelu(fmaf(w1[q][2], x2, fmaf(w1[q][1], x1, fmaf(w1[q][0], x0, b1[q]))));
+                const float h = gelu(fmaf(w1[q][2], x2, fmaf(w1[q][1], x1, fmaf(w1[q][0], x0, b1[q]))));
+                const __bf16 hi = (__bf16)h;
+                A[s][t] = hi;
+                Alo[s][t] = (__bf16)(h - (float)hi);
             }
         float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo[0], B[c][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo[1], B[c][1], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[c][0], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[c][1], acc, 0, 0, 0);
 #pragma unroll
@@ -332,11 +341,7 @@ cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *w
 
 cagra_status launch_mlp_grad(const float *feats, const float *target, int64_t n, const uint16_t *wb,
                              const float *norm, float *grad, double *loss, void *ws, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_mlp_backward)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_mlp_backward)) return a_;
     float *pg = (float *)ws;
     double *pl = (double *)((char *)ws + align_up((size_t)kBwdGrid * kNParam * 4, 256));
     k_mlp_backward<<<kBwdGrid, kBwdThreads, bwd_lds_bytes(), st>>>(feats, target, n, wb, norm, pg, pl);

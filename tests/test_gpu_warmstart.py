@@ -28,6 +28,26 @@ def host_norm(net):
     return n[:3], 1.0 / n[3:]
 
 
+def forward_error_bound(p, inter):
+    """Per-row bound on |y_gpu - y| for the kernel's arithmetic against the FP64
+    definition (same BF16 weights): FP32 rounding (u = 2^-24) of the
+    standardization and of every dot product (at most n + 2 roundings for n
+    terms), the GELU error of the erf approximation (Abramowitz & Stegun 7.1.26,
+    1.5e-7, plus FP32 evaluation: 5e-7 |x| in all), the split of each hidden
+    activation into two BF16 operands (|h - hi - lo| <= 2^-18 |h|), and errors
+    carried through GELU (|GELU'| <= 1.13) and the next layer's weights."""
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(p)
+    Z, z1, h1, z2, h2 = inter
+    u = 2.0 ** -24
+    gp = 1.13
+    eg = lambda x: 5e-7 * np.abs(x)  # noqa: E731
+    dz1 = 7 * u * (np.abs(Z) @ np.abs(W1).T + np.abs(b1))
+    dh1 = gp * dz1 + eg(z1)
+    dz2 = (dh1 + 2.0 ** -18 * np.abs(h1)) @ np.abs(W2).T + 130 * u * (np.abs(h1) @ np.abs(W2).T + np.abs(b2))
+    dh2 = gp * dz2 + eg(z2)
+    return dh2 @ np.abs(w3) + 66 * u * (np.abs(h2) @ np.abs(w3) + abs(b3)) + 1e-30
+
+
 def test_features_match_reference(mods):
     cagra, ws = mods
     g = graphgen.rmat_graph(14, 16, 3)
@@ -51,13 +71,13 @@ def test_forward_and_gradient_match_reference(mods):
     Td = torch.from_numpy(t.astype(np.float32)).cuda()
     p = bf16_params(net)
     mean, std = host_norm(net)
-    # the hidden 64 x 64 product takes BF16 inputs on the matrix cores
-    y_ref, _ = mlp.forward(p, X.astype(np.float32).astype(np.float64), mean, std, bf16_hidden=True)
+    y_ref, inter = mlp.forward(p, X.astype(np.float32).astype(np.float64), mean, std)
     y = net.forward(Fd).double().cpu().numpy()
     err = np.abs(y - y_ref)
-    print(f"forward: max abs err {err.max():.3e}, 99.9th pct {np.quantile(err, 0.999):.3e}")
-    assert np.quantile(err, 0.999) <= 1e-4 * max(1.0, np.max(np.abs(y_ref)))
-    assert err.max() <= 1e-2 * max(1.0, np.max(np.abs(y_ref)))  # rare BF16 rounding flips of a hidden unit
+    bound = forward_error_bound(p, inter)
+    print(f"forward: max abs err {err.max():.3e}, max err/bound {np.max(err / bound):.3f}, "
+          f"bound median {np.median(bound):.3e}")
+    assert np.all(err <= bound)
     loss_ref, g_ref = mlp.loss_and_grad(p, X.astype(np.float32).astype(np.float64), t.astype(np.float32), mean, std)
     g, loss = net.grad(Fd, Td)
     g = g.double().cpu().numpy()

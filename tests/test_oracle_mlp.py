@@ -59,10 +59,3 @@ def test_features_bruteforce():
 def test_start_vector_is_softmax():
     y = np.array([0.0, math.log(2.0), math.log(3.0)])
     assert np.allclose(mlp.start_vector(y), [1 / 6, 2 / 6, 3 / 6], atol=1e-15)
-
-
-def test_round_bf16_known_values():
-    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even -> 1; 1 + 3*2^-8 -> 1 + 2^-6
-    assert mlp.round_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
-    assert mlp.round_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
-    assert mlp.round_bf16(np.array([-2.5]))[0] == -2.5
