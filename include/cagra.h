@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CAGRA_ABI_VERSION 1
+#define CAGRA_ABI_VERSION 2
 
 typedef enum {
     CAGRA_OK = 0,
@@ -42,7 +42,11 @@ typedef enum {
     CAGRA_E_OVERFLOW = -2,  /* a count would not fit in int32 */
     CAGRA_E_CAPACITY = -3,  /* parameter beyond a kernel capacity (LDS bytes, segment count) */
     CAGRA_E_BUFFER = -4,    /* workspace too small or misaligned */
-    CAGRA_E_HIP = -5        /* a HIP runtime call or kernel launch failed */
+    CAGRA_E_HIP = -5,       /* a HIP runtime call or kernel launch failed */
+    CAGRA_E_NOT_CONVERGED = -6, /* an iteration cap was reached before the stopping rule held */
+    CAGRA_E_RANGE = -7      /* values outside the range the exact fixed-point merge sums
+                               (non-finite, or an absolute buffer mass of 64 or more in one
+                               merge block); the results of that iteration are not exact */
 } cagra_status;
 
 /* Element types of vertex values gathered by the segment processing step. */
@@ -272,7 +276,9 @@ size_t cagra_push_workspace_bytes(const cagra_segments *seg_t);
  * One PageRank iteration in the push direction: same formula, scalars and
  * start (cagra_pagerank_init with CAGRA_F32) as cagra_pagerank_iter; FP32
  * contributions. g is the graph itself (out_degree), seg_t the segmentation
- * of its reverse; vals is float[seg_t->Q] scratch.
+ * of its reverse; vals is float[seg_t->Q] scratch. scalars_out[3] carries
+ * scalars_in[3] unchanged: the push scatter does not check the range of its
+ * values.
  */
 cagra_status cagra_pagerank_push_iter(const cagra_graph *g, const cagra_segments *seg_t, double damping,
                                       const float *rank_in, const float *contrib_in, const double *scalars_in,
@@ -348,7 +354,8 @@ cagra_status cagra_merge(const cagra_segments *seg, int32_t op, const void *part
  * PageRank start: contrib_out[v] = rank[v] / out_degree[v] (0 where the
  * out-degree is 0) stored as contrib_type (CAGRA_F32 or CAGRA_BF16, round to
  * nearest even); scalars_out[0] = dangling mass sum_{out_degree=0} rank (FP64),
- * scalars_out[1] = 0, scalars_out[2] = sum of rank (FP64), scalars_out[3] = 0.
+ * scalars_out[1] = 0, scalars_out[2] = sum of rank (FP64), scalars_out[3] =
+ * number of non-finite rank values (the range count, see cagra_pagerank_iter).
  * The workspace needs 32*ceil(V/16384) + 256 bytes (the iteration workspace
  * of any segmentation of the graph is large enough).
  */
@@ -363,13 +370,20 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
  *   rank_out[v] = (1-d)/V + d * ( sum_{u->v} contrib_in[u] + scalars_in[0]/V )
  *   contrib_out[v] = rank_out[v] / out_degree[v] (0 if out_degree is 0)
  *   scalars_out[0] = dangling mass of rank_out, scalars_out[1] = ||rank_out - rank_in||_1,
- *   scalars_out[2] = sum of rank_out, scalars_out[3] = 0   (all FP64)
+ *   scalars_out[2] = sum of rank_out,
+ *   scalars_out[3] = range count: scalars_in[3] plus the number of merge blocks
+ *                    whose buffer values were non-finite or summed to 64 or more in
+ *                    absolute value   (all FP64)
  * partial is float[Q] scratch for the per-subgraph buffers. The merge adds the
  * FP32 buffer values exactly (each truncated toward zero to a multiple of 2^-56 and summed
- * as int64), so its result does not depend on the order of the additions;
- * buffer sums must stay below 64 in magnitude (true for rank vectors that sum
- * to at most 1). contrib_in is read with contrib_type, contrib_out written with
- * it. scalars_in must not alias scalars_out. Requires
+ * as int64), so its result does not depend on the order of the additions.
+ * That is exact while each merge block's buffer values sum to less than 64 in
+ * absolute value, which holds for non-negative rank vectors of mass at most 1;
+ * every block outside that range is counted in scalars_out[3], which carries
+ * over from iteration to iteration, so a non-zero count after any number of
+ * iterations means some iteration was not exact (cagra_pagerank_solve then
+ * returns CAGRA_E_RANGE). contrib_in is read with contrib_type, contrib_out
+ * written with it. scalars_in must not alias scalars_out. Requires
  * 8*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES.
  */
 cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
@@ -390,11 +404,60 @@ cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *se
                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * PageRank power iteration to a residual threshold (the Section 4 program's
+ * loop of EdgeMap and VertexMap, run until the L1 change falls below tol),
+ * driven from the host: cagra_pagerank_init, then cagra_pagerank_iter steps;
+ * after every check_every-th step the scalars are read back (the call
+ * SYNCHRONIZES the stream there) and the loop stops at the first L1 residual
+ * below tol.
+ *   rank0, rank1       float[V] pair; rank0 holds the start vector on entry
+ *   contrib0, contrib1 contribution pair: float[V] for CAGRA_F32 or when
+ *                      switch_tol > 0, uint16[V] for CAGRA_BF16 otherwise
+ *   scalars            double[8]: the two scalar sets of the pair
+ *   partial, workspace as for cagra_pagerank_iter
+ * BF16 finishing switch: with contrib_type CAGRA_BF16 and switch_tol > 0, the
+ * first residual read below switch_tol rebuilds the contributions as FP32 from
+ * the current ranks (cagra_pagerank_init) and the remaining iterations gather
+ * FP32, so the answer is no longer limited by BF16 rounding.
+ * The result is in rank[host_result->final_buf] and contrib[...] (the latter in
+ * FP32 once switched). Returns CAGRA_OK when the residual fell below tol,
+ * CAGRA_E_NOT_CONVERGED when max_iters steps ran without that (host_result
+ * still describes the last iterate), CAGRA_E_RANGE when a read-back range count
+ * (scalars[3]) is non-zero, or the status of a failed step.
+ */
+typedef struct {
+    double damping;        /* d in [0, 1] */
+    double tol;            /* stopping threshold on the L1 residual, > 0 */
+    double switch_tol;     /* CAGRA_BF16 only: residual below which to finish in FP32 (0: never) */
+    int32_t max_iters;     /* iteration cap, >= 1 */
+    int32_t check_every;   /* read the residual back every this many iterations, >= 1 */
+    int32_t contrib_type;  /* CAGRA_F32 or CAGRA_BF16 */
+} cagra_pr_params;
+typedef struct {
+    int32_t iters;         /* iterations run */
+    int32_t iters_bf16;    /* of which gathered BF16 contributions */
+    int32_t final_buf;     /* 0 or 1: which buffer of each pair holds the result */
+    double residual;       /* last L1 residual read back (inf before the first) */
+    double scalars[4];     /* last scalars read back (as cagra_pagerank_iter) */
+} cagra_pr_result;
+cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *seg, const cagra_pr_params *params,
+                                  float *rank0, float *rank1, void *contrib0, void *contrib1, double *scalars,
+                                  float *partial, void *workspace, size_t workspace_bytes,
+                                  cagra_pr_result *host_result, hipStream_t stream);
+
+/*
  * One synchronous min-label propagation step on a segmented undirected graph
- * (both edge directions present):
+ * (both edge directions present). Label propagation is one of the paper's
+ * applications (Section 6.1: it reads one integer label per vertex and needs no
+ * activeness check); it runs as the Section 4 program with EdgeUpdate = take
+ * the source's label, Merge = minimum, VertexMap = keep the smaller of the
+ * merged and the own label:
  *   labels_out[v] = min(labels_in[v], min over in-neighbours u of labels_in[u])
- * partial is int32[Q] scratch; *changed_out (device int32) = number of v whose
- * label changed.
+ * The segment processing (Section 3.2) gathers minima per subgraph row into
+ * partial, int32[Q] scratch; the cache-aware merge (Section 3.3) combines them
+ * with int32 minimum (exact, order-free). *changed_out (device int32) = number
+ * of v whose label changed. Repeated until no label changes, the labels reach
+ * the smallest vertex id of each connected component.
  */
 cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,
                                   int32_t *labels_out, int32_t *changed_out, void *workspace,
@@ -474,7 +537,9 @@ cagra_status cagra_multi_setup(cagra_multi *m, const cagra_graph *graphs, const 
 /* Uniform start vectors of every graph into pools [0]. */
 cagra_status cagra_multi_pagerank_start(const cagra_multi *m, hipStream_t stream);
 /* One PageRank iteration (as cagra_pagerank_iter, FP32 contributions) of every
-   graph: reads pools [parity], writes pools [1 - parity]. */
+   graph: reads pools [parity], writes pools [1 - parity]. Each graph's range
+   count scalars[.][3] carries over from step to step, as in cagra_pagerank_iter
+   (the start vectors set it to 0). */
 cagra_status cagra_multi_pagerank_step(const cagra_multi *m, int32_t parity, double damping, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
@@ -498,10 +563,11 @@ cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *s
 
 /*
  * y[r] = network(standardized features[r]) for r < n. weights: BF16
- * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. Exact GELU (erf);
- * FP32 arithmetic except the 64 x 64 hidden product, which runs on the matrix
- * cores with BF16 inputs (first-layer outputs rounded to BF16) and FP32
- * accumulation.
+ * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. GELU with erf from
+ * Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7); FP32 arithmetic. The 64 x 64
+ * hidden product runs on the matrix cores with the BF16 weights and each FP32
+ * activation split into two BF16 parts (hi + lo, within 2^-18 relative),
+ * accumulated in FP32.
  */
 cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t *weights, const float *norm,
                                float *y, hipStream_t stream);

@@ -17,7 +17,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcagra.so")
 
 # enums of include/cagra.h
-OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_BUFFER, E_HIP = 0, -1, -2, -3, -4, -5
+OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_BUFFER, E_HIP, E_NOT_CONVERGED, E_RANGE = 0, -1, -2, -3, -4, -5, -6, -7
+ABI_VERSION = 2
 F32, BF16, I32 = 0, 1, 2
 SUM_F32, MIN_I32, SUM_F32_COMP = 0, 1, 2
 LDS_BYTES = 163840
@@ -51,12 +52,22 @@ EXPORTS = [
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
     "cagra_validate_workspace_bytes", "cagra_validate_graph",
-    "cagra_pagerank_merge", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
+    "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
     "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
     "cagra_warm_start_vector",
 ]
+
+
+class CPrParams(ctypes.Structure):
+    _fields_ = [("damping", _c_dbl), ("tol", _c_dbl), ("switch_tol", _c_dbl), ("max_iters", _c_i32),
+                ("check_every", _c_i32), ("contrib_type", _c_i32)]
+
+
+class CPrResult(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("iters_bf16", _c_i32), ("final_buf", _c_i32), ("residual", _c_dbl),
+                ("scalars", _c_dbl * 4)]
 
 
 class CMulti(ctypes.Structure):
@@ -71,6 +82,26 @@ class CagraError(RuntimeError):
     def __init__(self, status: int, fn: str, detail: str):
         super().__init__(f"{fn} -> {status} ({detail})")
         self.status = status
+
+
+class NotConverged(CagraError):
+    """An iteration cap was reached before the residual fell below tol; `result`
+    holds what the run produced (for pagerank: (rank, residuals, steps))."""
+
+    def __init__(self, fn: str, detail: str, result=None):
+        super().__init__(E_NOT_CONVERGED, fn, detail)
+        self.result = result
+
+
+def check_range(scalars, fn: str = "pagerank"):
+    """Raise CagraError(E_RANGE) when an iteration's range count (scalars[3],
+    carried over from iteration to iteration) is non-zero: some merge block held
+    non-finite buffer values or more absolute mass than the exact fixed-point
+    sums allow, so the ranks are not exact. Reads the device scalars (syncs)."""
+    c = float(scalars[3].item())
+    if c != 0.0:
+        raise CagraError(E_RANGE, fn, f"range count {c:g}: buffer values non-finite or beyond the exact "
+                                      "fixed-point range in some iteration")
 
 
 _lib = None
@@ -112,6 +143,8 @@ def lib():
             "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_pagerank_solve": ([GP, SP, ctypes.POINTER(CPrParams), _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                      _c_vp, _c_size, ctypes.POINTER(CPrResult), st], ctypes.c_int),
             "cagra_push_workspace_bytes": ([SP], _c_size),
             "cagra_validate_workspace_bytes": ([], _c_size),
             "cagra_validate_graph": ([GP, _c_vp, _c_size, st], ctypes.c_int),
@@ -140,6 +173,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        if L.cagra_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"libcagra.so ABI {L.cagra_abi_version()} != binding ABI {ABI_VERSION}; rebuild")
         _lib = L
     return _lib
 
@@ -406,25 +441,81 @@ class PageRankState:
         return self.scalars[self.cur]
 
 
+@dataclass
+class SolveResult:
+    rank: object          # device float32 [V]
+    iters: int
+    iters_bf16: int
+    residual: float
+    scalars: list
+    converged: bool
+
+
+def pagerank_solve(dg: DeviceGraph, seg: Segments, tol: float = 1e-6, max_iters: int = 100, damping: float = 0.85,
+                   contrib_type: int = F32, switch_tol: float = 0.0, rank0=None, check_every: int = 1,
+                   stream=None, state: "SolveBuffers | None" = None) -> SolveResult:
+    """cagra_pagerank_solve: power iteration to the first L1 residual < tol (the
+    library's host-driven loop). BF16 contributions with switch_tol > 0 finish
+    in FP32 once the residual is below switch_tol. Returns a SolveResult with
+    converged False when max_iters ran out (CAGRA_E_NOT_CONVERGED); raises
+    CagraError for any other failure, E_RANGE included."""
+    buf = state or SolveBuffers(dg, seg, contrib_type, switch_tol)
+    if rank0 is None:
+        buf.rank[0].fill_(1.0 / dg.V)
+    else:
+        buf.rank[0].copy_(rank0)
+    p = CPrParams(damping, tol, switch_tol, max_iters, check_every, contrib_type)
+    r = CPrResult()
+    st = lib().cagra_pagerank_solve(ctypes.byref(dg.c), ctypes.byref(seg.c), ctypes.byref(p), _ptr(buf.rank[0]),
+                                    _ptr(buf.rank[1]), _ptr(buf.contrib[0]), _ptr(buf.contrib[1]), _ptr(buf.scalars),
+                                    _ptr(buf.partial), _ptr(buf.ws), buf.ws.numel(), ctypes.byref(r),
+                                    _stream(stream))
+    if st not in (OK, E_NOT_CONVERGED):
+        _check(st, "cagra_pagerank_solve")
+    return SolveResult(buf.rank[r.final_buf], int(r.iters), int(r.iters_bf16), float(r.residual),
+                       list(r.scalars), st == OK)
+
+
+class SolveBuffers:
+    """Device buffers of cagra_pagerank_solve (reusable across calls)."""
+
+    def __init__(self, dg: DeviceGraph, seg: Segments, contrib_type: int = F32, switch_tol: float = 0.0):
+        import torch
+        dev = _dev()
+        V = dg.V
+        wide = contrib_type == F32 or switch_tol > 0
+        cdt = torch.float32 if wide else torch.int16
+        self.rank = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
+        self.contrib = [torch.empty(V, dtype=cdt, device=dev) for _ in range(2)]
+        self.scalars = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.partial = torch.empty(max(seg.Q, 1), dtype=torch.float32, device=dev)
+        self.ws = iter_workspace(seg)
+
+
 def pagerank(dg: DeviceGraph, seg: Segments, iters: int = 20, damping: float = 0.85, contrib_type: int = F32,
-             tol: float = 0.0, rank0=None, check_every: int = 1):
-    """Power iteration; fixed `iters` steps, or stop at the first L1 residual < tol
-    (read back every `check_every` steps). Returns (rank tensor, residual list, steps)."""
+             tol: float = 0.0, rank0=None, check_every: int = 1, switch_tol: float = 0.0,
+             allow_not_converged: bool = False):
+    """Power iteration; fixed `iters` steps (tol 0), or stop at the first L1
+    residual < tol read back every `check_every` steps (through
+    cagra_pagerank_solve, at most `iters` steps). Returns (rank tensor, residual
+    list, steps): the list is None in fixed mode, else [last residual read].
+    Raises NotConverged when tol > 0 and the cap is reached (unless
+    allow_not_converged), and CagraError(E_RANGE) when an iteration's buffer
+    values left the exact fixed-point range."""
+    if tol > 0:
+        r = pagerank_solve(dg, seg, tol=tol, max_iters=iters, damping=damping, contrib_type=contrib_type,
+                           switch_tol=switch_tol, rank0=rank0, check_every=check_every)
+        out = (r.rank.clone(), [r.residual], r.iters)
+        if not r.converged and not allow_not_converged:
+            raise NotConverged("cagra_pagerank_solve", f"no L1 residual < {tol:g} in {iters} iterations "
+                                                       f"(last {r.residual:g})", out)
+        return out
     stt = PageRankState(dg, seg, contrib_type)
     stt.start(rank0)
-    res = []
-    steps = 0
-    for t in range(iters):
+    for _ in range(iters):
         stt.step(damping)
-        steps += 1
-        if tol > 0 and (steps % check_every == 0):
-            r = float(stt.scalars_now[1].item())
-            res.append(r)
-            if r < tol:
-                break
-    if tol <= 0:
-        res = None
-    return stt.rank_now.clone(), res, steps
+    check_range(stt.scalars_now)
+    return stt.rank_now.clone(), None, iters
 
 
 def labelprop(seg: Segments, max_iters: int = 1 << 20):

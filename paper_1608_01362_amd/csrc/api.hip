@@ -1,13 +1,30 @@
 // C ABI entry points: host-side validation, then kernel launches.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
 #include <vector>
 
 #include "common.h"
 
 namespace cagra {
+
+cagra_status ensure_dynamic_lds(const void *fn) {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CAGRA_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;  // (device, kernel) pairs already set
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({dev, fn})) return CAGRA_OK;
+    const cagra_status s = allow_dynamic_lds(fn);
+    if (s == CAGRA_OK) done.insert({dev, fn});
+    return s;
+}
 
 static thread_local char g_last_error[512] = "";
 
@@ -48,6 +65,7 @@ int32_t init_blocks(int32_t V);
 cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const float *rank, void *contrib_out,
                             double *scalars_out, void *ws, hipStream_t st);
 size_t ws_blk_bytes(int32_t V, int32_t nb);
+size_t ws_item_bytes(const cagra_segments *seg);
 size_t ws_slot_bytes(const cagra_segments *seg);
 cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
                              const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
@@ -130,7 +148,7 @@ static cagra_status check_built(const cagra_segments *seg) {
 }
 
 static size_t iter_ws_bytes(const cagra_segments *seg) {
-    return ws_blk_bytes(seg->V, seg->nb) + ws_slot_bytes(seg) + 256;
+    return ws_blk_bytes(seg->V, seg->nb) + ws_item_bytes(seg) + ws_slot_bytes(seg) + 256;
 }
 
 }  // namespace cagra
@@ -149,6 +167,8 @@ const char *cagra_status_string(int status) {
         case CAGRA_E_CAPACITY: return "CAGRA_E_CAPACITY";
         case CAGRA_E_BUFFER: return "CAGRA_E_BUFFER";
         case CAGRA_E_HIP: return "CAGRA_E_HIP";
+        case CAGRA_E_NOT_CONVERGED: return "CAGRA_E_NOT_CONVERGED";
+        case CAGRA_E_RANGE: return "CAGRA_E_RANGE";
         default: return "CAGRA_E_UNKNOWN";
     }
 }
@@ -369,6 +389,74 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
     if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
                            scalars_out, workspace, stream);
+}
+
+// Reads the four FP64 scalars of one iteration back to the host (synchronizes).
+static cagra_status read_scalars(const double *d_scalars, double (&h)[4], hipStream_t stream) {
+    CAGRA_HIP_CHECK(hipMemcpyAsync(h, d_scalars, sizeof(h), hipMemcpyDeviceToHost, stream));
+    CAGRA_HIP_CHECK(hipStreamSynchronize(stream));
+    return CAGRA_OK;
+}
+
+cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *seg, const cagra_pr_params *p,
+                                  float *rank0, float *rank1, void *contrib0, void *contrib1, double *scalars,
+                                  float *partial, void *workspace, size_t workspace_bytes,
+                                  cagra_pr_result *host_result, hipStream_t stream) {
+    cagra_status s;
+    if (!p || !host_result) return fail(CAGRA_E_INVALID, "params or host_result is NULL");
+    if ((s = check_pagerank(g, seg, p->damping, p->contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (!(p->tol > 0.0)) return fail(CAGRA_E_INVALID, "tol must be > 0");
+    if (p->max_iters < 1 || p->check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
+    if (!(p->switch_tol >= 0.0)) return fail(CAGRA_E_INVALID, "switch_tol must be >= 0");
+    if (p->switch_tol > 0.0 && p->contrib_type != CAGRA_BF16)
+        return fail(CAGRA_E_INVALID, "switch_tol applies to CAGRA_BF16 contributions only");
+    if (!rank0 || !rank1 || !contrib0 || !contrib1 || !scalars || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (rank0 == rank1 || contrib0 == contrib1) return fail(CAGRA_E_INVALID, "the two buffers of a pair must differ");
+    float *rank[2] = {rank0, rank1};
+    void *contrib[2] = {contrib0, contrib1};
+    double *sc[2] = {scalars, scalars + 4};
+    *host_result = cagra_pr_result{};
+    int32_t ct = p->contrib_type;
+    if ((s = launch_pr_init(g, ct, rank0, contrib0, sc[0], workspace, stream)) != CAGRA_OK) return s;
+    double h[4];
+    if ((s = read_scalars(sc[0], h, stream)) != CAGRA_OK) return s;
+    for (int c = 0; c < 4; ++c) host_result->scalars[c] = h[c];
+    host_result->residual = INFINITY;
+    if (h[3] != 0.0) return fail(CAGRA_E_RANGE, "the start vector holds %.0f non-finite values", h[3]);
+    int cur = 0;
+    bool converged = false;
+    while (host_result->iters < p->max_iters) {
+        if ((s = launch_gather(seg, CAGRA_SUM_F32, ct, contrib[cur], partial, stream)) != CAGRA_OK) return s;
+        if ((s = launch_merge_pr(g, seg, p->damping, ct, rank[cur], sc[cur], partial, rank[1 - cur],
+                                 contrib[1 - cur], sc[1 - cur], workspace, stream)) != CAGRA_OK)
+            return s;
+        cur = 1 - cur;
+        host_result->final_buf = cur;
+        host_result->iters++;
+        if (ct == CAGRA_BF16) host_result->iters_bf16++;
+        if (host_result->iters % p->check_every != 0 && host_result->iters < p->max_iters) continue;
+        if ((s = read_scalars(sc[cur], h, stream)) != CAGRA_OK) return s;
+        for (int c = 0; c < 4; ++c) host_result->scalars[c] = h[c];
+        host_result->residual = h[1];
+        if (h[3] != 0.0)
+            return fail(CAGRA_E_RANGE, "iteration %d: %g merge blocks held non-finite buffer values or an absolute "
+                        "buffer mass beyond the exact fixed-point range", host_result->iters, h[3]);
+        if (h[1] < p->tol) {
+            converged = true;
+            break;
+        }
+        if (ct == CAGRA_BF16 && p->switch_tol > 0.0 && h[1] < p->switch_tol) {
+            // finish in FP32: contributions rebuilt from the current ranks
+            ct = CAGRA_F32;
+            if ((s = launch_pr_init(g, ct, rank[cur], contrib[cur], sc[cur], workspace, stream)) != CAGRA_OK)
+                return s;
+        }
+    }
+    if (!converged)
+        return fail(CAGRA_E_NOT_CONVERGED, "no L1 residual below %g within %d iterations (last %g)", p->tol,
+                    p->max_iters, host_result->residual);
+    return CAGRA_OK;
 }
 
 cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,

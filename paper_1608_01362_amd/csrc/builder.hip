@@ -494,11 +494,7 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
 }
 
 static cagra_status allow_big_lds_impl() {
-    static bool done = false;
-    if (!done) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_count)) return a_;
-        done = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_count)) return a_;
     return CAGRA_OK;
 }
 

@@ -242,11 +242,7 @@ cagra_status launch_cf_iter(const cagra_segments *seg, const float *seg_values, 
                 seg->tile_span_row, seg->row_dst, x_in, seg->N, seg->ntiles, partial, tile_sq);
         CAGRA_LAUNCH_CHECK();
     }
-    static bool attr = false;
-    if (!attr) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_cf)) return a_;
-        attr = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_cf)) return a_;
     k_merge_cf<<<seg->nb, kCfThreads, cf_merge_lds_bytes(seg->B), st>>>(
         seg->row_dst, seg->block_ptr, partial, seg->V, seg->k, seg->B, seg->nb, (float)gamma, (float)lambda, x_in,
         x_out);

@@ -59,6 +59,11 @@ static inline cagra_status allow_dynamic_lds(const void *fn) {
     return CAGRA_OK;
 }
 
+// allow_dynamic_lds for `fn` once per device (thread-safe; later calls on the
+// same device return at once). Every launch with more than 64 KB of dynamic
+// LDS goes through this.
+cagra_status ensure_dynamic_lds(const void *fn);
+
 // Per-graph descriptor of the persistent multi-graph kernels (device memory).
 struct MultiDesc {
     const void *edge_src;  // 16-bit edge words (multi-graph runs use N <= CAGRA_EDGE16_MAX_N)
@@ -145,5 +150,37 @@ __device__ double block_sum_f64(double v, double *lds /* NT/64 entries */) {
     __syncthreads();
     return tot;  // valid in thread 0
 }
+
+// Four FP64 block sums at once, each in the order block_sum_f64 uses (fixed
+// shuffle tree, then waves in order); one LDS round trip for all four.
+// Results valid in thread 0.
+template <int NT>
+__device__ void block_sum4_f64(double (&v)[4], double *lds /* 4 * NT/64 entries */) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        for (int d = 32; d >= 1; d >>= 1) v[c] += __shfl_down(v[c], d, 64);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lds[c * (NT / 64) + w] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double tot = 0.0;
+            for (int i = 0; i < NT / 64; ++i) tot += lds[c * (NT / 64) + i];
+            v[c] = tot;
+        }
+    __syncthreads();
+}
+
+// Absolute buffer mass from which the int64 fixed-point sums (2^-56 per unit,
+// see fix56) could leave the exact range: a merge block whose buffer values
+// have |x| summing to this or more, or holding a non-finite value, is counted
+// in the iteration's range scalar instead of being trusted. Every partial sum
+// of a block below it stays under 2^62 in fixed point (the int64 limit is
+// 2^63), so FP rounding of the check itself cannot hide an overflow.
+constexpr double kFixAbsLimit = 64.0;
+__device__ __forceinline__ double range_flag(double absmass) { return absmass < kFixAbsLimit ? 0.0 : 1.0; }
 
 }  // namespace cagra

@@ -351,11 +351,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_multi_gather(const MultiDesc
 
 cagra_status launch_multi_gather(const MultiDesc *desc, const int32_t *tile_graph, int64_t total_tiles, int parity,
                                  int grid, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_multi_gather)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_multi_gather)) return a_;
     if (total_tiles == 0) return CAGRA_OK;
     k_multi_gather<<<grid, kGatherThreads, kStageBytes + CAGRA_STAGE_BYTES, st>>>(desc, tile_graph, total_tiles,
                                                                                    parity);
@@ -369,11 +365,7 @@ static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values,
     if (seg->ntiles == 0) return CAGRA_OK;
     auto kern = k_gather<Op, VT, STAGED, W>;
     const size_t lds = kStageBytes + (STAGED ? (size_t)seg->N * sizeof(VT) : 0);
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)kern)) return a_;
     kern<<<seg->ntiles, kGatherThreads, lds, st>>>(static_cast<const W *>(seg->edge_src), seg->E, seg->Q,
                                                   seg->tile_edge, seg->tile_seg, seg->tile_span_row, values, seg->V,
                                                   seg->N, seg->ntiles, partial, seg_active);

@@ -158,11 +158,7 @@ static cagra_status launch_ordered_t(const cagra_segments *seg, const void *part
     using T = typename Op::T;
     auto kern = k_merge_ordered<Op, COMP, STAGED>;
     size_t lds = (size_t)seg->B * sizeof(T) * (COMP ? 2 : 1) + (STAGED ? (size_t)seg->k * 8 : 0);
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)kern)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)kern)) return a_;
     kern<<<seg->nb, 64, lds, st>>>(seg->row_dst_lo, seg->block_ptr, (const T *)partial, seg->V, seg->k, seg->B,
                                    seg->nb, (T *)out, seg_active);
     CAGRA_LAUNCH_CHECK();
@@ -264,13 +260,16 @@ __device__ __forceinline__ void stream_block(const uint16_t *__restrict__ dlo, c
 constexpr int kEpiBatch = 8;  // vertices per thread whose loads are in flight together
 
 // PageRank vertex update of block b from its exact sums acc (LDS, int64 fixed
-// point); writes the block's FP64 partial sums to blk_out[0..3].
+// point); writes the block's FP64 partial sums to blk_out[0..3]: dangling mass,
+// L1 residual, mass, and the range flag (1 when the buffer values merged into
+// the block -- `am` is this thread's share of their absolute sum -- were
+// non-finite or too large for exact fixed-point sums, else 0).
 template <bool BF16OUT, int EPI = kEpiBatch>
 __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32_t V, int64_t vb, int32_t nv,
                                             const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
                                             const double *__restrict__ scalars_in, double damping,
                                             float *__restrict__ rank_out, void *__restrict__ contrib_out,
-                                            double *__restrict__ blk_out, double *red) {
+                                            double *__restrict__ blk_out, double am, double *red) {
     const double dd = damping;
     const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
     double dang = 0.0, res = 0.0, mass = 0.0;
@@ -302,50 +301,54 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
             mass += (double)r;
         }
     }
-    dang = block_sum_f64<kMergeThreads>(dang, red);
-    res = block_sum_f64<kMergeThreads>(res, red);
-    mass = block_sum_f64<kMergeThreads>(mass, red);
+    double v4[4] = {dang, res, mass, am};
+    block_sum4_f64<kMergeThreads>(v4, red);
     if (threadIdx.x == 0) {
-        blk_out[0] = dang;
-        blk_out[1] = res;
-        blk_out[2] = mass;
-        blk_out[3] = 0.0;
+        blk_out[0] = v4[0];
+        blk_out[1] = v4[1];
+        blk_out[2] = v4[2];
+        blk_out[3] = range_flag(v4[3]);
     }
 }
 
 // Item j of the S items of block b: the block's entries (flattened over
 // subgraphs) [P*j/S, P*(j+1)/S). With S == 1 the item is the whole block and
 // the vertex update follows at once. Otherwise the item stores its exact int64
-// sums in its own slot of the workspace, and k_merge_pr_finish adds the S
-// slots of the block (exactly, so the split does not change any result) and
-// applies the update.
+// sums in its own slot of the workspace and the absolute sum of its buffer
+// values in *item_abs, and k_merge_pr_finish adds the S slots of the block
+// (exactly, so the split does not change any result) and applies the update.
 template <bool BF16OUT, bool WIDE, int EPI = kEpiBatch>
 __device__ __forceinline__ void merge_pr_block(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b, int32_t j, int32_t S,
     const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
     double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
-    unsigned long long *__restrict__ slot, unsigned char *smem) {
+    unsigned long long *__restrict__ slot, double *__restrict__ item_abs, unsigned char *smem) {
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
     int32_t *pre = ofs + k;
     __shared__ int32_t tmp[16];
-    __shared__ double red[16];
+    __shared__ double red[4 * (kMergeThreads / 64)];
 
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = 0ull;
     const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
     const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
-    stream_block<float, WIDE>(row_dst_lo, partial, ofs, pre, k, F0, F1,
-                              [&](int32_t d, float x) { atomicAdd(&acc[d], fix56(x)); });
+    float am = 0.0f;  // this thread's share of the absolute buffer mass (range check)
+    stream_block<float, WIDE>(row_dst_lo, partial, ofs, pre, k, F0, F1, [&](int32_t d, float x) {
+        atomicAdd(&acc[d], fix56(x));
+        am += fabsf(x);
+    });
     __syncthreads();
     if (S > 1) {
         for (int i = threadIdx.x; i < nv; i += kMergeThreads) slot[i] = acc[i];
+        const double tot = block_sum_f64<kMergeThreads>((double)am, red);
+        if (threadIdx.x == 0) *item_abs = tot;
         return;
     }
     pr_epilogue<BF16OUT, EPI>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out, blk_out,
-                              red);
+                              (double)am, red);
 }
 
 // Slot of item j of a split block b whose first item is items_b: 2*(items_b - b)
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     int32_t nb, const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
     const double *__restrict__ scalars_in, double damping, float *__restrict__ rank_out,
     void *__restrict__ contrib_out, double *__restrict__ blk, unsigned long long *__restrict__ slots,
-    int32_t one_item) {
+    double *__restrict__ item_abs, int32_t one_item) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // the grid is the bound max_items; slots past the actual item count exit,
     // and the XCD remap spreads the actual items (not the bound) over the XCDs.
@@ -384,8 +387,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const ItemPlace ip = place_item(block_items, nb, total, xcd_group_map(blockIdx.x, total, kItemGroup));
     const int32_t b = ip.b, j = ip.j, S = ip.S;
     unsigned long long *slot = S > 1 ? slots + split_slot(block_items[b], b, j) * B : nullptr;
+    double *ia = S > 1 ? item_abs + block_items[b] + j : nullptr;
     merge_pr_block<BF16OUT, WIDE>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in,
-                                  damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, smem);
+                                  damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, ia, smem);
 }
 
 // Sum of the item slots of each split block, written into its first slot.
@@ -427,9 +431,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int32_t *__restrict__ block_items, int32_t V, int32_t B, int32_t nb, const float *__restrict__ rank_in,
     const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
     float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk,
-    const unsigned long long *__restrict__ slots, int32_t max_items) {
+    const unsigned long long *__restrict__ slots, const double *__restrict__ item_abs, int32_t max_items) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ double red[16];
+    __shared__ double red[4 * (kMergeThreads / 64)];
     const int32_t b = blockIdx.x;
     if (block_items[nb] > max_items) return;  // invalid bound: slots not written (see k_merge_pr)
     if (block_items[b + 1] - block_items[b] <= 1) return;  // merged in one piece
@@ -438,9 +442,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
     const unsigned long long *first = slots + split_slot(block_items[b], b, 0) * B;
     for (int i = threadIdx.x; i < nv; i += kMergeThreads) acc[i] = first[i];
+    // absolute buffer mass of the block: its items' sums in item order (thread 0)
+    double am = 0.0;
+    if (threadIdx.x == 0)
+        for (int32_t it = block_items[b]; it < block_items[b + 1]; ++it) am += item_abs[it];
     __syncthreads();
     pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out,
-                         blk + (int64_t)b * 4, red);
+                         blk + (int64_t)b * 4, am, red);
 }
 
 // Order-free merge of float buffer values into float sums (int64 fixed point,
@@ -467,11 +475,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_sum_fixed24(
 }
 
 cagra_status launch_merge_sum_fixed24(const cagra_segments *seg, const float *partial, float *out, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_sum_fixed24)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_sum_fixed24)) return a_;
     if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
     k_merge_sum_fixed24<<<seg->nb, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *
         merge_pr_block<false, false, 1>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B,
                                         (int)(gb - d.block_base), 0, 1, d.rank[parity], d.out_degree,
                                         d.scalars[parity], damping, d.rank[1 - parity], d.contrib[1 - parity],
-                                        blk + gb * 4, nullptr, smem);
+                                        blk + gb * 4, nullptr, nullptr, smem);
     }
 }
 
@@ -529,9 +533,10 @@ __global__ __launch_bounds__(256) void k_multi_start(const MultiDesc *__restrict
     }
 }
 
-// Per graph: fixed-order sum of its blocks' partials into scalars[parity].
+// Per graph: fixed-order sum of its blocks' partials into scalars[parity]. With
+// carry, the range count [3] also adds the previous step's (scalars[1 - parity]).
 __global__ __launch_bounds__(256) void k_multi_reduce(const MultiDesc *__restrict__ desc,
-                                                      const double *__restrict__ blk, int parity) {
+                                                      const double *__restrict__ blk, int parity, int carry) {
     __shared__ double red[4];
     const MultiDesc &d = desc[blockIdx.x];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(256) void k_multi_reduce(const MultiDesc *__restric
         for (int c = 0; c < 4; ++c) a[c] += blk[(d.block_base + j) * 4 + c];
     for (int c = 0; c < 4; ++c) {
         double t = block_sum_f64<256>(a[c], red);
-        if (threadIdx.x == 0) d.scalars[parity][c] = t;
+        if (threadIdx.x == 0) d.scalars[parity][c] = c == 3 && carry ? t + d.scalars[1 - parity][3] : t;
     }
 }
 
@@ -548,7 +553,7 @@ cagra_status launch_multi_start(const MultiDesc *desc, const int32_t *block_grap
     if (total_blocks == 0) return CAGRA_OK;
     k_multi_start<<<grid, 256, 0, st>>>(desc, block_graph, total_blocks, blk);
     CAGRA_LAUNCH_CHECK();
-    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 0);
+    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 0, 0);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -556,15 +561,11 @@ cagra_status launch_multi_start(const MultiDesc *desc, const int32_t *block_grap
 cagra_status launch_multi_merge(const MultiDesc *desc, const int32_t *block_graph, int64_t total_blocks,
                                 int32_t ngraphs, int parity, double damping, double *blk, size_t lds, int grid,
                                 hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_multi_merge)) return a_;
-        attr_set = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_multi_merge)) return a_;
     if (total_blocks == 0) return CAGRA_OK;
     k_multi_merge<<<grid, kMergeThreads, lds, st>>>(desc, block_graph, total_blocks, parity, damping, blk);
     CAGRA_LAUNCH_CHECK();
-    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 1 - parity);
+    k_multi_reduce<<<ngraphs, 256, 0, st>>>(desc, blk, 1 - parity, 1);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(256) void k_pr_init(const float *__restrict__ rank,
     __shared__ double red[4];
     const int64_t lo = (int64_t)blockIdx.x * kInitSpan;
     const int64_t hi = lo + kInitSpan < V ? lo + kInitSpan : V;
-    double dang = 0.0, mass = 0.0;
+    double dang = 0.0, mass = 0.0, bad = 0.0;
     for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
         const float r = rank[v];
         const int32_t od = outdeg[v];
@@ -648,20 +649,23 @@ __global__ __launch_bounds__(256) void k_pr_init(const float *__restrict__ rank,
         else reinterpret_cast<float *>(contrib_out)[v] = c;
         if (od == 0) dang += (double)r;
         mass += (double)r;
+        bad += isfinite(r) ? 0.0 : 1.0;
     }
     dang = block_sum_f64<256>(dang, red);
     mass = block_sum_f64<256>(mass, red);
+    bad = block_sum_f64<256>(bad, red);
     if (threadIdx.x == 0) {
         blk[(int64_t)blockIdx.x * 4 + 0] = dang;
         blk[(int64_t)blockIdx.x * 4 + 1] = 0.0;
         blk[(int64_t)blockIdx.x * 4 + 2] = mass;
-        blk[(int64_t)blockIdx.x * 4 + 3] = 0.0;
+        blk[(int64_t)blockIdx.x * 4 + 3] = bad;
     }
 }
 
-// Fixed-order FP64 reduction of n rows of 4 partial sums.
+// Fixed-order FP64 reduction of n rows of 4 partial sums. With carry non-null,
+// out[3] also adds carry[3] (the range count accumulates over iterations).
 __global__ __launch_bounds__(256) void k_reduce4(const double *__restrict__ blk, int32_t n,
-                                                 double *__restrict__ out) {
+                                                 double *__restrict__ out, const double *__restrict__ carry) {
     __shared__ double red[4];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     // four rows per thread and pass, loaded before they are added (same order)
@@ -681,7 +685,7 @@ __global__ __launch_bounds__(256) void k_reduce4(const double *__restrict__ blk,
         for (int c = 0; c < 4; ++c) a[c] += blk[(int64_t)j * 4 + c];
     for (int c = 0; c < 4; ++c) {
         double t = block_sum_f64<256>(a[c], red);
-        if (threadIdx.x == 0) out[c] = t;
+        if (threadIdx.x == 0) out[c] = c == 3 && carry ? t + carry[3] : t;
     }
 }
 
@@ -697,8 +701,8 @@ __global__ __launch_bounds__(256) void k_reduce_i32(const int32_t *__restrict__ 
 }
 
 // Fixed-order reductions of per-block partial sums (also used by the push path).
-cagra_status launch_reduce4(const double *blk, int32_t n, double *out, hipStream_t st) {
-    k_reduce4<<<1, 256, 0, st>>>(blk, n, out);
+cagra_status launch_reduce4(const double *blk, int32_t n, double *out, const double *carry, hipStream_t st) {
+    k_reduce4<<<1, 256, 0, st>>>(blk, n, out, carry);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -716,6 +720,8 @@ size_t ws_blk_bytes(int32_t V, int32_t nb) {
     const int64_t n = nb > init_blocks(V) ? nb : init_blocks(V);
     return align_up((size_t)n * 4 * sizeof(double), 256);
 }
+// One double per merge work item: the absolute buffer mass of a split item.
+size_t ws_item_bytes(const cagra_segments *seg) { return align_up((size_t)seg->max_items * sizeof(double), 256); }
 size_t ws_slot_bytes(const cagra_segments *seg) {
     return (size_t)2 * (size_t)(seg->max_items - seg->nb) * (size_t)seg->B * sizeof(unsigned long long);
 }
@@ -727,7 +733,7 @@ cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const fl
     if (contrib_type == CAGRA_BF16) k_pr_init<true><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
     else k_pr_init<false><<<nblk, 256, 0, st>>>(rank, g->out_degree, g->V, contrib_out, blk);
     CAGRA_LAUNCH_CHECK();
-    k_reduce4<<<1, 256, 0, st>>>(blk, nblk, scalars_out);
+    k_reduce4<<<1, 256, 0, st>>>(blk, nblk, scalars_out, nullptr);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -737,18 +743,16 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
                                       const float *rank_in, const double *scalars_in, const float *partial,
                                       float *rank_out, void *contrib_out, double *scalars_out, void *ws,
                                       hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr<BF16OUT, WIDE>)) return a_;
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_pr_finish<BF16OUT>)) return a_;
-        attr = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_pr<BF16OUT, WIDE>)) return a_;
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_pr_finish<BF16OUT>)) return a_;
     double *blk = reinterpret_cast<double *>(ws);
-    unsigned long long *slots =
-        reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + ws_blk_bytes(seg->V, seg->nb));
+    double *item_abs = reinterpret_cast<double *>(reinterpret_cast<char *>(ws) + ws_blk_bytes(seg->V, seg->nb));
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) +
+                                                                       ws_blk_bytes(seg->V, seg->nb) +
+                                                                       ws_item_bytes(seg));
     k_merge_pr<BF16OUT, WIDE><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
-        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots,
+        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots, item_abs,
         seg->max_items == seg->nb ? 1 : 0);
     CAGRA_LAUNCH_CHECK();
     // max_items is a bound on the item count; when it equals nb (a caller that
@@ -761,10 +765,10 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
         CAGRA_LAUNCH_CHECK();
         k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
             seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
-            contrib_out, blk, slots, seg->max_items);
+            contrib_out, blk, slots, item_abs, seg->max_items);
         CAGRA_LAUNCH_CHECK();
     }
-    k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out);
+    k_reduce4<<<1, 256, 0, st>>>(blk, seg->nb, scalars_out, scalars_in);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -789,11 +793,7 @@ cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in
                              int32_t *labels_out, int32_t *changed_out, void *ws, hipStream_t st) {
     int32_t *blk = reinterpret_cast<int32_t *>(ws);
     const size_t lds = merge_fused_lds_bytes(seg->B, seg->k, 4);
-    static bool attr = false;
-    if (!attr) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_lp)) return a_;
-        attr = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_lp)) return a_;
     k_merge_lp<<<seg->nb, kMergeThreads, lds, st>>>(seg->row_dst_lo, seg->block_ptr, partial, seg->V, seg->k, seg->B,
                                                     seg->nb, labels_in, labels_out, blk);
     CAGRA_LAUNCH_CHECK();

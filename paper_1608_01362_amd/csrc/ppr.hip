@@ -241,11 +241,7 @@ cagra_status launch_ppr_iter(const cagra_graph *g, const cagra_segments *seg, do
                 seg->tile_span_row, contrib_in, seg->N, seg->ntiles, partial);
         CAGRA_LAUNCH_CHECK();
     }
-    static bool attr = false;
-    if (!attr) {
-        if (cagra_status a_ = allow_dynamic_lds((const void *)k_merge_ppr)) return a_;
-        attr = true;
-    }
+    if (cagra_status a_ = ensure_dynamic_lds((const void *)k_merge_ppr)) return a_;
     k_merge_ppr<<<seg->nb, kPprThreads, ppr_merge_lds_bytes(seg->B), st>>>(
         seg->row_dst, seg->block_ptr, partial, seg->V, seg->k, seg->B, seg->nb, ncols, seeds, rank_in, g->out_degree,
         scalars_in, damping, rank_out, contrib_out, blk);

@@ -34,7 +34,7 @@
 
 namespace cagra {
 
-cagra_status launch_reduce4(const double *blk, int32_t n, double *out, hipStream_t st);
+cagra_status launch_reduce4(const double *blk, int32_t n, double *out, const double *carry, hipStream_t st);
 cagra_status launch_reduce_i32(const int32_t *blk, int32_t n, int32_t *out, hipStream_t st);
 
 constexpr int kPushWaves = CAGRA_TILE_WAVES;  // tiles carry one starting row per wave
@@ -500,21 +500,13 @@ static cagra_status launch_scatter(const cagra_segments *seg, const void *vals, 
     const size_t lds = push_scatter_lds_bytes(seg->N, (int)sizeof(typename PO::A));
     const unsigned grid = (unsigned)push_max_pieces(seg);
     if (edge16(seg->N)) {
-        static bool attr = false;
-        if (!attr) {
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_scatter<PO, uint16_t>)) return a_;
-            attr = true;
-        }
+        if (cagra_status a_ = ensure_dynamic_lds((const void *)k_push_scatter<PO, uint16_t>)) return a_;
         k_push_scatter<PO, uint16_t><<<grid, kPushThreads, lds, st>>>(
             static_cast<const uint16_t *>(seg->edge_src), seg->Q, seg->tile_edge, seg->tile_span_row,
             static_cast<const uint32_t *>(vals), seg->V, seg->N, ws.pfirst, seg->k, ws.piece_tile, ws.piece_seg,
             static_cast<typename PO::A *>(ws.slots));
     } else {
-        static bool attr = false;
-        if (!attr) {
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_scatter<PO, uint32_t>)) return a_;
-            attr = true;
-        }
+        if (cagra_status a_ = ensure_dynamic_lds((const void *)k_push_scatter<PO, uint32_t>)) return a_;
         k_push_scatter<PO, uint32_t><<<grid, kPushThreads, lds, st>>>(
             static_cast<const uint32_t *>(seg->edge_src), seg->Q, seg->tile_edge, seg->tile_span_row,
             static_cast<const uint32_t *>(vals), seg->V, seg->N, ws.pfirst, seg->k, ws.piece_tile, ws.piece_seg,
@@ -534,12 +526,8 @@ static cagra_status push_edges(const cagra_segments *seg, const void *x, void *v
     if (seg->Q > 0) {
         const size_t lds = push_expand_lds_bytes(seg->B, seg->k);
         const bool wide = seg->Q < (int64_t)kWave * seg->k * seg->nb;
-        static bool attr = false;
-        if (!attr) {
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_expand<true>)) return a_;
-            if (cagra_status a_ = allow_dynamic_lds((const void *)k_push_expand<false>)) return a_;
-            attr = true;
-        }
+        if (cagra_status a_ = ensure_dynamic_lds((const void *)k_push_expand<true>)) return a_;
+        if (cagra_status a_ = ensure_dynamic_lds((const void *)k_push_expand<false>)) return a_;
         if (wide)
             k_push_expand<true><<<seg->max_items, kMergeThreads, lds, st>>>(
                 seg->row_dst_lo, seg->block_ptr, seg->block_items, static_cast<const uint32_t *>(x), seg->V, seg->k,
@@ -564,7 +552,7 @@ cagra_status launch_pr_push(const cagra_graph *g, const cagra_segments *seg, dou
                                                    seg->V, seg->N, rank_in, g->out_degree, scalars_in, damping,
                                                    rank_out, contrib_out, static_cast<double *>(ws.blk));
     CAGRA_LAUNCH_CHECK();
-    return launch_reduce4(static_cast<const double *>(ws.blk), nblk, scalars_out, st);
+    return launch_reduce4(static_cast<const double *>(ws.blk), nblk, scalars_out, scalars_in, st);
 }
 
 cagra_status launch_lp_push(const cagra_segments *seg, const int32_t *labels_in, int32_t *vals, int32_t *labels_out,

@@ -98,7 +98,7 @@ class Network:
 def pagerank_target(dg, seg, tol=1e-8, max_iters=100):
     """log(V * r*) with r* the method's own FP32 PageRank at residual < tol."""
     import torch
-    r, _, _ = cagra.pagerank(dg, seg, iters=max_iters, tol=tol, check_every=4)
+    r, _, _ = cagra.pagerank(dg, seg, iters=max_iters, tol=tol, check_every=4, allow_not_converged=True)
     return torch.log(r.clamp_min(1e-30) * dg.V)
 
 
@@ -157,13 +157,6 @@ def solve(dg, seg, tol=1e-6, max_iters=100, net: Network | None = None):
         else:
             rank0 = None
             used = "uniform (fallback)"
-    st = cagra.PageRankState(dg, seg)
-    st.start(rank0)
-    it = 0
-    while it < max_iters:
-        st.step()
-        it += 1
-        if float(st.scalars_now[1].item()) < tol:
-            break
+    res = cagra.pagerank_solve(dg, seg, tol=tol, max_iters=max_iters, rank0=rank0)
     torch.cuda.synchronize()
-    return st.rank_now.clone(), it, (time.perf_counter() - t0) * 1e3, used
+    return res.rank.clone(), res.iters, (time.perf_counter() - t0) * 1e3, used

@@ -36,13 +36,15 @@ def test_exports_match_header(cagra):
     L = cagra.lib()
     for name in decl:
         assert hasattr(L, name)
-    assert L.cagra_abi_version() == 1
+    assert L.cagra_abi_version() == cagra.ABI_VERSION == 2
 
 
 def test_status_strings(cagra):
     L = cagra.lib()
     assert L.cagra_status_string(0) == b"CAGRA_OK"
     assert L.cagra_status_string(-4) == b"CAGRA_E_BUFFER"
+    assert L.cagra_status_string(-6) == b"CAGRA_E_NOT_CONVERGED"
+    assert L.cagra_status_string(-7) == b"CAGRA_E_RANGE"
     assert L.cagra_status_string(99) == b"CAGRA_E_UNKNOWN"
 
 
@@ -225,3 +227,39 @@ def test_validate_graph_arguments(cagra):
     assert L.cagra_validate_graph(ctypes.byref(_graph(cagra, src=None)), 1, n, None) == -1
     assert L.cagra_validate_graph(ctypes.byref(_graph(cagra)), None, n, None) == -4
     assert L.cagra_validate_graph(ctypes.byref(_graph(cagra)), 1, n - 1, None) == -4
+
+
+def test_pagerank_solve_validation(cagra):
+    """cagra_pagerank_solve rejects bad arguments before any HIP call."""
+    L = cagra.lib()
+    s = _fake_built(cagra)
+    g = _graph(cagra, V=100, E=50)
+    ws = L.cagra_iter_workspace_bytes(ctypes.byref(s))
+    res = cagra.CPrResult()
+
+    def call(p, r0=1, r1=2, c0=3, c1=4, sc=5, part=6, wsp=7, wsb=ws, result=res):
+        return L.cagra_pagerank_solve(ctypes.byref(g), ctypes.byref(s), None if p is None else ctypes.byref(p),
+                                      r0, r1, c0, c1, sc, part, wsp, wsb,
+                                      None if result is None else ctypes.byref(result), None)
+
+    ok = dict(damping=0.85, tol=1e-6, switch_tol=0.0, max_iters=100, check_every=1, contrib_type=cagra.F32)
+
+    def P(**kw):
+        d = dict(ok, **kw)
+        return cagra.CPrParams(d["damping"], d["tol"], d["switch_tol"], d["max_iters"], d["check_every"],
+                               d["contrib_type"])
+    assert call(None) == cagra.E_INVALID
+    assert call(P(), result=None) == cagra.E_INVALID
+    assert call(P(tol=0.0)) == cagra.E_INVALID
+    assert call(P(tol=float("nan"))) == cagra.E_INVALID
+    assert call(P(max_iters=0)) == cagra.E_INVALID
+    assert call(P(check_every=0)) == cagra.E_INVALID
+    assert call(P(switch_tol=1e-4)) == cagra.E_INVALID          # finishing switch needs BF16 contributions
+    assert call(P(switch_tol=-1.0, contrib_type=cagra.BF16)) == cagra.E_INVALID
+    assert call(P(damping=2.0)) == cagra.E_INVALID
+    assert call(P(contrib_type=7)) == cagra.E_INVALID
+    assert call(P(), r1=1) == cagra.E_INVALID                   # rank pair aliased
+    assert call(P(), c1=3) == cagra.E_INVALID                   # contribution pair aliased
+    assert call(P(), sc=None) == cagra.E_INVALID
+    assert call(P(), wsb=ws - 1) == cagra.E_BUFFER
+    assert L.cagra_last_error()

@@ -1,0 +1,147 @@
+"""Boundary behaviour on the GPU, through the C ABI: the range count of the
+exact fixed-point merge, the host-driven solve loop (convergence, the
+iteration cap, the BF16-to-FP32 finishing switch) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+@pytest.fixture(scope="module")
+def cagra():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1608_01362_amd import cagra as c
+    c.lib()
+    return c
+
+
+@pytest.fixture(scope="module")
+def small(cagra):
+    g = graphgen.rmat_graph(12, 16, 7)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 1024, 512, 4096)
+    return g, dg, seg
+
+
+@pytest.fixture(scope="module")
+def cfg1(cagra):
+    g = graphgen.rmat_graph(16, 16, 1)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 16384, 16384, 65536)
+    return g, dg, seg
+
+
+def test_nan_start_is_counted_and_raised(cagra, small):
+    import torch
+    g, dg, seg = small
+    hub = int(np.argmax(g.out_degree))
+    r0 = torch.full((g.V,), 1.0 / g.V, dtype=torch.float32, device="cuda")
+    r0[hub] = float("nan")
+    st = cagra.PageRankState(dg, seg)
+    st.start(r0)
+    assert float(st.scalars_now[3].item()) == 1.0  # one non-finite start value
+    st.step()
+    sc = st.scalars_now.cpu().numpy()
+    print(f"after one step: range count {sc[3]:g}")
+    assert sc[3] >= 2.0  # the start's count carried, plus the blocks the NaN reached
+    with pytest.raises(cagra.CagraError) as e:
+        cagra.pagerank(dg, seg, iters=3, rank0=r0)
+    assert e.value.status == cagra.E_RANGE
+    with pytest.raises(cagra.CagraError) as e:
+        cagra.pagerank_solve(dg, seg, tol=1e-6, rank0=r0)
+    assert e.value.status == cagra.E_RANGE
+
+
+def test_nan_buffer_value_counted_by_the_merge(cagra, small):
+    """A NaN contribution alone (start scalars clean) is caught by the merge."""
+    import torch
+    g, dg, seg = small
+    st = cagra.PageRankState(dg, seg)
+    st.start()
+    hub = int(np.argmax(g.out_degree))
+    st.contrib[0][hub] = float("nan")
+    st.scalars[0][3] = 0.0
+    st.step()
+    c = float(st.scalars_now[3].item())
+    print(f"range count with one NaN contribution: {c:g}")
+    assert c >= 1.0
+    # every block that received the hub's value is counted, and nothing else:
+    # the count equals the number of merge blocks holding an out-neighbour of the hub
+    outs = [v for v in range(g.V) if hub in g.in_sources[g.in_offsets[v]:g.in_offsets[v + 1]]]
+    assert c == len({v // seg.c.B for v in outs})
+    st.start()
+    st.step()
+    assert float(st.scalars_now[3].item()) == 0.0
+    torch.cuda.synchronize()
+
+
+def test_unnormalized_start_raises(cagra, small):
+    """A start vector of mass V (every rank 1) puts more absolute mass into a
+    merge block than the exact fixed-point sums can hold."""
+    import torch
+    g, dg, seg = small
+    ones = torch.ones(g.V, dtype=torch.float32, device="cuda")
+    with pytest.raises(cagra.CagraError) as e:
+        cagra.pagerank(dg, seg, iters=2, rank0=ones)
+    assert e.value.status == cagra.E_RANGE
+    # the normalized vector of the same shape is fine
+    r, _, _ = cagra.pagerank(dg, seg, iters=2, rank0=ones / g.V)
+    assert np.isfinite(r.cpu().numpy()).all()
+
+
+def test_solve_matches_the_iteration_and_the_oracle(cagra, cfg1):
+    g, dg, seg = cfg1
+    res = cagra.pagerank_solve(dg, seg, tol=1e-6, max_iters=100)
+    assert res.converged and res.residual < 1e-6 and res.iters_bf16 == 0
+    # the same kernels as the step-by-step iteration: bit-identical
+    st = cagra.PageRankState(dg, seg)
+    st.start()
+    for _ in range(res.iters):
+        st.step()
+    assert np.array_equal(st.rank_now.cpu().numpy(), res.rank.cpu().numpy())
+    ref, resid = oracle.pagerank(g, iters=100, tol=1e-6)
+    star, _ = oracle.pagerank(g, iters=400, tol=1e-14)
+    print(f"solve: {res.iters} iterations (oracle {len(resid)}), residual {res.residual:.3e}")
+    assert abs(res.iters - len(resid)) <= 1
+    assert np.abs(res.rank.double().cpu().numpy() - star).sum() <= D / (1 - D) * 1e-6 + 1e-6
+    # checking every 4th step stops at the first multiple of 4 at or after it
+    r4 = cagra.pagerank_solve(dg, seg, tol=1e-6, max_iters=100, check_every=4)
+    assert r4.converged and r4.iters == -(-res.iters // 4) * 4
+
+
+def test_iteration_cap_reports_not_converged(cagra, cfg1):
+    g, dg, seg = cfg1
+    r = cagra.pagerank_solve(dg, seg, tol=1e-6, max_iters=3)
+    assert not r.converged and r.iters == 3 and r.residual >= 1e-6
+    with pytest.raises(cagra.NotConverged) as e:
+        cagra.pagerank(dg, seg, iters=3, tol=1e-6)
+    assert e.value.status == cagra.E_NOT_CONVERGED
+    rank, resid, steps = e.value.result
+    assert steps == 3 and resid[0] == r.residual
+    ref, _ = oracle.pagerank(g, iters=3)
+    assert np.abs(rank.double().cpu().numpy() - ref).sum() <= 1e-6
+    rank2, _, steps2 = cagra.pagerank(dg, seg, iters=3, tol=1e-6, allow_not_converged=True)
+    assert steps2 == 3 and np.array_equal(rank.cpu().numpy(), rank2.cpu().numpy())
+
+
+def test_bf16_finishing_switch_reaches_the_fixed_point(cagra, cfg1):
+    """BF16 gathers alone converge to their own fixed point, about d*2^-9/(1-d)
+    away at worst; finishing in FP32 after the switch lands within the
+    contraction bound of the oracle's fixed point, as the FP32 run does."""
+    g, dg, seg = cfg1
+    star, _ = oracle.pagerank(g, iters=400, tol=1e-14)
+    plain = cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=cagra.BF16)
+    fin = cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=cagra.BF16, switch_tol=1e-4)
+    l1p = np.abs(plain.rank.double().cpu().numpy() - star).sum()
+    l1f = np.abs(fin.rank.double().cpu().numpy() - star).sum()
+    print(f"bf16 only: {plain.iters} iterations, L1 {l1p:.3e}; bf16 then fp32: {fin.iters} "
+          f"({fin.iters_bf16} bf16), L1 {l1f:.3e}")
+    assert plain.converged and fin.converged
+    assert 0 < fin.iters_bf16 < fin.iters
+    assert l1f <= D / (1 - D) * 1e-6 + 1e-6
+    assert l1p <= D * 2.0 ** -9 / (1 - D)
