@@ -16,6 +16,7 @@ cagra_status launch_gather(const cagra_segments *seg, int32_t op, int32_t value_
                            void *partial, hipStream_t st);
 cagra_status launch_merge(const cagra_segments *seg, int32_t op, const void *partial, void *out, hipStream_t st);
 cagra_status launch_merge_sum_fixed24(const cagra_segments *seg, const float *partial, float *out, hipStream_t st);
+cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st);
 
 constexpr int kH = 64;
 constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4480;
@@ -105,10 +106,17 @@ __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bi
 // hi = bf16(h) and lo = bf16(h - hi) (|h - hi - lo| <= 2^-18 |h|), and both
 // halves are accumulated: the hidden product keeps FP32-level accuracy for
 // twice the (cheap) matrix instructions.
+// With `rows`, the i-th row processed is rows[i] (features read and output
+// written at that row) and the count is n_dev[0] when n_dev is given. Each
+// row's arithmetic does not depend on the other rows of its tile, so a row's
+// output is the same bits whichever rows share its tile.
 __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__restrict__ feats, int64_t n,
                                                              const uint16_t *__restrict__ wb,
                                                              const float *__restrict__ norm,
-                                                             float *__restrict__ y) {
+                                                             float *__restrict__ y,
+                                                             const int32_t *__restrict__ rows,
+                                                             const int32_t *__restrict__ n_dev) {
+    if (n_dev) n = n_dev[0];
     const int lane = threadIdx.x & 63, kq = lane >> 4, jl = lane & 15;
     // first-layer weights of this lane's 16 units, second-layer operands, output weights
     float w1[16][3], b1[16];
@@ -140,8 +148,9 @@ __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__rest
     const int64_t wave = ((int64_t)blockIdx.x * kFwdThreads + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kFwdThreads) >> 6;
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
-        const int64_t r = tile * 16 + jl;
-        const bool live = r < n;
+        const int64_t i = tile * 16 + jl;
+        const bool live = i < n;
+        const int64_t r = live && rows ? (int64_t)rows[i] : i;
         const float x0 = live ? (feats[r * 3 + 0] - m0) * s0 : 0.0f;
         const float x1 = live ? (feats[r * 3 + 1] - m1) * s1 : 0.0f;
         const float x2 = live ? (feats[r * 3 + 2] - m2) * s2 : 0.0f;
@@ -175,8 +184,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__rest
         if (jl == 0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t ro = tile * 16 + 4 * kq + q;
-                if (ro < n) y[ro] = part[q] + b3;
+                const int64_t io = tile * 16 + 4 * kq + q;
+                if (io < n) y[rows ? (int64_t)rows[io] : io] = part[q] + b3;
             }
         }
     }
@@ -329,12 +338,15 @@ static size_t bwd_lds_bytes() {
     return (size_t)(((kNParam + 3 + 3) & ~3) + kBwdRows * 4 + kBwdRows + 4 * kBwdRows * kPad) * sizeof(float);
 }
 
+static unsigned forward_grid(int64_t n) {
+    int64_t g = ceil_div(ceil_div(n, 16), kFwdThreads / 64);
+    return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
 cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *wb, const float *norm, float *y,
                                 hipStream_t st) {
     if (n == 0) return CAGRA_OK;
-    int64_t g = ceil_div(ceil_div(n, 16), kFwdThreads / 64);
-    if (g > 4096) g = 4096;
-    k_mlp_forward<<<(unsigned)g, kFwdThreads, 0, st>>>(feats, n, wb, norm, y);
+    k_mlp_forward<<<forward_grid(n), kFwdThreads, 0, st>>>(feats, n, wb, norm, y, nullptr, nullptr);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -447,6 +459,211 @@ __global__ void k_soft_write(const float *__restrict__ y, int32_t V, const doubl
 }
 
 size_t softmax_ws_bytes(int32_t V) { return (size_t)ceil_div(V, kSoftSpan) * 2 * sizeof(double) + 256; }
+
+// ------------------------------------------------------------------ training inputs
+
+// Regression target of one vertex: log(V * r) (the network predicts log-ranks
+// relative to the uniform 1/V; ranks below 1e-30 are clamped there).
+__global__ void k_targets(const float *__restrict__ rank, int32_t V, float *__restrict__ t) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V) t[v] = (float)log((double)V * fmax((double)rank[v], 1e-30));
+}
+
+cagra_status launch_targets(const float *rank, int32_t V, float *t, hipStream_t st) {
+    k_targets<<<(unsigned)ceil_div(V, 256), 256, 0, st>>>(rank, V, t);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// Feature standardization: per column the mean and the sample standard
+// deviation (n - 1 denominator), FP64, two passes, fixed order: per-block
+// partial sums of kNormSpan rows, then one workgroup adds them in block order.
+constexpr int kNormSpan = 65536;
+int32_t norm_blocks(int64_t n) { return (int32_t)ceil_div(n, kNormSpan); }
+size_t norm_ws_bytes(int64_t n) { return align_up((size_t)norm_blocks(n) * 3 * sizeof(double), 256) + 256; }
+
+__global__ __launch_bounds__(256) void k_norm_pass(const float *__restrict__ f, int64_t n,
+                                                   const double *__restrict__ mean, double *__restrict__ blk) {
+    __shared__ double red[4 * 4];
+    const int64_t lo = (int64_t)blockIdx.x * kNormSpan, hi = lo + kNormSpan < n ? lo + kNormSpan : n;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const double m0 = mean ? mean[0] : 0.0, m1 = mean ? mean[1] : 0.0, m2 = mean ? mean[2] : 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += 256) {
+        const double x0 = (double)f[r * 3 + 0] - m0, x1 = (double)f[r * 3 + 1] - m1, x2 = (double)f[r * 3 + 2] - m2;
+        a[0] += mean ? x0 * x0 : x0;
+        a[1] += mean ? x1 * x1 : x1;
+        a[2] += mean ? x2 * x2 : x2;
+    }
+    block_sum4_f64<256>(a, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) blk[(int64_t)blockIdx.x * 3 + c] = a[c];
+}
+
+// Adds the block partials in block order (one thread per column); pass 0
+// writes the means into norm[0..2] and keeps them as FP64 in mean64, pass 1
+// writes 1 / max(std, 1e-6) into norm[3..5].
+__global__ void k_norm_final(const double *__restrict__ blk, int32_t nblk, int64_t n, int pass,
+                             double *__restrict__ mean64, float *__restrict__ norm) {
+    const int c = threadIdx.x;
+    if (c >= 3) return;
+    double s = 0.0;
+    for (int32_t b = 0; b < nblk; ++b) s += blk[(int64_t)b * 3 + c];
+    if (pass == 0) {
+        mean64[c] = s / (double)n;
+        norm[c] = (float)(s / (double)n);
+    } else {
+        const double sd = n > 1 ? sqrt(s / (double)(n - 1)) : 0.0;
+        norm[3 + c] = (float)(1.0 / fmax(sd, 1e-6));
+    }
+}
+
+cagra_status launch_feature_norm(const float *f, int64_t n, float *norm, void *ws, hipStream_t st) {
+    const int32_t nblk = norm_blocks(n);
+    double *blk = (double *)ws;
+    double *mean64 = (double *)((char *)ws + align_up((size_t)nblk * 3 * sizeof(double), 256));
+    k_norm_pass<<<nblk, 256, 0, st>>>(f, n, nullptr, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_norm_final<<<1, 64, 0, st>>>(blk, nblk, n, 0, mean64, norm);
+    CAGRA_LAUNCH_CHECK();
+    k_norm_pass<<<nblk, 256, 0, st>>>(f, n, mean64, blk);
+    CAGRA_LAUNCH_CHECK();
+    k_norm_final<<<1, 64, 0, st>>>(blk, nblk, n, 1, mean64, norm);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// SplitMix64 finalizer (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Minibatch draw: row i of draw d is row floor(h * n / 2^64) of the data, with
+// h the SplitMix64 output for counter d * batch + i under `seed` (Lemire's
+// multiply-shift range reduction; bias below n / 2^64).
+__global__ void k_sample_rows(const float *__restrict__ f, const float *__restrict__ t, int64_t n, uint64_t seed,
+                              int64_t draw, int32_t batch, float *__restrict__ fo, float *__restrict__ to) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch) return;
+    const uint64_t ctr = (uint64_t)draw * (uint64_t)batch + (uint64_t)i;
+    const uint64_t h = splitmix64_mix(seed + (ctr + 1) * 0x9e3779b97f4a7c15ull);
+    const int64_t r = (int64_t)__umul64hi(h, (uint64_t)n);
+    fo[i * 3 + 0] = f[r * 3 + 0];
+    fo[i * 3 + 1] = f[r * 3 + 1];
+    fo[i * 3 + 2] = f[r * 3 + 2];
+    to[i] = t[r];
+}
+
+cagra_status launch_sample_rows(const float *f, const float *t, int64_t n, uint64_t seed, int64_t draw, int32_t batch,
+                                float *fo, float *to, hipStream_t st) {
+    k_sample_rows<<<(unsigned)ceil_div(batch, 256), 256, 0, st>>>(f, t, n, seed, draw, batch, fo, to);
+    CAGRA_LAUNCH_CHECK();
+    return CAGRA_OK;
+}
+
+// ------------------------------------------------------------------ learned start, fused
+
+// A vertex without in-edges has features (0, log(1 + out-degree), 0): its
+// network output depends on its out-degree alone. The fused start evaluates
+// the network once per out-degree below kMemoDeg on exactly those features
+// (the bits the feature kernel writes for such a vertex) and copies that
+// output to every such vertex; all other rows go through the network
+// individually. Since a row's output does not depend on the rows evaluated
+// beside it, the result is bit-identical to evaluating every row.
+constexpr int32_t kMemoDeg = 1024;
+
+__global__ void k_memo_feats(float *__restrict__ f) {
+    const int32_t od = blockIdx.x * blockDim.x + threadIdx.x;
+    if (od >= kMemoDeg) return;
+    f[od * 3 + 0] = log1pf((float)0);
+    f[od * 3 + 1] = log1pf((float)od);
+    f[od * 3 + 2] = 0.0f;
+}
+
+// y[v] from the memo for vertices without in-edges and out-degree below
+// kMemoDeg; every other vertex is appended to rows (one atomic per wave).
+__global__ __launch_bounds__(256) void k_memo_split(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ outdeg, int32_t V,
+                                                    const float *__restrict__ ymemo, float *__restrict__ y,
+                                                    int32_t *__restrict__ rows, int32_t *__restrict__ count) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool net = false;
+    if (v < V) {
+        const int32_t od = outdeg[v];
+        if (off[v + 1] == off[v] && od < kMemoDeg) y[v] = ymemo[od];
+        else net = true;
+    }
+    const uint64_t m = __ballot(net);
+    int32_t base = 0;
+    if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(count, (int32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (net) rows[base + (int32_t)__popcll(m & lanemask_lt())] = (int32_t)v;
+}
+
+__global__ void k_zero_i32(int32_t *__restrict__ p, int32_t n) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+struct StartWs {
+    float *feats, *y, *memo_f, *memo_y;
+    int32_t *rows, *count;
+    void *feat_ws, *soft_ws;
+};
+
+static size_t start_layout(const cagra_segments *seg, char *base, StartWs *w) {
+    const int64_t V = seg->V;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return base ? base + at : nullptr;
+    };
+    char *p;
+    p = take((size_t)V * 3 * 4);
+    if (w) w->feats = (float *)p;
+    p = take((size_t)V * 4);
+    if (w) w->y = (float *)p;
+    p = take((size_t)kMemoDeg * 3 * 4);
+    if (w) w->memo_f = (float *)p;
+    p = take((size_t)kMemoDeg * 4);
+    if (w) w->memo_y = (float *)p;
+    p = take((size_t)V * 4);
+    if (w) w->rows = (int32_t *)p;
+    p = take(256);
+    if (w) w->count = (int32_t *)p;
+    p = take(features_ws_bytes(seg));
+    if (w) w->feat_ws = p;
+    p = take(softmax_ws_bytes(seg->V));
+    if (w) w->soft_ws = p;
+    return o + 256;
+}
+
+size_t learned_start_ws_bytes(const cagra_segments *seg) { return start_layout(seg, nullptr, nullptr); }
+
+cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *seg, const uint16_t *wb,
+                                  const float *norm, float *rank0, double *scal, void *ws, hipStream_t st) {
+    StartWs w;
+    start_layout(seg, (char *)ws, &w);
+    const int32_t V = g->V;
+    cagra_status s;
+    if ((s = launch_features(g, seg, w.feats, w.feat_ws, st)) != CAGRA_OK) return s;
+    k_memo_feats<<<(unsigned)ceil_div(kMemoDeg, 256), 256, 0, st>>>(w.memo_f);
+    CAGRA_LAUNCH_CHECK();
+    k_mlp_forward<<<forward_grid(kMemoDeg), kFwdThreads, 0, st>>>(w.memo_f, kMemoDeg, wb, norm, w.memo_y, nullptr,
+                                                                 nullptr);
+    CAGRA_LAUNCH_CHECK();
+    k_zero_i32<<<1, 64, 0, st>>>(w.count, 1);
+    CAGRA_LAUNCH_CHECK();
+    k_memo_split<<<(unsigned)ceil_div(V, 256), 256, 0, st>>>(g->in_offsets, g->out_degree, V, w.memo_y, w.y, w.rows,
+                                                            w.count);
+    CAGRA_LAUNCH_CHECK();
+    k_mlp_forward<<<forward_grid(V), kFwdThreads, 0, st>>>(w.feats, V, wb, norm, w.y, w.rows, w.count);
+    CAGRA_LAUNCH_CHECK();
+    if ((s = launch_softmax(w.y, V, rank0, scal, w.soft_ws, st)) != CAGRA_OK) return s;
+    return CAGRA_OK;
+}
 
 cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st) {
     const int32_t nblk = (int32_t)ceil_div(V, kSoftSpan);

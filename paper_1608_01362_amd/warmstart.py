@@ -58,7 +58,11 @@ class Network:
     losses: list = field(default_factory=list)
 
     @staticmethod
-    def create(seed: int, mean, std):
+    def create(seed: int, mean=None, std=None, norm=None):
+        """Parameters from init_params(seed) (FP32 master, BF16 copy by round to
+        nearest even in the library's Adam kernel convention), zero Adam state,
+        and the feature standardization: either `norm` (device float32 [6], as
+        cagra_feature_norm writes it) or host `mean`/`std` arrays."""
         import torch
         p = torch.from_numpy(init_params(seed)).cuda()
         net = Network()
@@ -66,8 +70,10 @@ class Network:
         net.weights = p.to(torch.bfloat16).view(torch.int16).contiguous()
         net.m = torch.zeros_like(p)
         net.v = torch.zeros_like(p)
-        norm = np.concatenate([np.asarray(mean, np.float32), 1.0 / np.asarray(std, np.float32)]).astype(np.float32)
-        net.norm = torch.from_numpy(norm).cuda()
+        if norm is None:
+            norm = torch.from_numpy(np.concatenate([np.asarray(mean, np.float32),
+                                                    1.0 / np.asarray(std, np.float32)]).astype(np.float32)).cuda()
+        net.norm = norm
         return net
 
     def forward(self, F):
@@ -96,26 +102,46 @@ class Network:
 
 
 def pagerank_target(dg, seg, tol=1e-8, max_iters=100):
-    """log(V * r*) with r* the method's own FP32 PageRank at residual < tol."""
+    """log(V * r*) (cagra_mlp_targets) with r* the method's own FP32 PageRank at
+    residual < tol (or after max_iters iterations)."""
     import torch
     r, _, _ = cagra.pagerank(dg, seg, iters=max_iters, tol=tol, check_every=4, allow_not_converged=True)
-    return torch.log(r.clamp_min(1e-30) * dg.V)
+    t = torch.empty(dg.V, dtype=torch.float32, device="cuda")
+    cagra._check(cagra.lib().cagra_mlp_targets(_p(r), dg.V, _p(t), cagra._stream()), "cagra_mlp_targets")
+    return t
+
+
+def feature_norm(F):
+    """Device float32 [6]: column means and 1/std of F [n, 3] (cagra_feature_norm)."""
+    import torch
+    L = cagra.lib()
+    n = F.shape[0]
+    norm = torch.empty(6, dtype=torch.float32, device="cuda")
+    nws = L.cagra_feature_norm_workspace_bytes(n)
+    ws = torch.empty(nws, dtype=torch.uint8, device="cuda")
+    cagra._check(L.cagra_feature_norm(_p(F), n, _p(norm), _p(ws), nws, cagra._stream()), "cagra_feature_norm")
+    return norm
+
+
+def sample_rows(F, T, seed: int, draw: int, batch: int, out=None):
+    """Minibatch `draw` of `batch` rows (cagra_sample_rows); returns (Fb, Tb)."""
+    import torch
+    if out is None:
+        out = (torch.empty(batch, 3, dtype=torch.float32, device="cuda"),
+               torch.empty(batch, dtype=torch.float32, device="cuda"))
+    Fb, Tb = out
+    cagra._check(cagra.lib().cagra_sample_rows(_p(F), _p(T), F.shape[0], seed & (2 ** 64 - 1), draw, batch, _p(Fb),
+                                               _p(Tb), cagra._stream()), "cagra_sample_rows")
+    return Fb, Tb
 
 
 def train(F, T, seed: int = 0, steps: int = 400, batch: int = 65536, lr: float = 3e-3, log=None):
     """Minibatch Adam on rows (F [n,3], T [n]) held on the GPU; deterministic row sampling."""
-    import torch
-    Fh = F.double()
-    mean = Fh.mean(dim=0).cpu().numpy()
-    std = Fh.std(dim=0).clamp_min(1e-6).cpu().numpy()
-    net = Network.create(seed, mean, std)
+    net = Network.create(seed, norm=feature_norm(F))
     n = F.shape[0]
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
+    bufs = None
     for s in range(steps):
-        idx = torch.randint(0, n, (min(batch, n),), device="cuda", generator=gen)
-        Fb = F.index_select(0, idx).contiguous()
-        Tb = T.index_select(0, idx).contiguous()
+        Fb, Tb = bufs = sample_rows(F, T, seed, s, min(batch, n), bufs)
         g, loss = net.grad(Fb, Tb)
         net.adam(g, lr=lr)
         if log and (s % 100 == 0 or s == steps - 1):
@@ -142,21 +168,40 @@ def start_vector(net: Network, F):
     return r0, bool(usable)
 
 
-def solve(dg, seg, tol=1e-6, max_iters=100, net: Network | None = None):
+def learned_start(net: Network, dg, seg, ws=None):
+    """(rank0, usable): the start vector in one library call (cagra_learned_start:
+    features, the network, softmax), bit-identical to start_vector(net,
+    features(dg, seg))."""
+    import torch
+    L = cagra.lib()
+    r0 = torch.empty(dg.V, dtype=torch.float32, device="cuda")
+    sc = torch.zeros(4, dtype=torch.float64, device="cuda")
+    n = L.cagra_learned_start_workspace_bytes(ctypes.byref(seg.c))
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    cagra._check(L.cagra_learned_start(ctypes.byref(dg.c), ctypes.byref(seg.c), _p(net.weights), _p(net.norm),
+                                       _p(r0), _p(sc), _p(ws), n, cagra._stream()), "cagra_learned_start")
+    s = sc.cpu().numpy()
+    usable = s[1] == 0 and np.isfinite(s[2]) and s[2] > 0
+    return r0, bool(usable)
+
+
+def solve(dg, seg, tol=1e-6, max_iters=100, net: Network | None = None, ws=None, buffers=None):
     """PageRank to residual < tol from the uniform start (net None) or the learned one.
-    Returns (rank, iterations, ms including features and network time, start used)."""
+    Returns (rank, iterations, ms including features and network time, start used).
+    ws / buffers: optional preallocated start workspace and solve buffers (so
+    that the timing covers no allocation)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rank0, used = None, "uniform"
     if net is not None:
-        F = features(dg, seg)
-        rank0, ok = start_vector(net, F)
+        rank0, ok = learned_start(net, dg, seg, ws)
         if ok:
             used = "learned"
         else:
             rank0 = None
             used = "uniform (fallback)"
-    res = cagra.pagerank_solve(dg, seg, tol=tol, max_iters=max_iters, rank0=rank0)
+    res = cagra.pagerank_solve(dg, seg, tol=tol, max_iters=max_iters, rank0=rank0, state=buffers)
     torch.cuda.synchronize()
     return res.rank.clone(), res.iters, (time.perf_counter() - t0) * 1e3, used
