@@ -38,13 +38,26 @@ def log(msg):
 
 
 def byte_model(V, E, Q, k, nb, wc, we=4):
-    """Algorithmic HBM bytes per iteration (what the method must move).
+    """HBM bytes per iteration that this layout moves.
     gather: edge words (we*E; we = 2 for 16-bit words, N <= 32768) + each segment's values
             staged once (wc*V) + buffer writes (4Q)
     merge:  buffer reads (4Q) + destination offsets in the block (2Q, uint16) + block index (4k(nb+1))
             + rank_in, out_degree, rank_out (12V) + contrib_out (wc*V)"""
     gather = we * E + wc * V + 4 * Q
     merge = 6 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
+    return gather, merge
+
+
+def csr_byte_model(V, E, Q, k, nb, wc, we=4):
+    """Algorithmic HBM bytes per iteration of the method's own data structures
+    (Sections 3.1-3.3: each subgraph a CSR with a row pointer and a 4-byte
+    destination per row, idxMap, block index), whatever the layout:
+    gather: sources (we*E) + row pointers (4(Q+1)) + segments staged once (wc*V) + buffers (4Q)
+    merge:  buffers (4Q) + destinations (4Q) + block index (4k(nb+1))
+            + rank_in, out_degree, rank_out (12V) + contrib_out (wc*V)
+    Total E*we + 16Q + 4k(nb+1) + V(12 + 2wc) (+4 for the last row pointer)."""
+    gather = we * E + 4 * (Q + 1) + wc * V + 4 * Q
+    merge = 8 * Q + 4 * k * (nb + 1) + 12 * V + wc * V
     return gather, merge
 
 
@@ -170,6 +183,60 @@ def cpu_baseline(g, budget_s=12.0):
             "cpu_model": model, "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
+def bf16_leg(cagra, dg, seg, args, conv, conv_rank, oref, log):
+    """BF16 contributions (FP32 accumulation, exact merge, FP64 reductions) on
+    the headline graph and layout, against the FP32 form: per-iteration time,
+    L1 and largest relative error against the FP64 oracle after 20 iterations,
+    and time to an L1 residual below 1e-6 with BF16 throughout and with the
+    switch to FP32 contributions once the residual is below 1e-4, each with its
+    L1 to the oracle's fixed point."""
+    import numpy as np
+    import torch
+
+    def errs(r, ref):
+        x = r.double().cpu().numpy()
+        return {"l1": float(np.abs(x - ref).sum()), "max_rel": float((np.abs(x - ref) / ref).max())}
+
+    def run20(ct):
+        st = cagra.PageRankState(dg, seg, ct)
+        st.start()
+        for _ in range(20):
+            st.step()
+        return st.rank_now.clone()
+
+    stb = cagra.PageRankState(dg, seg, cagra.BF16)
+    stb.start()
+    for _ in range(args.warmup):
+        stb.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        stb.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / args.steps
+    del stb
+    out = {"ms_per_step": round(ms_b, 4), "GTEPS": round(dg.E / (ms_b * 1e-3) / 1e9, 3),
+           "after_20": {"bf16": errs(run20(cagra.BF16), oref["r20"]), "f32": errs(run20(cagra.F32), oref["r20"])},
+           "oracle_iterations_to_fixed_point": oref["iterations_to_fixed_point"]}
+    to = {"f32": dict(conv, **errs(conv_rank, oref["star"]))}
+    for name, sw in (("bf16", 0.0), ("bf16_then_f32", 1e-4)):
+        buf = cagra.SolveBuffers(dg, seg, cagra.BF16, sw)
+        cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=cagra.BF16, switch_tol=sw, state=buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=cagra.BF16, switch_tol=sw, state=buf)
+        ms = (time.perf_counter() - t0) * 1e3
+        to[name] = {"iterations": r.iters, "iterations_bf16": r.iters_bf16, "ms": round(ms, 3),
+                    "final_residual": r.residual, **errs(r.rank, oref["star"])}
+        del buf
+    out["time_to_l1_1e-6"] = to
+    log(f"bf16: {ms_b:.3f} ms/step; to 1e-6: " +
+        ", ".join(f"{k} {v['iterations']} it {v['ms']:.1f} ms L1 {v['l1']:.2e}" for k, v in to.items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +259,8 @@ def main():
                     help="skip the measurement of the plain (unsegmented, one-segment) pull on the same graph")
     ap.add_argument("--no-clustered-line", action="store_true",
                     help="skip the extra measurement of the same graph after clustering")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the BF16, batching (64-seed PPR, 256 graphs) and warm-start legs of the line")
     ap.add_argument("--workload", default="pagerank",
                     choices=["pagerank", "labelprop", "ppr", "multigraph", "warmstart", "cluster", "cf", "bc", "push",
                              "nsweep"],
@@ -299,33 +368,43 @@ def main():
     V, E, Q, k, nb = g.V, g.E, seg.Q, seg.k, seg.c.nb
     we = 2 if args.N <= cagra.EDGE16_MAX_N else 4
     gb, mb = byte_model(V, E, Q, k, nb, wc, we)
-    wide_model = E * we + 16 * Q + 4 * k * (nb + 1) + V * (12 + 2 * wc)
+    cgb, cmb = csr_byte_model(V, E, Q, k, nb, wc, we)
     g_avg, m_avg = sum(gather_ms) / K, sum(merge_ms) / K
     if g_avg >= m_avg:
-        dom, dbytes, dms = "k_gather", gb, g_avg
+        dom, dbytes, cbytes, dms = "k_gather", gb, cgb, g_avg
     else:
-        dom, dbytes, dms = "k_merge_pr", mb, m_avg
-    achieved = dbytes / (dms * 1e-3) / 1e9
+        dom, dbytes, cbytes, dms = "k_merge_pr", mb, cmb, m_avg
+    achieved = cbytes / (dms * 1e-3) / 1e9
+    achieved_moved = dbytes / (dms * 1e-3) / 1e9
     gteps = E / (ms_per_step * 1e-3) / 1e9
     workload = f"pagerank_rmat{args.scale}_ef{args.edge_factor}_seed{args.seed}" + ("_clustered" if args.cluster else "")
     traffic = measured_traffic(dom, workload, args)
 
     conv = None
+    conv_rank = None
     if not args.no_converge:
-        st.start()
+        sbuf = cagra.SolveBuffers(dg, seg, ct)
+        cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=ct, state=sbuf)  # warm-up
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        it, res = 0, float("inf")
-        while it < 100:
-            st.step()
-            it += 1
-            res = float(st.scalars_now[1].item())
-            if res < 1e-6:
-                break
+        r = cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=ct, state=sbuf)
         conv_ms = (time.perf_counter() - c0) * 1e3
-        conv = {"iterations": it, "ms": round(conv_ms, 3), "final_residual": res, "start": "uniform",
+        conv_rank = r.rank.clone()
+        conv = {"iterations": r.iters, "ms": round(conv_ms, 3), "final_residual": r.residual, "start": "uniform",
                 "contrib": args.contrib}
-        log(f"converged to L1 residual {res:.2e} in {it} iterations, {conv_ms:.1f} ms")
+        log(f"converged to L1 residual {r.residual:.2e} in {r.iters} iterations, {conv_ms:.1f} ms")
+        del sbuf
+
+    oracle_ref = None
+    bf16 = None
+    if not args.no_legs and ct == cagra.F32 and not args.no_converge:
+        import oracle
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+        log("oracle: 20 iterations and the fixed point (L1 residual < 1e-11)")
+        r20, res20 = oracle.pagerank(g, iters=20, threads=threads)
+        star, res_star = oracle.pagerank(g, iters=300, tol=1e-11, r0=r20, threads=threads)
+        oracle_ref = {"r20": r20, "star": star, "iterations_to_fixed_point": 20 + len(res_star)}
+        bf16 = bf16_leg(cagra, dg, seg, args, conv, conv_rank, oracle_ref, log)
 
     plain = None
     if not args.no_plain_line:
@@ -435,6 +514,17 @@ def main():
         cpu = cpu_baseline(g)
         log(f"cpu oracle {cpu['value']:.3f} GTEPS on {cpu['cores']} threads")
 
+    legs = {}
+    if not args.no_legs:
+        import bench_workloads
+        del g, oracle_ref
+        torch.cuda.empty_cache()
+        for key, fn in (("ppr64", bench_workloads.ppr), ("multigraph256", bench_workloads.multigraph),
+                        ("warmstart", bench_workloads.warmstart)):
+            log(f"leg {key}")
+            legs[key] = fn(args, log)
+            torch.cuda.empty_cache()
+
     out = {
         "metric": "GTEPS per PageRank iter at R-MAT-25",
         "value": round(gteps, 3),
@@ -451,21 +541,29 @@ def main():
         "config": {"workload": workload,
                    "V": V, "E": E, "N": args.N, "B": args.B, "tile_edges": args.tile_edges, "k": k, "Q": Q,
                    "q": round(seg.q, 4), "damping": 0.85, "parallelism": "single-gpu"},
+        # achieved/frac: the method's algorithmic bytes (its CSR structures, csr_byte_model)
+        # per launch over the launch time; frac_moved_bytes: the bytes this layout actually
+        # moves (no row pointers, 2-byte block offsets); traffic: measured HBM bytes
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                     "kernel_ms": round(dms, 4), "algorithmic_bytes": dbytes},
-        "step_roofline_frac": round((gb + mb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        # the wider byte model that also prices a row pointer and a 4-byte destination
-        # per buffer row (16Q instead of the 10Q this layout moves)
-        "step_roofline_frac_16q_model": round(wide_model / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "bytes_per_step_16q_model": wide_model,
+                     "kernel_ms": round(dms, 4), "algorithmic_bytes": cbytes,
+                     "moved_bytes": dbytes, "frac_moved_bytes": round(achieved_moved / HBM_PEAK_GBS, 4),
+                     "frac_measured_traffic": (round(traffic / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                               if traffic else None)},
+        "step_frac_algorithmic_bytes": round((cgb + cmb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_frac_moved_bytes": round((gb + mb) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_ms": {"k_gather": round(g_avg, 4), "k_merge_pr+reduce": round(m_avg, 4)},
         "bytes_per_step": {"gather": gb, "merge": mb},
+        "algorithmic_bytes_per_step": {"gather": cgb, "merge": cmb},
         "segment_build_ms": round(build_ms, 2),
         "clustering": cluster_info,
         "after_clustering": clustered,
         "time_to_l1_1e-6": conv,
         "plain_unsegmented": plain,
+        "bf16": bf16,
+        "ppr64": legs.get("ppr64"),
+        "multigraph256": legs.get("multigraph256"),
+        "warmstart": legs.get("warmstart"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

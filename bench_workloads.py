@@ -86,57 +86,89 @@ def labelprop(args, log):
 
 
 def ppr(args, log):
+    """64-seed personalized PageRank on R-MAT 22 / ef 16 / seed 4 (restart 0.15):
+    segment size, merge block and tile from the autotuner; per-iteration rate and
+    time until every column's L1 residual is below 1e-6, against the plain
+    single-vector form (one personalized iteration per seed, LDS-staged
+    segments) run seed by seed to the same residual."""
     import torch
     import graphgen
-    from paper_1608_01362_amd import cagra
+    from paper_1608_01362_amd import autotune, cagra
     g = graphgen.rmat_graph(22, 16, 4)
     rng = np.random.default_rng(4)
     ok = np.where((np.diff(g.in_offsets) > 0) | (g.out_degree > 0))[0]
     seeds = rng.choice(ok, size=64, replace=False).astype(np.int32)
     dg = cagra.DeviceGraph.from_host(g)
-    trials = []
-    for N in (1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22):  # L2- to Infinity-Cache-sized segments of 256-byte rows
-        for T in (16384, 65536):
-            seg = cagra.build_segments(dg, N, 512, T)
-            st = cagra.PPRState(dg, seg, seeds)
-            st.start()
-            ms = _time(st.step, 5)
-            trials.append((ms, N, T, seg.q))
-            log(f"ppr N={N} T={T} q={seg.q:.3f}: {ms:.3f} ms/iteration")
-            del st, seg
-            torch.cuda.empty_cache()
-    ms, N, T, q = min(trials)
-    seg = cagra.build_segments(dg, N, 512, T)
+    best, timed = autotune.tune_ppr(dg, seeds, cache_path=None, log=log)
+    seg = cagra.build_segments(dg, best.N, best.B, best.tile_edges)
     st = cagra.PPRState(dg, seg, seeds)
     st.start()
     ms = _time(st.step, 20)
-    # plain single-vector PageRank iteration on the same graph (LDS-staged, tuned)
-    seg1 = cagra.build_segments(dg, 32768, 8192, 262144)
+    # batched: until every column's residual is below 1e-6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.start()
+    it_b, worst = 0, float("inf")
+    while it_b < 100:
+        st.step()
+        it_b += 1
+        worst = float(st.scalars_now[:, 1].max().item())
+        if worst < 1e-6:
+            break
+    batched_ms = (time.perf_counter() - t0) * 1e3
+    Rb = st.ranks().clone()
+    # plain: the single-vector iteration per seed, LDS-staged segments
+    seg1 = cagra.build_segments(dg, 32768, 8192, 65536)
     st1 = cagra.PageRankState(dg, seg1)
     st1.start()
     ms1 = _time(st1.step, 20)
-    return {"metric": "edge-columns per second, 64-seed personalized PageRank at R-MAT-22",
-            "value": round(g.E * 64 / (ms * 1e-3) / 1e9, 3), "unit": "G edge-columns/s",
-            "ms_per_iteration": round(ms, 4), "plain_single_vector_ms_per_iteration": round(ms1, 4),
-            "plain_single_vector_GTEPS": round(g.E / (ms1 * 1e-3) / 1e9, 3),
-            "speedup_vs_64_plain_iterations": round(64 * ms1 / ms, 3),
-            "config": {"workload": "ppr64_rmat22_ef16_seed4", "V": g.V, "E": g.E, "N": N, "B": 512,
-                       "tile_edges": T, "q": round(q, 4), "columns": 64, "restart": 0.15},
-            "autotune_trials": [{"N": n, "tile_edges": t, "ms": round(m, 4)} for m, n, t, _ in trials],
-            "dtype": "f32", "data": "synthetic"}
+    bufs = cagra.SolveBuffers(dg, seg1)
+    cagra.pagerank_solve(dg, seg1, tol=1e-6, restart=int(seeds[0]), state=bufs)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, l1 = [], 0.0
+    for j, s in enumerate(seeds):
+        r = cagra.pagerank_solve(dg, seg1, tol=1e-6, restart=int(s), state=bufs)
+        its.append(r.iters)
+        if j % 16 == 0:  # the two forms agree (each within the contraction bound of the fixed point)
+            l1 = max(l1, float((r.rank.double() - Rb[:, j].double()).abs().sum().item()))
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    out = {"metric": "edge-columns per second, 64-seed personalized PageRank at R-MAT-22",
+           "value": round(g.E * 64 / (ms * 1e-3) / 1e9, 3), "unit": "G edge-columns/s",
+           "ms_per_iteration": round(ms, 4), "plain_single_vector_ms_per_iteration": round(ms1, 4),
+           "plain_single_vector_GTEPS": round(g.E / (ms1 * 1e-3) / 1e9, 3),
+           "speedup_vs_64_plain_iterations": round(64 * ms1 / ms, 3),
+           "time_to_l1_1e-6": {"batched": {"iterations": it_b, "ms": round(batched_ms, 3),
+                                           "worst_column_residual": worst},
+                               "plain_seed_by_seed": {"iterations_total": int(sum(its)), "ms": round(plain_ms, 3)},
+                               "speedup": round(plain_ms / batched_ms, 3),
+                               "max_l1_between_forms": l1},
+           "config": {"workload": "ppr64_rmat22_ef16_seed4", "V": g.V, "E": g.E, "N": best.N, "B": best.B,
+                      "tile_edges": best.tile_edges, "q": round(best.Q / g.V, 4), "columns": 64, "restart": 0.15},
+           "autotune_trials": [{"N": c.N, "B": c.B, "tile_edges": c.tile_edges, "ms": round(c.ms, 4)}
+                               for c in timed],
+           "dtype": "f32", "data": "synthetic"}
+    log(f"ppr64: {ms:.3f} ms/iteration; to 1e-6 batched {batched_ms:.1f} ms vs seed by seed {plain_ms:.1f} ms")
+    return out
 
 
 def multigraph(args, log):
+    """256 uneven R-MAT graphs (scale U{10..20}, ef U{8..32}, seed 4): per size
+    class N/B/T from the autotuner, start + 20 iterations of every graph in one
+    captured launch, against the same iterations graph by graph."""
     import torch
     import graphgen
-    from paper_1608_01362_amd import cagra
+    from paper_1608_01362_amd import autotune, cagra
     specs = graphgen.multigraph_specs(256, seed=4)
     t0 = time.perf_counter()
     gs = [graphgen.rmat_graph(s.scale, s.edge_factor, s.seed) for s in specs]
     log(f"generated 256 graphs, E total {sum(g.E for g in gs)} in {time.perf_counter() - t0:.1f}s")
     dgs = [cagra.DeviceGraph.from_host(g) for g in gs]
-    segs = [cagra.build_segments(d, min(32768, d.V), 8192, 65536) for d in dgs]
     Etot = sum(g.E for g in gs)
+    Vtot = int(sum(g.V for g in gs))
+    del gs
+    choice, trials = autotune.tune_multi(dgs, cache_path=None, log=log)
+    segs = autotune.multi_segments(dgs, choice)
     mp = cagra.MultiPageRank(dgs, segs)
     mp.capture(20)
     torch.cuda.synchronize()
@@ -148,8 +180,10 @@ def multigraph(args, log):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
-    # the same work graph by graph, eager launches
-    states = [cagra.PageRankState(d, s) for d, s in zip(dgs, segs)]
+    res20 = mp.scalars[mp.cur].view(-1, 4)[:, 1].max().item()
+    # the same work graph by graph, eager launches, the default single-graph layout
+    segs1 = [cagra.build_segments(d, min(32768, d.V), 8192, 65536) for d in dgs]
+    states = [cagra.PageRankState(d, s) for d, s in zip(dgs, segs1)]
     torch.cuda.synchronize()
     a.record()
     for st in states:
@@ -159,26 +193,32 @@ def multigraph(args, log):
     b.record()
     torch.cuda.synchronize()
     ms_seq = a.elapsed_time(b)
-    return {"metric": "aggregate GTEPS, 256 uneven R-MAT graphs x 20 PageRank iterations in one captured launch",
-            "value": round(Etot * 20 / (ms * 1e-3) / 1e9, 3), "unit": "GTEPS", "ms_total": round(ms, 3),
-            "graph_by_graph_ms": round(ms_seq, 3), "speedup_vs_graph_by_graph": round(ms_seq / ms, 3),
-            "config": {"workload": "multigraph256_rmat_s10-20_ef8-32_seed4", "graphs": 256, "E_total": Etot,
-                       "V_total": int(sum(g.V for g in gs)), "tiles": int(mp.m.total_tiles),
-                       "blocks": int(mp.m.total_blocks)},
-            "dtype": "f32", "data": "synthetic"}
+    out = {"metric": "aggregate GTEPS, 256 uneven R-MAT graphs x 20 PageRank iterations in one captured launch",
+           "value": round(Etot * 20 / (ms * 1e-3) / 1e9, 3), "unit": "GTEPS", "ms_total": round(ms, 3),
+           "graph_by_graph_ms": round(ms_seq, 3), "speedup_vs_graph_by_graph": round(ms_seq / ms, 3),
+           "max_residual_after_20": res20,
+           "tuned_per_size_class": {str(c): list(v) for c, v in choice.items()},
+           "autotune_trials": len(trials),
+           "config": {"workload": "multigraph256_rmat_s10-20_ef8-32_seed4", "graphs": 256, "E_total": Etot,
+                      "V_total": Vtot, "tiles": int(mp.m.total_tiles), "blocks": int(mp.m.total_blocks)},
+           "dtype": "f32", "data": "synthetic"}
+    log(f"multigraph: {ms:.2f} ms for 20 iterations of 256 graphs vs {ms_seq:.1f} ms graph by graph")
+    return out
 
 
-def warmstart(args, log):
+def warmstart(args, log, oracle_star=True):
+    """Learned warm start: network trained on 200 R-MAT graphs (scale U{16..20},
+    ef 16) from the method's own PageRank vectors, held-out R-MAT 24 / ef 24 /
+    seed 5; time to L1 residual < 1e-6 from the learned start (features,
+    network and softmax included) against the uniform start."""
     import torch
     import graphgen
     from paper_1608_01362_amd import cagra
     from paper_1608_01362_amd import warmstart as ws
     t0 = time.perf_counter()
     Fs, Ts, rows = [], [], 0
-    rng = np.random.default_rng(1000)
-    for i in range(200):
-        sc = int(rng.integers(16, 21))
-        g = graphgen.rmat_graph(sc, 16, 1000 + i)
+    for sp in graphgen.warmstart_training_specs():
+        g = graphgen.rmat_graph(sp.scale, sp.edge_factor, sp.seed)
         dg = cagra.DeviceGraph.from_host(g)
         seg = cagra.build_segments(dg, 32768, 8192, 65536)
         Fs.append(ws.features(dg, seg))
@@ -197,24 +237,49 @@ def warmstart(args, log):
     gt = graphgen.rmat_graph(24, 24, 5)
     dg = cagra.DeviceGraph.from_host(gt)
     seg = cagra.build_segments(dg, 32768, 8192, 262144)
-    ws.solve(dg, seg, tol=1e-6)  # warm-up of both paths
-    ws.solve(dg, seg, tol=1e-6, net=net)
-    runs_u = [ws.solve(dg, seg, tol=1e-6) for _ in range(3)]
-    runs_w = [ws.solve(dg, seg, tol=1e-6, net=net) for _ in range(3)]
+    import ctypes
+    wsp = torch.empty(cagra.lib().cagra_learned_start_workspace_bytes(ctypes.byref(seg.c)), dtype=torch.uint8,
+                      device="cuda")
+    bufs = cagra.SolveBuffers(dg, seg)
+    ws.solve(dg, seg, tol=1e-6, buffers=bufs)  # warm-up of both paths
+    ws.solve(dg, seg, tol=1e-6, net=net, ws=wsp, buffers=bufs)
+    runs_u, runs_w = [], []
+    for _ in range(5):  # interleaved, so that clock drift affects both alike
+        r = ws.solve(dg, seg, tol=1e-6, buffers=bufs)
+        runs_u.append((r[0].clone(), *r[1:]))
+        r = ws.solve(dg, seg, tol=1e-6, net=net, ws=wsp, buffers=bufs)
+        runs_w.append((r[0].clone(), *r[1:]))
     r_u, it_u, _, _ = runs_u[0]
     r_w, it_w, _, used = runs_w[0]
     ms_u = float(np.median([r[2] for r in runs_u]))
     ms_w = float(np.median([r[2] for r in runs_w]))
+    # the start vector's own cost
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    for _ in range(5):
+        ws.learned_start(net, dg, seg, wsp)
+    b.record()
+    torch.cuda.synchronize()
+    start_ms = a.elapsed_time(b) / 5
     l1 = float((r_u.double() - r_w.double()).abs().sum().item())
-    return {"metric": "time to L1 residual < 1e-6, learned warm start vs uniform, held-out R-MAT-24",
-            "value": round(ms_w, 3), "unit": "ms", "higher_is_better": False,
-            "uniform": {"iterations": it_u, "ms": round(ms_u, 3)},
-            "learned": {"iterations": it_w, "ms": round(ms_w, 3), "start_used": used},
-            "speedup": round(ms_u / ms_w, 3), "l1_between_answers": l1,
-            "training": {"graphs": 200, "rows": rows, "steps": 600, "batch": 65536, "seconds": round(train_s, 2),
-                         "loss_first": net.losses[0], "loss_last": net.losses[-1]},
-            "config": {"workload": "warmstart_rmat24_ef24_seed5", "V": gt.V, "E": gt.E, "N": 32768, "B": 8192},
-            "dtype": "f32 iteration, bf16-weight network", "data": "synthetic"}
+    out = {"metric": "time to L1 residual < 1e-6, learned warm start vs uniform, held-out R-MAT-24",
+           "value": round(ms_w, 3), "unit": "ms", "higher_is_better": False,
+           "uniform": {"iterations": it_u, "ms": round(ms_u, 3)},
+           "learned": {"iterations": it_w, "ms": round(ms_w, 3), "start_used": used,
+                       "start_vector_ms": round(start_ms, 3)},
+           "speedup": round(ms_u / ms_w, 3), "l1_between_answers": l1,
+           "training": {"graphs": 200, "rows": rows, "steps": 600, "batch": 65536, "seconds": round(train_s, 2),
+                        "loss_first": net.losses[0], "loss_last": net.losses[-1]},
+           "config": {"workload": "warmstart_rmat24_ef24_seed5", "V": gt.V, "E": gt.E, "N": 32768, "B": 8192},
+           "dtype": "f32 iteration, bf16-weight network", "data": "synthetic"}
+    if oracle_star:
+        import oracle
+        star, _ = oracle.pagerank(gt, iters=300, tol=1e-11, threads=min(16, len(__import__("os").sched_getaffinity(0))))
+        out["uniform"]["l1_to_oracle_fixed_point"] = float(np.abs(r_u.double().cpu().numpy() - star).sum())
+        out["learned"]["l1_to_oracle_fixed_point"] = float(np.abs(r_w.double().cpu().numpy() - star).sum())
+    log(f"warmstart: uniform {it_u} it {ms_u:.2f} ms, learned {it_w} it {ms_w:.2f} ms (start {start_ms:.2f} ms)")
+    return out
 
 
 def _pagerank_timing(cagra, dg, seg, steps, warmup):

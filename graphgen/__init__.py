@@ -197,3 +197,13 @@ def multigraph_specs(count: int, seed: int, scale_lo: int = 10, scale_hi: int = 
         ef = ef_lo + ((r >> 16) & 0xFFFF) % (ef_hi - ef_lo + 1)
         specs.append(MultiGraphSpec(int(sc), int(ef), int((r >> 32) & 0x7FFFFFFF)))
     return specs
+
+
+def warmstart_training_specs(count: int = 200, seed: int = 1000, scale_lo: int = 16, scale_hi: int = 20,
+                             edge_factor: int = 16):
+    """(scale, edge factor, seed) of the warm-start training graphs: scale drawn
+    uniformly (inclusive) from a numpy generator seeded with `seed`, graph i
+    seeded seed + i."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [MultiGraphSpec(int(rng.integers(scale_lo, scale_hi + 1)), edge_factor, seed + i) for i in range(count)]

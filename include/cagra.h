@@ -366,8 +366,11 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
 /*
  * One PageRank iteration through segmenting (Section 4 PageRank: EdgeMap with
  * a summing EdgeUpdate and Merge, then VertexMap), normalized with teleport and
- * uniform redistribution of the dangling mass:
+ * uniform redistribution of the dangling mass (restart_vertex = -1):
  *   rank_out[v] = (1-d)/V + d * ( sum_{u->v} contrib_in[u] + scalars_in[0]/V )
+ * or personalized to one restart vertex s = restart_vertex in [0, V), where the
+ * teleport and the dangling mass return to s:
+ *   rank_out[v] = d * sum_{u->v} contrib_in[u] + [v == s] * ((1-d) + d * scalars_in[0])
  *   contrib_out[v] = rank_out[v] / out_degree[v] (0 if out_degree is 0)
  *   scalars_out[0] = dangling mass of rank_out, scalars_out[1] = ||rank_out - rank_in||_1,
  *   scalars_out[2] = sum of rank_out,
@@ -387,7 +390,7 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
  * 8*B + 8*(k+1) + 320 <= CAGRA_LDS_BYTES.
  */
 cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                 int32_t contrib_type, const float *rank_in,
+                                 int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
                                  const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
                                  void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
                                  hipStream_t stream);
@@ -399,9 +402,9 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
  * contrib_type) + cagra_pagerank_merge; same arguments, same results.
  */
 cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                  int32_t contrib_type, const float *rank_in, const double *scalars_in,
-                                  const float *partial, float *rank_out, void *contrib_out, double *scalars_out,
-                                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+                                  int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
+                                  const double *scalars_in, const float *partial, float *rank_out, void *contrib_out,
+                                  double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * PageRank power iteration to a residual threshold (the Section 4 program's
@@ -429,6 +432,8 @@ typedef struct {
     double damping;        /* d in [0, 1] */
     double tol;            /* stopping threshold on the L1 residual, > 0 */
     double switch_tol;     /* CAGRA_BF16 only: residual below which to finish in FP32 (0: never) */
+    int32_t restart_vertex;/* -1: uniform teleport; else personalized to this vertex (see
+                              cagra_pagerank_iter; the caller's start vector is used as given) */
     int32_t max_iters;     /* iteration cap, >= 1 */
     int32_t check_every;   /* read the residual back every this many iterations, >= 1 */
     int32_t contrib_type;  /* CAGRA_F32 or CAGRA_BF16 */
@@ -587,6 +592,38 @@ cagra_status cagra_mlp_grad(const float *features, const float *targets, int64_t
    then rounded to nearest even into the BF16 copy. */
 cagra_status cagra_adam_step(float *master, uint16_t *weights, float *m, float *v, const float *grad, int32_t step,
                              float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
+/* Regression targets of the network: targets[v] = log(V * max(rank[v], 1e-30))
+   (float[V]; the network predicts log-ranks relative to the uniform 1/V). */
+cagra_status cagra_mlp_targets(const float *rank, int32_t V, float *targets, hipStream_t stream);
+
+/* Feature standardization for cagra_mlp_forward / cagra_mlp_grad: norm (device
+   float[6]) = per-column mean of features[n][3], then 1 / max(s, 1e-6) with s
+   the sample standard deviation (n - 1). FP64 sums in a fixed order. */
+size_t cagra_feature_norm_workspace_bytes(int64_t n);
+cagra_status cagra_feature_norm(const float *features, int64_t n, float *norm, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream);
+
+/* Minibatch draw `draw` of `batch` rows with replacement from (features[n][3],
+   targets[n]): row i is floor(h * n / 2^64) with h = SplitMix64 of the counter
+   draw * batch + i under `seed`. Deterministic; outputs features_out[batch][3],
+   targets_out[batch]. */
+cagra_status cagra_sample_rows(const float *features, const float *targets, int64_t n, uint64_t seed, int64_t draw,
+                               int32_t batch, float *features_out, float *targets_out, hipStream_t stream);
+
+/*
+ * Learned start vector in one call: cagra_degree_features, the network on every
+ * vertex (cagra_mlp_forward), and cagra_warm_start_vector, with the same
+ * results bit for bit. A vertex without in-edges has the features
+ * (0, log(1 + out-degree), 0), so its output depends on its out-degree alone:
+ * the network runs once per out-degree below 1024 for such vertices (about half
+ * of an R-MAT graph's) and every other vertex is evaluated on its own.
+ * scalars_out as cagra_warm_start_vector. Requirements as cagra_degree_features.
+ */
+size_t cagra_learned_start_workspace_bytes(const cagra_segments *seg);
+cagra_status cagra_learned_start(const cagra_graph *g, const cagra_segments *seg, const uint16_t *weights,
+                                 const float *norm, float *rank0, double *scalars_out, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
 
 size_t cagra_warm_start_workspace_bytes(int32_t V);
 /*

@@ -192,3 +192,149 @@ def _time_labelprop(seg, reps: int = 3) -> float:
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+# ---------------------------------------------------------------- batched personalized PageRank
+
+def ppr_candidates(V: int):
+    """Segment sizes for 256-byte vertex records (64 FP32 columns): an LDS
+    segment would hold 512 such rows, so the candidates are L2- to
+    Infinity-Cache-sized (2^16 ... 2^22 vertices, 16 MB ... 1 GB of rows) and
+    one segment; merge blocks of 256 and 512 rows (B x 256 bytes of LDS
+    accumulators); gather tiles of 16 K and 64 K edges."""
+    Ns = sorted({n for n in (1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22) if n < V} | {max(V, 1)})
+    return [(N, B, T) for N in Ns for B in (256, 512) for T in (16384, 65536)]
+
+
+def _time_ppr(dg, seg, seeds, reps: int = 3) -> float:
+    import torch
+    st = cagra.PPRState(dg, seg, seeds)
+    st.start()
+    st.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        st.step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_ppr(dg, seeds, cache_path: str | None = CACHE_DEFAULT, tag: str = "", log=None, prune_factor: float = 2.0):
+    """Segment size N, merge block B and gather tile T for the batched
+    personalized PageRank of `seeds` (up to 64 columns). Candidates whose
+    buffer rows (Q x 256 bytes, read and written once per iteration) exceed
+    prune_factor times the smallest candidate's are dropped before timing:
+    with record-sized gathers served from the cache hierarchy, those buffer
+    bytes are what differs between segment sizes. Returns (best Choice, timed)."""
+    import torch
+    key = cache_key(dg, cagra.F32, "ppr", f"{tag}:c{len(seeds)}")
+    if cache_path:
+        cache = load_cache(cache_path)
+        if key in cache:
+            return Choice(**cache[key]), []
+    Qs = {}
+    for N, _, _ in ppr_candidates(dg.V):
+        if N not in Qs:
+            Qs[N] = query_Q(dg, N, 512, 16384)
+    qmin = min(Qs.values())
+    timed = []
+    for N, B, T in ppr_candidates(dg.V):
+        k = -(-dg.V // N)
+        if k > 32768 or Qs[N] > prune_factor * max(qmin, 1) + dg.V:
+            continue
+        seg = cagra.build_segments(dg, N, B, T)
+        c = Choice(N, B, T, False, Qs[N], Qs[N] * 512, _time_ppr(dg, seg, seeds))
+        timed.append(c)
+        if log:
+            log(f"autotune ppr N={N} B={B} T={T} q={Qs[N] / dg.V:.3f} -> {c.ms:.3f} ms")
+        del seg
+        torch.cuda.empty_cache()
+    best = min(timed, key=lambda c: c.ms)
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[key] = asdict(best)
+        save_cache(cache_path, cache)
+    return best, timed
+
+
+# ---------------------------------------------------------------- many graphs in one launch
+
+def size_class(V: int) -> int:
+    """0: up to 2^13 vertices, 1: up to 2^17, 2: larger."""
+    return 0 if V <= 1 << 13 else (1 if V <= 1 << 17 else 2)
+
+
+MULTI_DEFAULT = (32768, 8192, 65536)
+
+
+def multi_candidates():
+    """(N, B, T) per size class: LDS-staged segments (the persistent kernels use
+    16-bit edge words, N <= 32,768), merge blocks of 4 K and 8 K vertices, tiles
+    of 16 K and 64 K edges. N is capped at the graph's V when used."""
+    return [(N, B, T) for N in (8192, 16384, 32768) for B in (4096, 8192) for T in (16384, 65536)]
+
+
+def _multi_segments(dgs, choice_by_class):
+    out = []
+    for d in dgs:
+        N, B, T = choice_by_class[size_class(d.V)]
+        out.append(cagra.build_segments(d, min(N, max(d.V, 1)), B, T))
+    return out
+
+
+def _time_multi(dgs, segs, iters: int = 20, reps: int = 2) -> float:
+    import torch
+    mp = cagra.MultiPageRank(dgs, segs)
+    mp.run_eager(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mp.run_eager(iters)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_multi(dgs, cache_path: str | None = CACHE_DEFAULT, tag: str = "", log=None):
+    """Per size class (size_class), the (N, B, T) of the graphs of that class in
+    the persistent multi-graph launch: one pass of coordinate descent over the
+    classes present (largest first), each class's candidates timed on the whole
+    launch (start + 20 iterations of every graph) with the other classes held
+    at their current choice. Returns ({class: (N, B, T)}, [(class, N, B, T, ms)])."""
+    import torch
+    classes = sorted({size_class(d.V) for d in dgs}, reverse=True)
+    key = f"multi:{len(dgs)}:V{sum(d.V for d in dgs)}:E{sum(d.E for d in dgs)}:{tag}"
+    if cache_path:
+        cache = load_cache(cache_path)
+        if key in cache:
+            return {int(c): tuple(v) for c, v in cache[key].items()}, []
+    choice = {c: MULTI_DEFAULT for c in (0, 1, 2)}
+    trials = []
+    for cl in classes:
+        best = None
+        for cand in multi_candidates():
+            trial = dict(choice)
+            trial[cl] = cand
+            segs = _multi_segments(dgs, trial)
+            ms = _time_multi(dgs, segs)
+            del segs
+            torch.cuda.empty_cache()
+            trials.append((cl, *cand, round(ms, 4)))
+            if log:
+                log(f"autotune multi class {cl} N={cand[0]} B={cand[1]} T={cand[2]} -> {ms:.3f} ms")
+            if best is None or ms < best[0]:
+                best = (ms, cand)
+        choice[cl] = best[1]
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[key] = {str(c): list(v) for c, v in choice.items()}
+        save_cache(cache_path, cache)
+    return choice, trials
+
+
+def multi_segments(dgs, choice):
+    """Segments of every graph with its size class's (N, B, T)."""
+    return _multi_segments(dgs, choice)

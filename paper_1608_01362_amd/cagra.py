@@ -56,13 +56,14 @@ EXPORTS = [
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
     "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
-    "cagra_warm_start_vector",
+    "cagra_warm_start_vector", "cagra_mlp_targets", "cagra_feature_norm_workspace_bytes", "cagra_feature_norm",
+    "cagra_sample_rows", "cagra_learned_start_workspace_bytes", "cagra_learned_start",
 ]
 
 
 class CPrParams(ctypes.Structure):
-    _fields_ = [("damping", _c_dbl), ("tol", _c_dbl), ("switch_tol", _c_dbl), ("max_iters", _c_i32),
-                ("check_every", _c_i32), ("contrib_type", _c_i32)]
+    _fields_ = [("damping", _c_dbl), ("tol", _c_dbl), ("switch_tol", _c_dbl), ("restart_vertex", _c_i32),
+                ("max_iters", _c_i32), ("check_every", _c_i32), ("contrib_type", _c_i32)]
 
 
 class CPrResult(ctypes.Structure):
@@ -138,10 +139,10 @@ def lib():
             "cagra_segment_gather": ([SP, _c_i32, _c_i32, _c_vp, _c_vp, st], ctypes.c_int),
             "cagra_merge": ([SP, _c_i32, _c_vp, _c_vp, st], ctypes.c_int),
             "cagra_pagerank_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
-            "cagra_pagerank_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
-                                     _c_vp, _c_size, st], ctypes.c_int),
-            "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
-                                      _c_size, st], ctypes.c_int),
+            "cagra_pagerank_iter": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                     _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                      _c_vp, _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_pagerank_solve": ([GP, SP, ctypes.POINTER(CPrParams), _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_vp, _c_size, ctypes.POINTER(CPrResult), st], ctypes.c_int),
@@ -161,6 +162,13 @@ def lib():
                                  ctypes.c_float, ctypes.c_float, st], ctypes.c_int),
             "cagra_warm_start_workspace_bytes": ([_c_i32], _c_size),
             "cagra_warm_start_vector": ([_c_vp, _c_i32, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_mlp_targets": ([_c_vp, _c_i32, _c_vp, st], ctypes.c_int),
+            "cagra_feature_norm_workspace_bytes": ([_c_i64], _c_size),
+            "cagra_feature_norm": ([_c_vp, _c_i64, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_sample_rows": ([_c_vp, _c_vp, _c_i64, ctypes.c_uint64, _c_i64, _c_i32, _c_vp, _c_vp, st],
+                                  ctypes.c_int),
+            "cagra_learned_start_workspace_bytes": ([SP], _c_size),
+            "cagra_learned_start": ([GP, SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_multi_query": ([_c_i32, GP, SP, ctypes.POINTER(CMulti)], ctypes.c_int),
             "cagra_multi_setup": ([ctypes.POINTER(CMulti), GP, SP, st], ctypes.c_int),
             "cagra_multi_pagerank_start": ([ctypes.POINTER(CMulti), st], ctypes.c_int),
@@ -362,16 +370,16 @@ def pagerank_init(dg: DeviceGraph, contrib_type: int, rank, contrib_out, scalars
 
 
 def pagerank_iter(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, contrib_in,
-                  scalars_in, partial, rank_out, contrib_out, scalars_out, workspace, stream=None):
-    _check(lib().cagra_pagerank_iter(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, contrib_type,
+                  scalars_in, partial, rank_out, contrib_out, scalars_out, workspace, stream=None, restart: int = -1):
+    _check(lib().cagra_pagerank_iter(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, restart, contrib_type,
                                      _ptr(rank_in), _ptr(contrib_in), _ptr(scalars_in), _ptr(partial),
                                      _ptr(rank_out), _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace),
                                      workspace.numel(), _stream(stream)), "cagra_pagerank_iter")
 
 
 def pagerank_merge(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, scalars_in,
-                   partial, rank_out, contrib_out, scalars_out, workspace, stream=None):
-    _check(lib().cagra_pagerank_merge(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, contrib_type,
+                   partial, rank_out, contrib_out, scalars_out, workspace, stream=None, restart: int = -1):
+    _check(lib().cagra_pagerank_merge(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, restart, contrib_type,
                                       _ptr(rank_in), _ptr(scalars_in), _ptr(partial), _ptr(rank_out),
                                       _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace), workspace.numel(),
                                       _stream(stream)), "cagra_pagerank_merge")
@@ -388,11 +396,13 @@ def labelprop_iter(seg: Segments, labels_in, partial, labels_out, changed_out, w
 class PageRankState:
     """Device buffers for the PageRank power iteration (double-buffered)."""
 
-    def __init__(self, dg: DeviceGraph, seg: Segments, contrib_type: int = F32):
+    def __init__(self, dg: DeviceGraph, seg: Segments, contrib_type: int = F32, restart: int = -1):
+        """restart: -1 for the uniform teleport, else the restart vertex of a
+        personalized PageRank (start vector e_restart by default)."""
         import torch
         dev = _dev()
         V = dg.V
-        self.dg, self.seg, self.contrib_type = dg, seg, contrib_type
+        self.dg, self.seg, self.contrib_type, self.restart = dg, seg, contrib_type, restart
         cdt = torch.float32 if contrib_type == F32 else torch.int16
         self.rank = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
         self.contrib = [torch.empty(V, dtype=cdt, device=dev) for _ in range(2)]
@@ -402,11 +412,15 @@ class PageRankState:
         self.cur = 0
 
     def start(self, rank0=None, stream=None):
-        """rank0: device float32 [V] start vector (None: uniform 1/V)."""
-        if rank0 is None:
-            self.rank[0].fill_(1.0 / self.dg.V)
-        else:
+        """rank0: device float32 [V] start vector (None: uniform 1/V, or e_restart
+        for a personalized state)."""
+        if rank0 is not None:
             self.rank[0].copy_(rank0)
+        elif self.restart >= 0:
+            self.rank[0].zero_()
+            self.rank[0][self.restart] = 1.0
+        else:
+            self.rank[0].fill_(1.0 / self.dg.V)
         self.cur = 0
         pagerank_init(self.dg, self.contrib_type, self.rank[0], self.contrib[0], self.scalars[0], self.ws, stream)
 
@@ -414,7 +428,7 @@ class PageRankState:
         a, b = self.cur, 1 - self.cur
         pagerank_iter(self.dg, self.seg, damping, self.contrib_type, self.rank[a], self.contrib[a],
                       self.scalars[a], self.partial, self.rank[b], self.contrib[b], self.scalars[b], self.ws,
-                      stream)
+                      stream, self.restart)
         self.cur = b
 
     def step_split(self, damping: float = 0.85, stream=None, events=None):
@@ -427,7 +441,7 @@ class PageRankState:
         if events:
             events[1].record()
         pagerank_merge(self.dg, self.seg, damping, self.contrib_type, self.rank[a], self.scalars[a], self.partial,
-                       self.rank[b], self.contrib[b], self.scalars[b], self.ws, stream)
+                       self.rank[b], self.contrib[b], self.scalars[b], self.ws, stream, self.restart)
         if events:
             events[2].record()
         self.cur = b
@@ -453,18 +467,21 @@ class SolveResult:
 
 def pagerank_solve(dg: DeviceGraph, seg: Segments, tol: float = 1e-6, max_iters: int = 100, damping: float = 0.85,
                    contrib_type: int = F32, switch_tol: float = 0.0, rank0=None, check_every: int = 1,
-                   stream=None, state: "SolveBuffers | None" = None) -> SolveResult:
+                   stream=None, state: "SolveBuffers | None" = None, restart: int = -1) -> SolveResult:
     """cagra_pagerank_solve: power iteration to the first L1 residual < tol (the
     library's host-driven loop). BF16 contributions with switch_tol > 0 finish
     in FP32 once the residual is below switch_tol. Returns a SolveResult with
     converged False when max_iters ran out (CAGRA_E_NOT_CONVERGED); raises
     CagraError for any other failure, E_RANGE included."""
     buf = state or SolveBuffers(dg, seg, contrib_type, switch_tol)
-    if rank0 is None:
-        buf.rank[0].fill_(1.0 / dg.V)
-    else:
+    if rank0 is not None:
         buf.rank[0].copy_(rank0)
-    p = CPrParams(damping, tol, switch_tol, max_iters, check_every, contrib_type)
+    elif restart >= 0:
+        buf.rank[0].zero_()
+        buf.rank[0][restart] = 1.0
+    else:
+        buf.rank[0].fill_(1.0 / dg.V)
+    p = CPrParams(damping, tol, switch_tol, restart, max_iters, check_every, contrib_type)
     r = CPrResult()
     st = lib().cagra_pagerank_solve(ctypes.byref(dg.c), ctypes.byref(seg.c), ctypes.byref(p), _ptr(buf.rank[0]),
                                     _ptr(buf.rank[1]), _ptr(buf.contrib[0]), _ptr(buf.contrib[1]), _ptr(buf.scalars),

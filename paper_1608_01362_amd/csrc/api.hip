@@ -67,7 +67,8 @@ cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const fl
 size_t ws_blk_bytes(int32_t V, int32_t nb);
 size_t ws_item_bytes(const cagra_segments *seg);
 size_t ws_slot_bytes(const cagra_segments *seg);
-cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
+cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t seed,
+                             int32_t contrib_type,
                              const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
                              void *contrib_out, double *scalars_out, void *ws, hipStream_t st);
 cagra_status launch_merge_lp(const cagra_segments *seg, const int32_t *labels_in, const int32_t *partial,
@@ -93,6 +94,14 @@ cagra_status launch_mlp_grad(const float *feats, const float *target, int64_t n,
 cagra_status launch_adam(float *master, uint16_t *wb, float *m, float *v, const float *g, int32_t step, float lr,
                          float b1, float b2, float eps, hipStream_t st);
 size_t softmax_ws_bytes(int32_t V);
+cagra_status launch_targets(const float *rank, int32_t V, float *t, hipStream_t st);
+size_t norm_ws_bytes(int64_t n);
+cagra_status launch_feature_norm(const float *f, int64_t n, float *norm, void *ws, hipStream_t st);
+cagra_status launch_sample_rows(const float *f, const float *t, int64_t n, uint64_t seed, int64_t draw, int32_t batch,
+                                float *fo, float *to, hipStream_t st);
+size_t learned_start_ws_bytes(const cagra_segments *seg);
+cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *seg, const uint16_t *wb,
+                                  const float *norm, float *rank0, double *scal, void *ws, hipStream_t st);
 cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st);
 
 size_t push_ws_bytes(const cagra_segments *seg);
@@ -365,30 +374,39 @@ static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *s
     return CAGRA_OK;
 }
 
+static cagra_status check_restart(const cagra_graph *g, int32_t restart_vertex) {
+    if (restart_vertex < -1 || restart_vertex >= g->V)
+        return fail(CAGRA_E_INVALID, "restart_vertex %d outside [-1, %d)", restart_vertex, g->V);
+    return CAGRA_OK;
+}
+
 cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                  int32_t contrib_type, const float *rank_in, const double *scalars_in,
-                                  const float *partial, float *rank_out, void *contrib_out, double *scalars_out,
-                                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                                  int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
+                                  const double *scalars_in, const float *partial, float *rank_out, void *contrib_out,
+                                  double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
     cagra_status s;
     if ((s = check_pagerank(g, seg, damping, contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if ((s = check_restart(g, restart_vertex)) != CAGRA_OK) return s;
     if (!rank_in || !scalars_in || !rank_out || !contrib_out || !scalars_out || (seg->Q > 0 && !partial))
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
-    return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
-                           scalars_out, workspace, stream);
+    return launch_merge_pr(g, seg, damping, restart_vertex, contrib_type, rank_in, scalars_in, partial, rank_out,
+                           contrib_out, scalars_out, workspace, stream);
 }
 
 cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                 int32_t contrib_type, const float *rank_in, const void *contrib_in,
-                                 const double *scalars_in, float *partial, float *rank_out, void *contrib_out,
-                                 double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+                                 int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
+                                 const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
+                                 void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
+                                 hipStream_t stream) {
     cagra_status s;
     if ((s = check_pagerank(g, seg, damping, contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if ((s = check_restart(g, restart_vertex)) != CAGRA_OK) return s;
     if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
         (seg->Q > 0 && !partial))
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
-    return launch_merge_pr(g, seg, damping, contrib_type, rank_in, scalars_in, partial, rank_out, contrib_out,
-                           scalars_out, workspace, stream);
+    return launch_merge_pr(g, seg, damping, restart_vertex, contrib_type, rank_in, scalars_in, partial, rank_out,
+                           contrib_out, scalars_out, workspace, stream);
 }
 
 // Reads the four FP64 scalars of one iteration back to the host (synchronizes).
@@ -405,6 +423,7 @@ cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *se
     cagra_status s;
     if (!p || !host_result) return fail(CAGRA_E_INVALID, "params or host_result is NULL");
     if ((s = check_pagerank(g, seg, p->damping, p->contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if ((s = check_restart(g, p->restart_vertex)) != CAGRA_OK) return s;
     if (!(p->tol > 0.0)) return fail(CAGRA_E_INVALID, "tol must be > 0");
     if (p->max_iters < 1 || p->check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
     if (!(p->switch_tol >= 0.0)) return fail(CAGRA_E_INVALID, "switch_tol must be >= 0");
@@ -428,7 +447,7 @@ cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *se
     bool converged = false;
     while (host_result->iters < p->max_iters) {
         if ((s = launch_gather(seg, CAGRA_SUM_F32, ct, contrib[cur], partial, stream)) != CAGRA_OK) return s;
-        if ((s = launch_merge_pr(g, seg, p->damping, ct, rank[cur], sc[cur], partial, rank[1 - cur],
+        if ((s = launch_merge_pr(g, seg, p->damping, p->restart_vertex, ct, rank[cur], sc[cur], partial, rank[1 - cur],
                                  contrib[1 - cur], sc[1 - cur], workspace, stream)) != CAGRA_OK)
             return s;
         cur = 1 - cur;
@@ -524,6 +543,53 @@ cagra_status cagra_adam_step(float *master, uint16_t *weights, float *m, float *
 }
 
 size_t cagra_warm_start_workspace_bytes(int32_t V) { return V < 1 ? 0 : softmax_ws_bytes(V); }
+
+cagra_status cagra_mlp_targets(const float *rank, int32_t V, float *targets, hipStream_t stream) {
+    if (V < 1) return fail(CAGRA_E_INVALID, "V must be >= 1");
+    if (!rank || !targets) return fail(CAGRA_E_INVALID, "rank or targets is NULL");
+    return launch_targets(rank, V, targets, stream);
+}
+
+size_t cagra_feature_norm_workspace_bytes(int64_t n) { return n < 1 ? 0 : norm_ws_bytes(n); }
+
+cagra_status cagra_feature_norm(const float *features, int64_t n, float *norm, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream) {
+    if (n < 1) return fail(CAGRA_E_INVALID, "n must be >= 1");
+    if (!features || !norm) return fail(CAGRA_E_INVALID, "features or norm is NULL");
+    if (!workspace || workspace_bytes < norm_ws_bytes(n))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", norm_ws_bytes(n), workspace_bytes);
+    return launch_feature_norm(features, n, norm, workspace, stream);
+}
+
+cagra_status cagra_sample_rows(const float *features, const float *targets, int64_t n, uint64_t seed, int64_t draw,
+                               int32_t batch, float *features_out, float *targets_out, hipStream_t stream) {
+    if (n < 1 || batch < 0 || draw < 0) return fail(CAGRA_E_INVALID, "n must be >= 1, batch and draw >= 0");
+    if (batch > 0 && (!features || !targets || !features_out || !targets_out))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (batch == 0) return CAGRA_OK;
+    return launch_sample_rows(features, targets, n, seed, draw, batch, features_out, targets_out, stream);
+}
+
+size_t cagra_learned_start_workspace_bytes(const cagra_segments *seg) {
+    if (!seg || seg->V < 1) return 0;
+    return learned_start_ws_bytes(seg);
+}
+
+cagra_status cagra_learned_start(const cagra_graph *g, const cagra_segments *seg, const uint16_t *weights,
+                                 const float *norm, float *rank0, double *scalars_out, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream) {
+    cagra_status s;
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (!weights || !norm || !rank0 || !scalars_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    if (!workspace || workspace_bytes < learned_start_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", learned_start_ws_bytes(seg),
+                    workspace_bytes);
+    return launch_learned_start(g, seg, weights, norm, rank0, scalars_out, workspace, stream);
+}
 
 cagra_status cagra_warm_start_vector(const float *y, int32_t V, float *rank0, double *scalars_out,
                                      void *workspace, size_t workspace_bytes, hipStream_t stream) {

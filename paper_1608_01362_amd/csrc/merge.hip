@@ -267,11 +267,14 @@ constexpr int kEpiBatch = 8;  // vertices per thread whose loads are in flight t
 template <bool BF16OUT, int EPI = kEpiBatch>
 __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32_t V, int64_t vb, int32_t nv,
                                             const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
-                                            const double *__restrict__ scalars_in, double damping,
+                                            const double *__restrict__ scalars_in, double damping, int32_t seed,
                                             float *__restrict__ rank_out, void *__restrict__ contrib_out,
                                             double *__restrict__ blk_out, double am, double *red) {
     const double dd = damping;
-    const double base = (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V;
+    // teleport and dangling mass: spread over all vertices, or (personalized,
+    // seed >= 0) returned to the seed vertex alone
+    const double base = seed < 0 ? (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V : 0.0;
+    const double sbase = (1.0 - dd) + dd * scalars_in[0];
     double dang = 0.0, res = 0.0, mass = 0.0;
     // EPI vertices per thread per pass, their loads issued together (one memory
     // round trip per pass, not per vertex); sums keep the vertex order
@@ -290,7 +293,7 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
             if (i >= nv) break;
             const int64_t v = vb + i;
             const double sum = (double)(long long)acc[i] * kFixInv;
-            const float r = (float)(base + dd * sum);
+            const float r = (float)((v == seed ? sbase : base) + dd * sum);
             rank_out[v] = r;
             const int32_t od = odv[u];
             const float c = od > 0 ? r / (float)od : 0.0f;
@@ -322,8 +325,9 @@ __device__ __forceinline__ void merge_pr_block(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const float *__restrict__ partial, int32_t V, int32_t k, int32_t B, int b, int32_t j, int32_t S,
     const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in,
-    double damping, float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk_out,
-    unsigned long long *__restrict__ slot, double *__restrict__ item_abs, unsigned char *smem) {
+    double damping, int32_t seed, float *__restrict__ rank_out, void *__restrict__ contrib_out,
+    double *__restrict__ blk_out, unsigned long long *__restrict__ slot, double *__restrict__ item_abs,
+    unsigned char *smem) {
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
     int32_t *ofs = reinterpret_cast<int32_t *>(smem + align_up((size_t)B * 8, 16));
     int32_t *pre = ofs + k;
@@ -347,8 +351,8 @@ __device__ __forceinline__ void merge_pr_block(
         if (threadIdx.x == 0) *item_abs = tot;
         return;
     }
-    pr_epilogue<BF16OUT, EPI>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out, blk_out,
-                              (double)am, red);
+    pr_epilogue<BF16OUT, EPI>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, seed, rank_out, contrib_out,
+                              blk_out, (double)am, red);
 }
 
 // Slot of item j of a split block b whose first item is items_b: 2*(items_b - b)
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     const uint16_t *__restrict__ row_dst_lo, const int32_t *__restrict__ block_ptr,
     const int32_t *__restrict__ block_items, const float *__restrict__ partial, int32_t V, int32_t k, int32_t B,
     int32_t nb, const float *__restrict__ rank_in, const int32_t *__restrict__ outdeg,
-    const double *__restrict__ scalars_in, double damping, float *__restrict__ rank_out,
+    const double *__restrict__ scalars_in, double damping, int32_t seed, float *__restrict__ rank_out,
     void *__restrict__ contrib_out, double *__restrict__ blk, unsigned long long *__restrict__ slots,
     double *__restrict__ item_abs, int32_t one_item) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr(
     unsigned long long *slot = S > 1 ? slots + split_slot(block_items[b], b, j) * B : nullptr;
     double *ia = S > 1 ? item_abs + block_items[b] + j : nullptr;
     merge_pr_block<BF16OUT, WIDE>(row_dst_lo, block_ptr, partial, V, k, B, b, j, S, rank_in, outdeg, scalars_in,
-                                  damping, rank_out, contrib_out, blk + (int64_t)b * 4, slot, ia, smem);
+                                  damping, seed, rank_out, contrib_out, blk + (int64_t)b * 4, slot, ia, smem);
 }
 
 // Sum of the item slots of each split block, written into its first slot.
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(kSlotThreads) void k_slot_sum(const int32_t *__rest
 template <bool BF16OUT>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     const int32_t *__restrict__ block_items, int32_t V, int32_t B, int32_t nb, const float *__restrict__ rank_in,
-    const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping,
+    const int32_t *__restrict__ outdeg, const double *__restrict__ scalars_in, double damping, int32_t seed,
     float *__restrict__ rank_out, void *__restrict__ contrib_out, double *__restrict__ blk,
     const unsigned long long *__restrict__ slots, const double *__restrict__ item_abs, int32_t max_items) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -447,7 +451,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_pr_finish(
     if (threadIdx.x == 0)
         for (int32_t it = block_items[b]; it < block_items[b + 1]; ++it) am += item_abs[it];
     __syncthreads();
-    pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, rank_out, contrib_out,
+    pr_epilogue<BF16OUT>(acc, V, vb, nv, rank_in, outdeg, scalars_in, damping, seed, rank_out, contrib_out,
                          blk + (int64_t)b * 4, am, red);
 }
 
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_multi_merge(const MultiDesc *
         // (two workgroups per CU)
         merge_pr_block<false, false, 1>(d.row_dst_lo, d.block_ptr, d.partial, d.V, d.k, d.B,
                                         (int)(gb - d.block_base), 0, 1, d.rank[parity], d.out_degree,
-                                        d.scalars[parity], damping, d.rank[1 - parity], d.contrib[1 - parity],
+                                        d.scalars[parity], damping, -1, d.rank[1 - parity], d.contrib[1 - parity],
                                         blk + gb * 4, nullptr, nullptr, smem);
     }
 }
@@ -739,7 +743,7 @@ cagra_status launch_pr_init(const cagra_graph *g, int32_t contrib_type, const fl
 }
 
 template <bool BF16OUT, bool WIDE>
-static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments *seg, double damping,
+static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t seed,
                                       const float *rank_in, const double *scalars_in, const float *partial,
                                       float *rank_out, void *contrib_out, double *scalars_out, void *ws,
                                       hipStream_t st) {
@@ -752,7 +756,7 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
                                                                        ws_item_bytes(seg));
     k_merge_pr<BF16OUT, WIDE><<<seg->max_items, kMergeThreads, merge_fused_lds_bytes(seg->B, seg->k, 8), st>>>(
         seg->row_dst_lo, seg->block_ptr, seg->block_items, partial, seg->V, seg->k, seg->B, seg->nb, rank_in,
-        g->out_degree, scalars_in, damping, rank_out, contrib_out, blk, slots, item_abs,
+        g->out_degree, scalars_in, damping, seed, rank_out, contrib_out, blk, slots, item_abs,
         seg->max_items == seg->nb ? 1 : 0);
     CAGRA_LAUNCH_CHECK();
     // max_items is a bound on the item count; when it equals nb (a caller that
@@ -764,7 +768,7 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
             seg->block_items, seg->V, seg->B, seg->nb, seg->max_items, parts, slots);
         CAGRA_LAUNCH_CHECK();
         k_merge_pr_finish<BF16OUT><<<seg->nb, kMergeThreads, (size_t)seg->B * 8, st>>>(
-            seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, rank_out,
+            seg->block_items, seg->V, seg->B, seg->nb, rank_in, g->out_degree, scalars_in, damping, seed, rank_out,
             contrib_out, blk, slots, item_abs, seg->max_items);
         CAGRA_LAUNCH_CHECK();
     }
@@ -773,19 +777,20 @@ static cagra_status launch_merge_pr_t(const cagra_graph *g, const cagra_segments
     return CAGRA_OK;
 }
 
-cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t contrib_type,
+cagra_status launch_merge_pr(const cagra_graph *g, const cagra_segments *seg, double damping, int32_t seed,
+                             int32_t contrib_type,
                              const float *rank_in, const double *scalars_in, const float *partial, float *rank_out,
                              void *contrib_out, double *scalars_out, void *ws, hipStream_t st) {
     // mean entries per (subgraph, block) range below one 64-entry step: wide walk
     const bool wide = seg->Q < (int64_t)kWave * seg->k * seg->nb;
     if (contrib_type == CAGRA_BF16)
-        return wide ? launch_merge_pr_t<true, true>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+        return wide ? launch_merge_pr_t<true, true>(g, seg, damping, seed, rank_in, scalars_in, partial, rank_out,
                                                     contrib_out, scalars_out, ws, st)
-                    : launch_merge_pr_t<true, false>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+                    : launch_merge_pr_t<true, false>(g, seg, damping, seed, rank_in, scalars_in, partial, rank_out,
                                                      contrib_out, scalars_out, ws, st);
-    return wide ? launch_merge_pr_t<false, true>(g, seg, damping, rank_in, scalars_in, partial, rank_out, contrib_out,
+    return wide ? launch_merge_pr_t<false, true>(g, seg, damping, seed, rank_in, scalars_in, partial, rank_out, contrib_out,
                                                  scalars_out, ws, st)
-                : launch_merge_pr_t<false, false>(g, seg, damping, rank_in, scalars_in, partial, rank_out,
+                : launch_merge_pr_t<false, false>(g, seg, damping, seed, rank_in, scalars_in, partial, rank_out,
                                                   contrib_out, scalars_out, ws, st);
 }
 

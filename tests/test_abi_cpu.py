@@ -97,7 +97,7 @@ def test_calls_reject_unbuilt_segments(cagra):
     assert L.cagra_merge(ctypes.byref(s), 0, 1, 1, None) == -1
     assert L.cagra_labelprop_iter(ctypes.byref(s), 1, 1, 1, 1, 1, 1 << 20, None) == -1
     g = _graph(cagra)
-    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, -1, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
                                  None) == -1
     assert L.cagra_pagerank_init(ctypes.byref(g), 5, 1, 1, 1, 1, 1 << 20, None) == -1
     assert L.cagra_pagerank_init(ctypes.byref(g), 0, 1, 1, 1, 1, 0, None) == -4
@@ -125,13 +125,13 @@ def test_validation_of_built_segments(cagra):
     # fused merge LDS: 8*B + 8*(k+1) + 64 bytes; B = 16384 with k = 4096 does not fit
     s = _fake_built(cagra, B=16384, V=32768, N=8)
     g = _graph(cagra, V=32768, E=50)
-    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, -1, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 20,
                                  None) == -3
     assert L.cagra_iter_workspace_bytes(ctypes.byref(s)) > 0
     # workspace too small is reported before any launch
     s = _fake_built(cagra)
     g = _graph(cagra, V=100, E=50)
-    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, 0, 1, 1, 1, 1, 1, 1, 1, 1, 8, None) == -4
+    assert L.cagra_pagerank_iter(ctypes.byref(g), ctypes.byref(s), 0.85, -1, 0, 1, 1, 1, 1, 1, 1, 1, 1, 8, None) == -4
 
 
 def test_edge_word_bytes(cagra):
@@ -246,8 +246,8 @@ def test_pagerank_solve_validation(cagra):
 
     def P(**kw):
         d = dict(ok, **kw)
-        return cagra.CPrParams(d["damping"], d["tol"], d["switch_tol"], d["max_iters"], d["check_every"],
-                               d["contrib_type"])
+        return cagra.CPrParams(d["damping"], d["tol"], d["switch_tol"], d.get("restart", -1), d["max_iters"],
+                               d["check_every"], d["contrib_type"])
     assert call(None) == cagra.E_INVALID
     assert call(P(), result=None) == cagra.E_INVALID
     assert call(P(tol=0.0)) == cagra.E_INVALID
@@ -258,6 +258,8 @@ def test_pagerank_solve_validation(cagra):
     assert call(P(switch_tol=-1.0, contrib_type=cagra.BF16)) == cagra.E_INVALID
     assert call(P(damping=2.0)) == cagra.E_INVALID
     assert call(P(contrib_type=7)) == cagra.E_INVALID
+    assert call(P(restart=-2)) == cagra.E_INVALID
+    assert call(P(restart=100)) == cagra.E_INVALID                # outside [-1, V)
     assert call(P(), r1=1) == cagra.E_INVALID                   # rank pair aliased
     assert call(P(), c1=3) == cagra.E_INVALID                   # contribution pair aliased
     assert call(P(), sc=None) == cagra.E_INVALID

@@ -23,3 +23,17 @@ def test_lowest_id_sources_valid_csc():
             want = want[want != v][:d]
             assert np.array_equal(r, want)
             assert d == 0 or r.max() <= maxdeg
+
+
+def test_byte_models():
+    """The method's algorithmic bytes per iteration (its per-subgraph CSR:
+    sources, row pointers, 4-byte destinations, block index, vertex arrays)
+    total E*we + 16Q + 4k(nb+1) + V(12 + 2wc) plus the last row pointer; the
+    bytes this layout moves drop the row pointers and halve the destinations."""
+    import bench
+    V, E, Q, k, nb = 33554432, 1047207919, 575669056, 1024, 4096
+    for wc, we in ((4, 2), (2, 2), (4, 4)):
+        cg, cm = bench.csr_byte_model(V, E, Q, k, nb, wc, we)
+        assert cg + cm == E * we + 16 * Q + 4 * k * (nb + 1) + V * (12 + 2 * wc) + 4
+        g, m = bench.byte_model(V, E, Q, k, nb, wc, we)
+        assert (cg - g, cm - m) == (4 * (Q + 1), 2 * Q)

@@ -56,6 +56,36 @@ def test_bf16_contributions_round_to_nearest_even(cagra):
                               for i in bad[:8, 0].tolist()]
 
 
+def test_bf16_conversion_exhaustive(cagra):
+    """Every one of the 2^32 FP32 bit patterns through the BF16 contribution
+    path (rank / 1), in chunks, against torch's round-to-nearest-even: equal
+    bits for every non-NaN pattern (denormals and both zeros included), and a
+    NaN for every NaN pattern (payloads are not compared)."""
+    import torch
+    chunk = 1 << 26
+    V = chunk
+    od = torch.ones(V, dtype=torch.int32, device="cuda")
+    off = torch.zeros(V + 1, dtype=torch.int32, device="cuda")
+    g = SimpleNamespace(c=cagra.CGraph(V, 0, off.data_ptr(), off.data_ptr(), od.data_ptr()))
+    contrib = torch.empty(V, dtype=torch.int16, device="cuda")
+    scal = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ws = torch.empty(32 * ((V + 16383) // 16384) + 256, dtype=torch.uint8, device="cuda")
+    for c0 in range(0, 1 << 32, chunk):
+        bits = torch.arange(c0, c0 + chunk, dtype=torch.int64, device="cuda")
+        bits = torch.where(bits >= (1 << 31), bits - (1 << 32), bits).to(torch.int32)
+        x = bits.view(torch.float32)
+        cagra.pagerank_init(g, cagra.BF16, x, contrib, scal, ws)
+        want = x.to(torch.bfloat16).view(torch.int16)
+        nan_in = torch.isnan(x)
+        got_nan = ((contrib & 0x7F80) == 0x7F80) & ((contrib & 0x7F) != 0)
+        bad = ((contrib != want) & ~nan_in) | (nan_in & ~got_nan)
+        n_bad = int(bad.sum().item())
+        if n_bad:
+            i = int(bad.nonzero()[0, 0].item())
+            raise AssertionError(f"{n_bad} mismatches in chunk {c0:#x}; first pattern {(c0 + i) & 0xFFFFFFFF:#010x}: "
+                                 f"got {int(contrib[i].item()) & 0xFFFF:#06x} want {int(want[i].item()) & 0xFFFF:#06x}")
+
+
 def test_pagerank_resume_from_saved_vector(cagra):
     """Ten iterations, a host copy of the rank vector, a fresh state started
     from it and ten more iterations give the uninterrupted twenty-iteration
