@@ -396,6 +396,26 @@ cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg
                                  hipStream_t stream);
 
 /*
+ * cagra_pagerank_iter without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The iteration's scratch (per-block FP64
+ * partial sums, split-block slots) lives in a static device array of
+ * CAGRA_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; the call
+ * allocates nothing. Iterations whose workspace (cagra_iter_workspace_bytes)
+ * exceeds that size are rejected with CAGRA_E_CAPACITY before any launch.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other threads) race and must not be issued. Same
+ * arguments otherwise, same kernels, bit-identical results.
+ */
+#define CAGRA_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t cagra_noalloc_scratch_bytes(void);
+cagra_status cagra_pagerank_iter_noalloc(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                         int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
+                                         const void *contrib_in, const double *scalars_in, float *partial,
+                                         float *rank_out, void *contrib_out, double *scalars_out,
+                                         hipStream_t stream);
+
+/*
  * The merge half of cagra_pagerank_iter on its own: cache-aware merge of an
  * already gathered partial[Q] (Section 3.3) followed by the vertex update
  * (Section 4 VertexMap). cagra_pagerank_iter == cagra_segment_gather(SUM_F32,

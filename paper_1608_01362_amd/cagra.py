@@ -52,7 +52,8 @@ EXPORTS = [
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
     "cagra_validate_workspace_bytes", "cagra_validate_graph",
-    "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
+    "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_noalloc_scratch_bytes", "cagra_pagerank_iter_noalloc",
+    "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
     "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
@@ -144,6 +145,9 @@ def lib():
             "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_vp, _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_noalloc_scratch_bytes": ([], _c_size),
+            "cagra_pagerank_iter_noalloc": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                             _c_vp, _c_vp, st], ctypes.c_int),
             "cagra_pagerank_solve": ([GP, SP, ctypes.POINTER(CPrParams), _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_vp, _c_size, ctypes.POINTER(CPrResult), st], ctypes.c_int),
             "cagra_push_workspace_bytes": ([SP], _c_size),
@@ -375,6 +379,15 @@ def pagerank_iter(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: 
                                      _ptr(rank_in), _ptr(contrib_in), _ptr(scalars_in), _ptr(partial),
                                      _ptr(rank_out), _ptr(contrib_out), _ptr(scalars_out), _ptr(workspace),
                                      workspace.numel(), _stream(stream)), "cagra_pagerank_iter")
+
+
+def pagerank_iter_noalloc(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, contrib_in,
+                          scalars_in, partial, rank_out, contrib_out, scalars_out, stream=None, restart: int = -1):
+    """cagra_pagerank_iter with the library's static scratch instead of a workspace."""
+    _check(lib().cagra_pagerank_iter_noalloc(ctypes.byref(dg.c), ctypes.byref(seg.c), damping, restart, contrib_type,
+                                             _ptr(rank_in), _ptr(contrib_in), _ptr(scalars_in), _ptr(partial),
+                                             _ptr(rank_out), _ptr(contrib_out), _ptr(scalars_out), _stream(stream)),
+           "cagra_pagerank_iter_noalloc")
 
 
 def pagerank_merge(dg: DeviceGraph, seg: Segments, damping: float, contrib_type: int, rank_in, scalars_in,

@@ -357,8 +357,8 @@ cagra_status cagra_pagerank_init(const cagra_graph *g, int32_t contrib_type, con
     return launch_pr_init(g, contrib_type, rank, contrib_out, scalars_out, workspace, stream);
 }
 
-static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *seg, double damping,
-                                   int32_t contrib_type, size_t workspace_bytes, const void *workspace) {
+static cagra_status check_pagerank_core(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                        int32_t contrib_type) {
     cagra_status s;
     if ((s = check_graph(g, true)) != CAGRA_OK) return s;
     if ((s = check_built(seg)) != CAGRA_OK) return s;
@@ -368,6 +368,13 @@ static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *s
         return fail(CAGRA_E_INVALID, "contrib_type must be CAGRA_F32 or CAGRA_BF16");
     if (merge_fused_lds_total(seg->B, seg->k, 8) > CAGRA_LDS_BYTES)
         return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    return CAGRA_OK;
+}
+
+static cagra_status check_pagerank(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                   int32_t contrib_type, size_t workspace_bytes, const void *workspace) {
+    cagra_status s;
+    if ((s = check_pagerank_core(g, seg, damping, contrib_type)) != CAGRA_OK) return s;
     if (!workspace || workspace_bytes < iter_ws_bytes(seg))
         return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg),
                     workspace_bytes);
@@ -393,17 +400,36 @@ cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *se
                            contrib_out, scalars_out, workspace, stream);
 }
 
+}  // extern "C"
+
+namespace cagra {
+// Arguments of one PageRank iteration apart from its workspace.
+cagra_status check_pagerank_args(const cagra_graph *g, const cagra_segments *seg, double damping,
+                                 int32_t restart_vertex, int32_t contrib_type, const void *rank_in,
+                                 const void *contrib_in, const void *scalars_in, const void *partial,
+                                 const void *rank_out, const void *contrib_out, const void *scalars_out) {
+    cagra_status s;
+    if ((s = check_pagerank_core(g, seg, damping, contrib_type)) != CAGRA_OK) return s;
+    if ((s = check_restart(g, restart_vertex)) != CAGRA_OK) return s;
+    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
+        (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    return CAGRA_OK;
+}
+}  // namespace cagra
+
+extern "C" {
+
 cagra_status cagra_pagerank_iter(const cagra_graph *g, const cagra_segments *seg, double damping,
                                  int32_t restart_vertex, int32_t contrib_type, const float *rank_in,
                                  const void *contrib_in, const double *scalars_in, float *partial, float *rank_out,
                                  void *contrib_out, double *scalars_out, void *workspace, size_t workspace_bytes,
                                  hipStream_t stream) {
     cagra_status s;
+    if ((s = check_pagerank_args(g, seg, damping, restart_vertex, contrib_type, rank_in, contrib_in, scalars_in,
+                                 partial, rank_out, contrib_out, scalars_out)) != CAGRA_OK)
+        return s;
     if ((s = check_pagerank(g, seg, damping, contrib_type, workspace_bytes, workspace)) != CAGRA_OK) return s;
-    if ((s = check_restart(g, restart_vertex)) != CAGRA_OK) return s;
-    if (!rank_in || !contrib_in || !scalars_in || !rank_out || !contrib_out || !scalars_out ||
-        (seg->Q > 0 && !partial))
-        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if ((s = launch_gather(seg, CAGRA_SUM_F32, contrib_type, contrib_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_pr(g, seg, damping, restart_vertex, contrib_type, rank_in, scalars_in, partial, rank_out,
                            contrib_out, scalars_out, workspace, stream);
