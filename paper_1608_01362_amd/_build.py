@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcagra.so")
 SOURCES = ["api.hip", "builder.hip", "gather.hip", "merge.hip", "ppr.hip", "multi.hip", "warmstart.hip", "cluster.hip",
-           "cf.hip", "bc.hip", "push.hip", "validate.hip", "noalloc.hip"]
+           "cf.hip", "bc.hip", "push.hip", "validate.hip", "noalloc.hip", "segsort.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

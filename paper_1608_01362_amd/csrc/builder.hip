@@ -10,9 +10,9 @@
 //      "sortByDestination" per subgraph), carrying each run's destination and
 //      length, and stable-sorts the edges by the segment of their source,
 //      carrying the finished edge word (local index + row-start flag): both
-//      are device radix sorts (rocPRIM), whose block-local ranking keeps the
-//      writes coalesced where a direct scatter of runs and edges writes a few
-//      bytes per cache line,
+//      with the stable digit passes of segsort.hip, whose tile-local ranking in
+//      LDS keeps the writes coalesced where a direct scatter of runs and edges
+//      writes a few bytes per cache line,
 //   3. writes the rows and their offsets from the sorted runs,
 //   4. builds the merge block index (Section 3.3) and the gather tile table.
 // Everything is integer work; the result is unique and bit-identical run to run.
@@ -20,11 +20,14 @@
 
 #include <vector>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "common.h"
 
 namespace cagra {
+
+size_t seg_sort_ws_bytes(int64_t n, int bits, int value_bytes);
+template <typename V>
+cagra_status seg_sort_pairs(const uint16_t *keys_in, const V *vals_in, uint16_t *keys_out, V *vals_out, int64_t n,
+                            int bits, void *ws, size_t ws_bytes, hipStream_t st);
 
 // ------------------------------------------------------------------ scan
 
@@ -160,6 +163,15 @@ static cagra_status scan_i32(const int32_t *in, int32_t *out, int64_t n, bool in
     cagra_status s = scan_i32_rec<Op>(in, out, n, inclusive, ar, st);
     ar.used = mark;
     return s;
+}
+
+size_t scan_add_ws_bytes(int64_t n) { return scan_ws_bytes(n); }
+
+// Exclusive prefix sum of n int32 values (in place allowed), temporaries in ws.
+cagra_status scan_add_exclusive(const int32_t *in, int32_t *out, int64_t n, void *ws, size_t ws_bytes,
+                                hipStream_t st) {
+    Arena ar{(char *)ws, ws_bytes, 0};
+    return scan_i32<ScanAdd>(in, out, n, false, ar, st);
 }
 
 // ------------------------------------------------------------------ builder kernels
@@ -395,22 +407,15 @@ size_t query_workspace_bytes(int32_t V, int64_t E, int32_t N) {
     return a.used + 256;
 }
 
-// Temporary storage of the two radix sorts (size queries only, no launches).
+// Temporary storage of the two stable sorts by segment (sizes only).
 struct SortTemps {
     size_t rows = 0, edges = 0;
 };
 
 static cagra_status sort_temps(int64_t E, int64_t Q, int32_t k, bool w16, SortTemps &t) {
     const int bits = nbits_for(k);
-    hipError_t e = rocprim::radix_sort_pairs(nullptr, t.rows, (uint16_t *)nullptr, (uint16_t *)nullptr,
-                                             (unsigned long long *)nullptr, (unsigned long long *)nullptr,
-                                             (size_t)Q, 0, bits);
-    if (e != hipSuccess) return fail(CAGRA_E_HIP, "run sort size query failed: %s", hipGetErrorString(e));
-    e = w16 ? rocprim::radix_sort_pairs(nullptr, t.edges, (uint16_t *)nullptr, (uint16_t *)nullptr,
-                                        (uint16_t *)nullptr, (uint16_t *)nullptr, (size_t)E, 0, bits)
-            : rocprim::radix_sort_pairs(nullptr, t.edges, (uint16_t *)nullptr, (uint16_t *)nullptr,
-                                        (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)E, 0, bits);
-    if (e != hipSuccess) return fail(CAGRA_E_HIP, "edge sort size query failed: %s", hipGetErrorString(e));
+    t.rows = seg_sort_ws_bytes(Q, bits, (int)sizeof(unsigned long long));
+    t.edges = seg_sort_ws_bytes(E, bits, w16 ? 2 : 4);
     return CAGRA_OK;
 }
 
@@ -562,20 +567,21 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     const int bits = nbits_for(k);
     k_run_kv<<<grid_for(Q, 256), 256, 0, st>>>(run_first, run_seg, run_dst, Q, rkey, rval);
     CAGRA_LAUNCH_CHECK();
-    size_t tb = tmp.rows;
-    CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, rkey, rkey_s, rval, rval_s, (size_t)Q, 0, bits, st));
+    if ((s = seg_sort_pairs<unsigned long long>(rkey, rval, rkey_s, rval_s, Q, bits, stmp, tmp_bytes, st)) !=
+        CAGRA_OK)
+        return s;
     if (w16) {
         k_edge_kv<uint16_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint16_t *)eval);
         CAGRA_LAUNCH_CHECK();
-        tb = tmp.edges;
-        CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, ekey, ekey_s, (uint16_t *)eval,
-                                                  (uint16_t *)seg->edge_src, (size_t)E, 0, bits, st));
+        if ((s = seg_sort_pairs<uint16_t>(ekey, (const uint16_t *)eval, ekey_s, (uint16_t *)seg->edge_src, E, bits,
+                                          stmp, tmp_bytes, st)) != CAGRA_OK)
+            return s;
     } else {
         k_edge_kv<uint32_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint32_t *)eval);
         CAGRA_LAUNCH_CHECK();
-        tb = tmp.edges;
-        CAGRA_HIP_CHECK(rocprim::radix_sort_pairs(stmp, tb, ekey, ekey_s, (uint32_t *)eval,
-                                                  (uint32_t *)seg->edge_src, (size_t)E, 0, bits, st));
+        if ((s = seg_sort_pairs<uint32_t>(ekey, (const uint32_t *)eval, ekey_s, (uint32_t *)seg->edge_src, E, bits,
+                                          stmp, tmp_bytes, st)) != CAGRA_OK)
+            return s;
     }
     k_seg_begin_sorted<<<grid_for(k + 1, 256), 256, 0, st>>>(rkey_s, Q, k, seg->seg_row_begin);
     CAGRA_LAUNCH_CHECK();

@@ -84,8 +84,10 @@ def test_rmat25_twenty_iterations(cagra, rmat25, rmat25_dev):
     r20 = st.rank_now.double().cpu().numpy()
     sc = st.scalars_now.cpu().numpy()
     # one step, vertex by vertex, from the same input vector: sampled vertices plus
-    # the largest in-degree rows; each GPU row sum has at most N terms in FP32 and the
-    # contributions are FP32, so |err| <= (N + 2) * 2^-24 * value
+    # the largest in-degree rows. Per vertex v the GPU rounds each contribution once
+    # (FP32), sums each subgraph row of its in-edges in FP32 (at most indeg(v) - 1
+    # roundings over all rows, the merge is exact) and rounds the result once, so
+    # |err| <= (indeg(v) + 2) * 2^-24 * value
     rng = np.random.default_rng(0)
     indeg = np.diff(rmat25.in_offsets)
     vs = np.concatenate([rng.integers(0, rmat25.V, 4000), np.argsort(indeg)[-64:]]).astype(np.int32)
@@ -93,7 +95,7 @@ def test_rmat25_twenty_iterations(cagra, rmat25, rmat25_dev):
     got = r20[vs]
     rel = np.abs(got - want) / want
     print(f"step spot check: max rel err {rel.max():.3e} over {len(vs)} vertices")
-    assert np.all(rel <= (32768 + 2) * 2.0 ** -24)
+    assert np.all(rel <= (indeg[vs] + 2) * 2.0 ** -24)
     assert abs(sc[2] - 1.0) <= 1e-5 and np.all(r20 > 0)
     # the whole 20-iteration result against the oracle
     ref, res = oracle.pagerank(rmat25, iters=20)

@@ -354,6 +354,13 @@ def test_fused_merge_split_blocks(cagra, name):
         # whose dangling mass is the second step's input
         s0 = float(_host(st.scalars[1])[0])
     assert np.array_equal(ranks[0], ranks[1])
+    # against the oracle's step from the same FP32 input vector, vertex by vertex:
+    # contributions rounded once, FP32 row sums (at most indeg - 1 roundings), an
+    # exact merge and one final rounding give (indeg + 2) * 2^-24 relative
+    r1 = _host(st.rank[1 - st.cur]).astype(np.float64)
+    step = oracle.pagerank_step_at(g, r1, np.arange(g.V, dtype=np.int32))
+    indeg = np.diff(g.in_offsets)
+    assert np.all(np.abs(ranks[0].astype(np.float64) - step) <= (indeg + 2) * 2.0 ** -24 * step)
     ref = oracle.segment(g, N, B)
     exact = [Fraction(0)] * g.V
     scale = 2 ** 56
