@@ -253,21 +253,22 @@ def warmstart(args, log, oracle_star=True):
     r_w, it_w, _, used = runs_w[0]
     ms_u = float(np.median([r[2] for r in runs_u]))
     ms_w = float(np.median([r[2] for r in runs_w]))
-    # the start vector's own cost
-    torch.cuda.synchronize()
-    a, b = _events()
-    a.record()
-    for _ in range(5):
-        ws.learned_start(net, dg, seg, wsp)
-    b.record()
-    torch.cuda.synchronize()
-    start_ms = a.elapsed_time(b) / 5
+    # the start vector's own cost, and its parts
+    start_ms = _time(lambda: ws.learned_start(net, dg, seg, wsp), 5)
+    F = ws.features(dg, seg)
+    feat_ms = _time(lambda: ws.features(dg, seg), 5)
+    y = net.forward(F)
+    fwd_all_ms = _time(lambda: net.forward(F), 5)
+    unfused_ms = _time(lambda: ws.start_vector(net, ws.features(dg, seg)), 5)
+    del F, y
     l1 = float((r_u.double() - r_w.double()).abs().sum().item())
     out = {"metric": "time to L1 residual < 1e-6, learned warm start vs uniform, held-out R-MAT-24",
            "value": round(ms_w, 3), "unit": "ms", "higher_is_better": False,
            "uniform": {"iterations": it_u, "ms": round(ms_u, 3)},
            "learned": {"iterations": it_w, "ms": round(ms_w, 3), "start_used": used,
-                       "start_vector_ms": round(start_ms, 3)},
+                       "start_vector_ms": round(start_ms, 3),
+                       "parts_ms": {"features": round(feat_ms, 3), "network_every_row": round(fwd_all_ms, 3),
+                                    "unfused_start": round(unfused_ms, 3)}},
            "speedup": round(ms_u / ms_w, 3), "l1_between_answers": l1,
            "training": {"graphs": 200, "rows": rows, "steps": 600, "batch": 65536, "seconds": round(train_s, 2),
                         "loss_first": net.losses[0], "loss_last": net.losses[-1]},

@@ -66,19 +66,35 @@ __device__ __forceinline__ int32_t row_of_edge(const int32_t *__restrict__ off, 
     return lo;
 }
 
-// Edge keys (new destination, new source); each thread takes kEdgesPerThread
-// consecutive edges, finds the first one's row by binary search and walks on.
-__global__ void k_cl_edge_keys(const int32_t *__restrict__ in_offsets, const int32_t *__restrict__ in_sources,
-                               int32_t V, int64_t E, const int32_t *__restrict__ inv, int bits,
-                               unsigned long long *__restrict__ keys) {
-    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kEdgesPerThread;
-    if (e0 >= E) return;
-    const int64_t e1 = e0 + kEdgesPerThread < E ? e0 + kEdgesPerThread : E;
-    int32_t r = row_of_edge(in_offsets, V, e0);
-    for (int64_t e = e0; e < e1; ++e) {
-        while ((int64_t)in_offsets[r + 1] <= e) ++r;
-        keys[e] = ((unsigned long long)(uint32_t)inv[r] << bits) | (unsigned long long)(uint32_t)inv[in_sources[e]];
+// Edge keys (new destination, new source) for a tile of kKeyThreads *
+// kEdgesPerThread consecutive edges: the tile's sources are staged in LDS with
+// coalesced loads, each thread takes kEdgesPerThread consecutive edges (the
+// first one's row by binary search, then walking the offsets), and the keys
+// leave through LDS with coalesced stores.
+constexpr int kKeyThreads = 256;
+constexpr int kKeyTile = kKeyThreads * kEdgesPerThread;
+
+__global__ __launch_bounds__(kKeyThreads) void k_cl_edge_keys(const int32_t *__restrict__ in_offsets,
+                                                              const int32_t *__restrict__ in_sources, int32_t V,
+                                                              int64_t E, const int32_t *__restrict__ inv, int bits,
+                                                              unsigned long long *__restrict__ keys) {
+    __shared__ int32_t src[kKeyTile];
+    __shared__ unsigned long long key[kKeyTile];
+    const int64_t base = (int64_t)blockIdx.x * kKeyTile;
+    const int n = (int)(E - base < kKeyTile ? E - base : kKeyTile);
+    for (int i = threadIdx.x; i < n; i += kKeyThreads) src[i] = in_sources[base + i];
+    __syncthreads();
+    const int i0 = threadIdx.x * kEdgesPerThread;
+    if (i0 < n) {
+        const int i1 = i0 + kEdgesPerThread < n ? i0 + kEdgesPerThread : n;
+        int32_t r = row_of_edge(in_offsets, V, base + i0);
+        for (int i = i0; i < i1; ++i) {
+            while ((int64_t)in_offsets[r + 1] <= base + i) ++r;
+            key[i] = ((unsigned long long)(uint32_t)inv[r] << bits) | (unsigned long long)(uint32_t)inv[src[i]];
+        }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kKeyThreads) keys[base + i] = key[i];
 }
 
 __global__ void k_cl_sources(const unsigned long long *__restrict__ keys, int64_t E, unsigned long long mask,
@@ -175,8 +191,8 @@ cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offs
     if (E == 0) return CAGRA_OK;
     // 3. relabel edges: one sort by (new destination, new source)
     const int bits = id_bits(V);
-    k_cl_edge_keys<<<grid_of(ceil_div(E, kEdgesPerThread), 256), 256, 0, st>>>(g->in_offsets, g->in_sources, V, E,
-                                                                               inv, bits, ekeys);
+    k_cl_edge_keys<<<grid_of(E, kKeyTile), kKeyThreads, 0, st>>>(g->in_offsets, g->in_sources, V, E, inv, bits,
+                                                                 ekeys);
     CAGRA_LAUNCH_CHECK();
     b = t.esort;
     CAGRA_HIP_CHECK(rocprim::radix_sort_keys(tmp, b, ekeys, ekeys_sorted, (size_t)E, 0, 2 * bits, st));

@@ -581,34 +581,101 @@ __global__ void k_memo_feats(float *__restrict__ f) {
     f[od * 3 + 2] = 0.0f;
 }
 
-// y[v] from the memo for vertices without in-edges and out-degree below
-// kMemoDeg; every other vertex is appended to rows (one atomic per wave).
-__global__ __launch_bounds__(256) void k_memo_split(const int32_t *__restrict__ off,
-                                                    const int32_t *__restrict__ outdeg, int32_t V,
-                                                    const float *__restrict__ ymemo, float *__restrict__ y,
-                                                    int32_t *__restrict__ rows, int32_t *__restrict__ count) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool net = false;
-    if (v < V) {
-        const int32_t od = outdeg[v];
-        if (off[v + 1] == off[v] && od < kMemoDeg) y[v] = ymemo[od];
-        else net = true;
-    }
-    const uint64_t m = __ballot(net);
-    int32_t base = 0;
-    if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(count, (int32_t)__popcll(m));
-    base = __shfl(base, 0, 64);
-    if (net) rows[base + (int32_t)__popcll(m & lanemask_lt())] = (int32_t)v;
+// The vertices are split in spans of kSplitSpan: a span's vertices without
+// in-edges (and out-degree below kMemoDeg) take y from the memo, the others
+// are listed in ascending order for the network (count, scan, list: no
+// contended atomics, and the list is the same on every run).
+constexpr int kSplitThreads = 256;
+constexpr int kSplitItems = 16;
+constexpr int kSplitSpan = kSplitThreads * kSplitItems;
+
+__device__ __forceinline__ bool needs_network(const int32_t *__restrict__ off, const int32_t *__restrict__ outdeg,
+                                              int64_t v) {
+    return !(off[v + 1] == off[v] && outdeg[v] < kMemoDeg);
 }
 
-__global__ void k_zero_i32(int32_t *__restrict__ p, int32_t n) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+__global__ __launch_bounds__(kSplitThreads) void k_memo_split_count(const int32_t *__restrict__ off,
+                                                                    const int32_t *__restrict__ outdeg, int32_t V,
+                                                                    const float *__restrict__ ymemo,
+                                                                    float *__restrict__ y,
+                                                                    int32_t *__restrict__ span_count) {
+    __shared__ int32_t wsum[kSplitThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSplitSpan;
+    int32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kSplitItems; ++j) {
+        const int64_t v = base + j * kSplitThreads + threadIdx.x;
+        if (v < V) {
+            if (needs_network(off, outdeg, v)) ++c;
+            else y[v] = ymemo[outdeg[v]];
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_down(c, d, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int i = 0; i < kSplitThreads / 64; ++i) t += wsum[i];
+        span_count[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of n span counts in place (one workgroup); total[0] = the sum.
+__global__ __launch_bounds__(1024) void k_scan_spans(int32_t *__restrict__ a, int32_t n, int32_t *__restrict__ total) {
+    __shared__ int32_t wsum[16];
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    int32_t s = 0;
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) s += a[lo + i];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t incl = s;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int32_t pre = incl - s;
+    for (int i = 0; i < w; ++i) pre += wsum[i];
+    for (int i = 0; i < per; ++i)
+        if (lo + i < n) {
+            const int32_t x = a[lo + i];
+            a[lo + i] = pre;
+            pre += x;
+        }
+    if (threadIdx.x == 1023) total[0] = pre;
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_memo_split_rows(const int32_t *__restrict__ off,
+                                                                   const int32_t *__restrict__ outdeg, int32_t V,
+                                                                   const int32_t *__restrict__ span_ofs,
+                                                                   int32_t *__restrict__ rows) {
+    __shared__ int32_t wc[kSplitThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSplitSpan;
+    int32_t run = span_ofs[blockIdx.x];
+    for (int j = 0; j < kSplitItems; ++j) {
+        const int64_t v = base + j * kSplitThreads + threadIdx.x;
+        const bool net = v < V && needs_network(off, outdeg, v);
+        const uint64_t m = __ballot(net);
+        if (lane == 0) wc[w] = (int32_t)__popcll(m);
+        __syncthreads();
+        int32_t pos = run + (int32_t)__popcll(m & lanemask_lt());
+        int32_t all = 0;
+        for (int i = 0; i < kSplitThreads / 64; ++i) {
+            if (i < w) pos += wc[i];
+            all += wc[i];
+        }
+        if (net) rows[pos] = (int32_t)v;
+        run += all;
+        __syncthreads();  // wc is rewritten by the next step
+    }
 }
 
 struct StartWs {
     float *feats, *y, *memo_f, *memo_y;
-    int32_t *rows, *count;
+    int32_t *rows, *count, *spans;
     void *feat_ws, *soft_ws;
 };
 
@@ -633,6 +700,8 @@ static size_t start_layout(const cagra_segments *seg, char *base, StartWs *w) {
     if (w) w->rows = (int32_t *)p;
     p = take(256);
     if (w) w->count = (int32_t *)p;
+    p = take((size_t)ceil_div(V, kSplitSpan) * 4);
+    if (w) w->spans = (int32_t *)p;
     p = take(features_ws_bytes(seg));
     if (w) w->feat_ws = p;
     p = take(softmax_ws_bytes(seg->V));
@@ -654,10 +723,12 @@ cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *se
     k_mlp_forward<<<forward_grid(kMemoDeg), kFwdThreads, 0, st>>>(w.memo_f, kMemoDeg, wb, norm, w.memo_y, nullptr,
                                                                  nullptr);
     CAGRA_LAUNCH_CHECK();
-    k_zero_i32<<<1, 64, 0, st>>>(w.count, 1);
+    const int32_t nspans = (int32_t)ceil_div(V, kSplitSpan);
+    k_memo_split_count<<<nspans, kSplitThreads, 0, st>>>(g->in_offsets, g->out_degree, V, w.memo_y, w.y, w.spans);
     CAGRA_LAUNCH_CHECK();
-    k_memo_split<<<(unsigned)ceil_div(V, 256), 256, 0, st>>>(g->in_offsets, g->out_degree, V, w.memo_y, w.y, w.rows,
-                                                            w.count);
+    k_scan_spans<<<1, 1024, 0, st>>>(w.spans, nspans, w.count);
+    CAGRA_LAUNCH_CHECK();
+    k_memo_split_rows<<<nspans, kSplitThreads, 0, st>>>(g->in_offsets, g->out_degree, V, w.spans, w.rows);
     CAGRA_LAUNCH_CHECK();
     k_mlp_forward<<<forward_grid(V), kFwdThreads, 0, st>>>(w.feats, V, wb, norm, w.y, w.rows, w.count);
     CAGRA_LAUNCH_CHECK();

@@ -373,3 +373,15 @@ def test_fused_merge_split_blocks(cagra, name):
     want = np.array([base + d * float(Fraction(int(e)) / scale) for e in exact], dtype=np.float64)
     got = ranks[0].astype(np.float64)
     assert np.all(np.abs(got - want) <= np.spacing(np.float32(want)).astype(np.float64) * 1.01)
+
+
+@pytest.mark.parametrize("N", [1, 3, 7])
+def test_builder_bit_exact_many_segments(cagra, N):
+    """Up to the 32,768-segment limit (keys of 15 bits: three stable digit passes
+    in the segment-major reorder), ragged last segment."""
+    from layout_check import check_layout_vectorized
+    g = graphgen.rmat_graph(15, 8, 6)
+    assert -(-g.V // N) <= 32768
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, N, 512, 4096)
+    check_layout_vectorized(cagra, g, seg, oracle.segment(g, N, 512))
