@@ -1,25 +1,32 @@
 // Frequency-based clustering (Section 5) and relabelling, before segmenting.
 //
 // 1. Vertex keys: out-degree where it is strictly above the average degree
-//    E / V, else 0. A stable radix sort of (key, id) pairs in descending key
-//    order gives the new order: clustered vertices by out-degree from high to
-//    low (ties keep the original order), then every other vertex in its
-//    original order.
+//    E / V, else 0, stored bit-inverted so that a stable ascending radix sort
+//    of (key, id) pairs gives the new order: clustered vertices by out-degree
+//    from high to low (ties keep the original order), then every other vertex
+//    in its original order.
 // 2. inv[perm[i]] = i; new out-degrees and in-degrees follow perm; a scan of
 //    the in-degrees gives the new row offsets.
 // 3. Every edge u -> v becomes the key (inv[v] << b) | inv[u] (b bits per id);
 //    one radix sort of these keys lays the edges out row by row with sources
 //    ascending, and the low bits are the new source ids.
 //
-// The sorts and the scan are rocPRIM's device primitives; clustering runs once
-// per graph, off the iteration's hot path.
+// The sorts are the stable radix passes of segsort.hip and the scan the
+// builder's; clustering runs once per graph, off the iteration's hot path.
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "common.h"
 
 namespace cagra {
+
+struct NoValue;
+template <typename K, typename V>
+cagra_status radix_sort_stable(const K *keys_in, const V *vals_in, K *keys_out, V *vals_out, int64_t n, int bits,
+                               void *ws, size_t ws_bytes, hipStream_t st);
+size_t sort_ws_bytes(int64_t n, int bits, int key_bytes, int value_bytes);
+cagra_status scan_add_exclusive(const int32_t *in, int32_t *out, int64_t n, void *ws, size_t ws_bytes,
+                                hipStream_t st);
+size_t scan_add_ws_bytes(int64_t n);
 
 constexpr int kEdgesPerThread = 16;
 
@@ -28,7 +35,7 @@ __global__ void k_cl_vertex_keys(const int32_t *__restrict__ outdeg, int32_t V, 
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     const int64_t od = outdeg[v];
-    key[v] = od * (int64_t)V > E ? (uint32_t)od : 0u;
+    key[v] = ~(od * (int64_t)V > E ? (uint32_t)od : 0u);
     id[v] = (int32_t)v;
 }
 
@@ -49,9 +56,10 @@ __global__ void k_cl_relabel(const int32_t *__restrict__ perm, const uint32_t *_
     cnt[i] = in_offsets[old + 1] - in_offsets[old];
     if (hot) {
         // exactly one writer: the last clustered vertex, or vertex 0 when there is none
-        const bool last_hot = key_sorted[i] > 0 && (i + 1 == V || key_sorted[i + 1] == 0);
+        // keys are stored bit-inverted: a clustered vertex has ~key > 0
+        const bool last_hot = ~key_sorted[i] > 0u && (i + 1 == V || ~key_sorted[i + 1] == 0u);
         if (last_hot) *hot = (int32_t)(i + 1);
-        if (i == 0 && key_sorted[0] == 0) *hot = 0;
+        if (i == 0 && ~key_sorted[0] == 0u) *hot = 0;
     }
 }
 
@@ -111,24 +119,16 @@ static int id_bits(int32_t V) {
 
 static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// rocPRIM temporary-storage sizes (no launches with a null storage pointer).
+// Temporary-storage sizes of the two sorts and the scan.
 struct ClusterTemps {
     size_t vsort = 0, scan = 0, esort = 0;
 };
 
 static cagra_status cluster_temps(int32_t V, int64_t E, ClusterTemps &t) {
     const int bits = id_bits(V);
-    hipError_t e = rocprim::radix_sort_pairs_desc(nullptr, t.vsort, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                  (int32_t *)nullptr, (int32_t *)nullptr, (size_t)V, 0, 32);
-    if (e != hipSuccess) return fail(CAGRA_E_HIP, "vertex sort size query failed: %s", hipGetErrorString(e));
-    e = rocprim::exclusive_scan(nullptr, t.scan, (int32_t *)nullptr, (int32_t *)nullptr, 0, (size_t)V + 1,
-                                rocprim::plus<int32_t>());
-    if (e != hipSuccess) return fail(CAGRA_E_HIP, "scan size query failed: %s", hipGetErrorString(e));
-    if (E > 0) {
-        e = rocprim::radix_sort_keys(nullptr, t.esort, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
-                                     (size_t)E, 0, 2 * bits);
-        if (e != hipSuccess) return fail(CAGRA_E_HIP, "edge sort size query failed: %s", hipGetErrorString(e));
-    }
+    t.vsort = sort_ws_bytes(V, 32, 4, 4);
+    t.scan = scan_add_ws_bytes((int64_t)V + 1);
+    t.esort = E > 0 ? sort_ws_bytes(E, 2 * bits, 8, 0) : 0;
     return CAGRA_OK;
 }
 
@@ -179,23 +179,23 @@ cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offs
     // 1. new vertex order
     k_cl_vertex_keys<<<grid_of(V, 256), 256, 0, st>>>(g->out_degree, V, E, key, id);
     CAGRA_LAUNCH_CHECK();
-    size_t b = t.vsort;
-    CAGRA_HIP_CHECK(rocprim::radix_sort_pairs_desc(tmp, b, key, key_sorted, id, perm, (size_t)V, 0, 32, st));
+    cagra_status s;
+    if ((s = radix_sort_stable<uint32_t, int32_t>(key, id, key_sorted, perm, V, 32, tmp, tmp_bytes, st)) != CAGRA_OK)
+        return s;
     // 2. relabel vertices, new row offsets
     k_cl_relabel<<<grid_of((int64_t)V + 1, 256), 256, 0, st>>>(perm, key_sorted, g->in_offsets, g->out_degree, V,
                                                                 inv, outdeg_new, cnt, hot);
     CAGRA_LAUNCH_CHECK();
-    b = t.scan;
-    CAGRA_HIP_CHECK(rocprim::exclusive_scan(tmp, b, cnt, in_offsets_new, 0, (size_t)V + 1,
-                                            rocprim::plus<int32_t>(), st));
+    if ((s = scan_add_exclusive(cnt, in_offsets_new, (int64_t)V + 1, tmp, tmp_bytes, st)) != CAGRA_OK) return s;
     if (E == 0) return CAGRA_OK;
     // 3. relabel edges: one sort by (new destination, new source)
     const int bits = id_bits(V);
     k_cl_edge_keys<<<grid_of(E, kKeyTile), kKeyThreads, 0, st>>>(g->in_offsets, g->in_sources, V, E, inv, bits,
                                                                  ekeys);
     CAGRA_LAUNCH_CHECK();
-    b = t.esort;
-    CAGRA_HIP_CHECK(rocprim::radix_sort_keys(tmp, b, ekeys, ekeys_sorted, (size_t)E, 0, 2 * bits, st));
+    if ((s = radix_sort_stable<unsigned long long, NoValue>(ekeys, nullptr, ekeys_sorted, nullptr, E, 2 * bits, tmp,
+                                                             tmp_bytes, st)) != CAGRA_OK)
+        return s;
     k_cl_sources<<<grid_of(E, 256), 256, 0, st>>>(ekeys_sorted, E, (1ull << bits) - 1ull, in_sources_new);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;

@@ -1,7 +1,9 @@
-// Stable reorder of (key, value) pairs by a small key (a segment id, below
-// 2^16): the segment-major step of the Section 3.1 preprocessing, where the
-// rows and the edges, produced in destination order, are regrouped by the
-// segment of their sources while keeping destination order inside a segment.
+// Stable reorder of (key, value) pairs by an unsigned key: the segment-major
+// step of the Section 3.1 preprocessing, where the rows and the edges,
+// produced in destination order, are regrouped by the segment of their
+// sources while keeping destination order inside a segment (16-bit keys), and
+// the vertex order and edge relabelling of the Section 5 clustering (32- and
+// 64-bit keys, the latter without values).
 //
 // Least-significant-digit radix passes over digits of at most 6 bits. One
 // pass: every tile of kSortTile pairs counts its digits (k_sort_count), one
@@ -11,9 +13,14 @@
 // its wave; per-wave digit counts order the waves) and writes each digit's run
 // of the tile contiguously. The passes are stable, so the last one leaves the
 // pairs ordered by key and, for equal keys, in input order.
+#include <type_traits>
+
 #include "common.h"
 
 namespace cagra {
+
+// Value type of a sort of keys alone.
+struct NoValue {};
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
@@ -30,7 +37,8 @@ size_t scan_add_ws_bytes(int64_t n);
 static int sort_passes(int bits) { return bits <= 0 ? 0 : (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
 
 // Digit counts of one tile, digit-major: counts[d * ntiles + tile].
-__global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint16_t *__restrict__ keys, int64_t n, int shift,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(const K *__restrict__ keys, int64_t n, int shift,
                                                              int dbits, int32_t ntiles, int32_t *__restrict__ counts) {
     __shared__ int32_t h[kMaxDigits];
     const int ndig = 1 << dbits, mask = ndig - 1;
@@ -40,7 +48,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint16_t *__r
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         const int64_t i = base + j * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
+        if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & (K)mask)], 1);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < ndig; d += kSortThreads) counts[(int64_t)d * ntiles + blockIdx.x] = h[d];
@@ -49,14 +57,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint16_t *__r
 // One stable pass: pair i of the tile (i = j * kSortThreads + thread) goes to
 // offsets[digit * ntiles + tile] + (its rank among the tile's pairs with that
 // digit, in input order).
-template <typename V>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint16_t *__restrict__ kin,
-                                                               const V *__restrict__ vin, int64_t n, int shift,
-                                                               int dbits, int32_t ntiles,
+template <typename K, typename V>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ kin, const V *__restrict__ vin,
+                                                               int64_t n, int shift, int dbits, int32_t ntiles,
                                                                const int32_t *__restrict__ offsets,
-                                                               uint16_t *__restrict__ kout, V *__restrict__ vout) {
-    __shared__ uint16_t sk[kSortTile];
-    __shared__ V sv[kSortTile];
+                                                               K *__restrict__ kout, V *__restrict__ vout) {
+    constexpr bool kVals = !std::is_same<V, NoValue>::value;
+    using VS = typename std::conditional<kVals, V, char>::type;  // stored value type
+    __shared__ K sk[kSortTile];
+    __shared__ VS sv[kVals ? kSortTile : 1];
     __shared__ int32_t run[kMaxDigits];                 // next local slot of each digit
     __shared__ int32_t lofs[kMaxDigits];                // first local slot of each digit
     __shared__ int32_t gofs[kMaxDigits];                // output offset of this tile's run of each digit
@@ -66,16 +75,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint16_t *_
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int cnt = (int)(n - base < kSortTile ? n - base : kSortTile);
 
-    uint16_t key[kSortItems];
-    V val[kSortItems];
+    K key[kSortItems];
+    VS val[kSortItems];
     int dig[kSortItems];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         const int p = j * kSortThreads + tid;
         const bool ok = p < cnt;
-        key[j] = ok ? kin[base + p] : (uint16_t)0;
-        val[j] = ok ? vin[base + p] : (V)0;
-        dig[j] = ok ? (key[j] >> shift) & mask : ndig;  // ndig: no pair
+        key[j] = ok ? kin[base + p] : (K)0;
+        if constexpr (kVals) val[j] = ok ? vin[base + p] : (V)0;
+        dig[j] = ok ? (int)((key[j] >> shift) & (K)mask) : ndig;  // ndig: no pair
     }
     for (int d = tid; d < ndig; d += kSortThreads) run[d] = 0;
     __syncthreads();
@@ -115,7 +124,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint16_t *_
             int32_t pos = run[d] + lrank;
             for (int x = 0; x < w; ++x) pos += wcnt[par][x][d];
             sk[pos] = key[j];
-            sv[pos] = val[j];
+            if constexpr (kVals) sv[pos] = val[j];
         }
         __syncthreads();
         if (tid < ndig) {
@@ -128,69 +137,81 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint16_t *_
     }
     __syncthreads();
     for (int p = tid; p < cnt; p += kSortThreads) {
-        const uint16_t kk = sk[p];
-        const int d = (kk >> shift) & mask;
+        const K kk = sk[p];
+        const int d = (int)((kk >> shift) & (K)mask);
         const int64_t g = (int64_t)gofs[d] + (p - lofs[d]);
         kout[g] = kk;
-        vout[g] = sv[p];
+        if constexpr (kVals) vout[g] = sv[p];
     }
 }
 
-size_t seg_sort_ws_bytes(int64_t n, int bits, int value_bytes) {
+size_t sort_ws_bytes(int64_t n, int bits, int key_bytes, int value_bytes) {
     const int passes = sort_passes(bits);
     if (passes == 0 || n <= 0) return 256;
     const int dbits = (bits + passes - 1) / passes;
     const int64_t ntiles = ceil_div(n, kSortTile);
     const int64_t ncounts = ((int64_t)1 << dbits) * ntiles;
     ArenaSize a;
-    a.take<uint16_t>(n);                   // keys between passes
+    a.take<char>(n * (int64_t)key_bytes);    // keys between passes
     a.take<char>(n * (int64_t)value_bytes);  // values between passes
-    a.take<int32_t>(ncounts);              // digit counts, then offsets
+    a.take<int32_t>(ncounts);                // digit counts, then offsets
     return a.used + scan_add_ws_bytes(ncounts) + 512;
 }
 
-// Stable sort of n pairs by key (keys < 2^bits, bits <= 16). keys_in/vals_in
-// are read (not modified); keys_out/vals_out receive the sorted pairs and must
-// not alias the inputs.
-template <typename V>
-cagra_status seg_sort_pairs(const uint16_t *keys_in, const V *vals_in, uint16_t *keys_out, V *vals_out, int64_t n,
-                            int bits, void *ws, size_t ws_bytes, hipStream_t st) {
+size_t seg_sort_ws_bytes(int64_t n, int bits, int value_bytes) { return sort_ws_bytes(n, bits, 2, value_bytes); }
+
+// Stable sort of n (key, value) pairs by key (keys < 2^bits, bits up to the key
+// width); V = NoValue sorts keys alone. keys_in/vals_in are read (not
+// modified); keys_out/vals_out receive the sorted pairs and must not alias the
+// inputs.
+template <typename K, typename V>
+cagra_status radix_sort_stable(const K *keys_in, const V *vals_in, K *keys_out, V *vals_out, int64_t n, int bits,
+                               void *ws, size_t ws_bytes, hipStream_t st) {
+    constexpr bool kVals = !std::is_same<V, NoValue>::value;
+    constexpr int kValBytes = kVals ? (int)sizeof(V) : 0;
     if (n <= 0) return CAGRA_OK;
     if (bits < 1) bits = 1;
-    if (bits > 16) return fail(CAGRA_E_CAPACITY, "sort keys wider than 16 bits");
+    if (bits > (int)(8 * sizeof(K))) return fail(CAGRA_E_CAPACITY, "sort keys wider than the key type");
     const int passes = sort_passes(bits);
     const int dbits = (bits + passes - 1) / passes;
-    if (ws_bytes < seg_sort_ws_bytes(n, bits, (int)sizeof(V)))
-        return fail(CAGRA_E_BUFFER, "builder workspace too small (sort temporaries)");
+    if (ws_bytes < sort_ws_bytes(n, bits, (int)sizeof(K), kValBytes))
+        return fail(CAGRA_E_BUFFER, "workspace too small (sort temporaries)");
     const int64_t ntiles64 = ceil_div(n, kSortTile);
     if (ntiles64 * ((int64_t)1 << dbits) > INT32_MAX) return fail(CAGRA_E_OVERFLOW, "sort too large");
     const int32_t ntiles = (int32_t)ntiles64;
     Arena ar{(char *)ws, ws_bytes, 0};
-    uint16_t *ktmp = ar.take<uint16_t>(n);
-    V *vtmp = reinterpret_cast<V *>(ar.take<char>(n * (int64_t)sizeof(V)));
+    K *ktmp = reinterpret_cast<K *>(ar.take<char>(n * (int64_t)sizeof(K)));
+    V *vtmp = kVals ? reinterpret_cast<V *>(ar.take<char>(n * (int64_t)kValBytes)) : nullptr;
     int32_t *counts = ar.take<int32_t>(((int64_t)1 << dbits) * ntiles);
     char *scan_ws = ar.base + align_up(ar.used, 256);
     const size_t scan_bytes = ws_bytes - align_up(ar.used, 256);
-    const uint16_t *ks = keys_in;
+    const K *ks = keys_in;
     const V *vs = vals_in;
     for (int p = 0; p < passes; ++p) {
         // the last pass writes the output; earlier ones alternate between the
         // temporaries and the output
         const bool to_out = ((passes - 1 - p) & 1) == 0;
-        uint16_t *kd = to_out ? keys_out : ktmp;
+        K *kd = to_out ? keys_out : ktmp;
         V *vd = to_out ? vals_out : vtmp;
         const int shift = p * dbits;
-        k_sort_count<<<ntiles, kSortThreads, 0, st>>>(ks, n, shift, dbits, ntiles, counts);
+        k_sort_count<K><<<ntiles, kSortThreads, 0, st>>>(ks, n, shift, dbits, ntiles, counts);
         CAGRA_LAUNCH_CHECK();
         if (cagra_status s = scan_add_exclusive(counts, counts, ((int64_t)1 << dbits) * ntiles, scan_ws, scan_bytes,
                                                 st))
             return s;
-        k_sort_scatter<V><<<ntiles, kSortThreads, 0, st>>>(ks, vs, n, shift, dbits, ntiles, counts, kd, vd);
+        k_sort_scatter<K, V><<<ntiles, kSortThreads, 0, st>>>(ks, vs, n, shift, dbits, ntiles, counts, kd, vd);
         CAGRA_LAUNCH_CHECK();
         ks = kd;
         vs = vd;
     }
     return CAGRA_OK;
+}
+
+template <typename V>
+cagra_status seg_sort_pairs(const uint16_t *keys_in, const V *vals_in, uint16_t *keys_out, V *vals_out, int64_t n,
+                            int bits, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (bits > 16) return fail(CAGRA_E_CAPACITY, "sort keys wider than 16 bits");
+    return radix_sort_stable<uint16_t, V>(keys_in, vals_in, keys_out, vals_out, n, bits, ws, ws_bytes, st);
 }
 
 template cagra_status seg_sort_pairs<uint16_t>(const uint16_t *, const uint16_t *, uint16_t *, uint16_t *, int64_t,
@@ -200,5 +221,10 @@ template cagra_status seg_sort_pairs<uint32_t>(const uint16_t *, const uint32_t 
 template cagra_status seg_sort_pairs<unsigned long long>(const uint16_t *, const unsigned long long *, uint16_t *,
                                                          unsigned long long *, int64_t, int, void *, size_t,
                                                          hipStream_t);
+template cagra_status radix_sort_stable<uint32_t, int32_t>(const uint32_t *, const int32_t *, uint32_t *, int32_t *,
+                                                           int64_t, int, void *, size_t, hipStream_t);
+template cagra_status radix_sort_stable<unsigned long long, NoValue>(const unsigned long long *, const NoValue *,
+                                                                     unsigned long long *, NoValue *, int64_t, int,
+                                                                     void *, size_t, hipStream_t);
 
 }  // namespace cagra

@@ -46,3 +46,12 @@ def test_pool_keeps_staged_candidates_when_cache_gathers_move_fewer_bytes():
     assert all(c.N != 8192 for c in pool)  # 1.64x the best staged bytes: pruned
     only_unstaged = autotune.select_pool(cands[:2], 1.6, 4)
     assert [c.N for c in only_unstaged] == [1 << 25, 1 << 24]
+
+
+def test_batched_and_multi_candidates():
+    c = autotune.ppr_candidates(1 << 22)
+    assert {n for n, _, _ in c} == {1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22}
+    assert all(b <= 512 for _, b, _ in c)  # the batched merge keeps B x 64 floats in LDS
+    assert autotune.size_class(1 << 13) == 0 and autotune.size_class(1 << 14) == 1
+    assert autotune.size_class(1 << 17) == 1 and autotune.size_class(1 << 18) == 2
+    assert all(n <= cagra.EDGE16_MAX_N for n, _, _ in autotune.multi_candidates())
