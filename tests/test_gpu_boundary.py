@@ -145,3 +145,24 @@ def test_bf16_finishing_switch_reaches_the_fixed_point(cagra, cfg1):
     assert 0 < fin.iters_bf16 < fin.iters
     assert l1f <= D / (1 - D) * 1e-6 + 1e-6
     assert l1p <= D * 2.0 ** -9 / (1 - D)
+
+
+@pytest.mark.parametrize("name", ["single_vertex", "no_edges", "two_cycle"])
+def test_solve_on_degenerate_graphs(cagra, name):
+    """Graphs whose answer is known: one vertex (rank 1), isolated vertices
+    (uniform, every vertex dangling), a 2-cycle (uniform); the residual after
+    the first step is 0 (below any tol), so one iteration decides."""
+    if name == "single_vertex":
+        g = graphgen.from_edge_list(1, [])
+    elif name == "no_edges":
+        g = graphgen.from_edge_list(50, [])
+    else:
+        g = graphgen.from_edge_list(2, [(0, 1), (1, 0)])
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 16, 16, 64)
+    r = cagra.pagerank_solve(dg, seg, tol=1e-9, max_iters=5)
+    assert r.converged and r.iters == 1
+    got = r.rank.double().cpu().numpy()
+    assert np.allclose(got, 1.0 / g.V, rtol=1e-6, atol=0)
+    ref, _ = oracle.pagerank(g, iters=1)
+    assert np.abs(got - ref).sum() <= 1e-6
