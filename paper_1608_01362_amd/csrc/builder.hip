@@ -21,13 +21,9 @@
 #include <vector>
 
 #include "common.h"
+#include "radix.h"
 
 namespace cagra {
-
-size_t seg_sort_ws_bytes(int64_t n, int bits, int value_bytes);
-template <typename V>
-cagra_status seg_sort_pairs(const uint16_t *keys_in, const V *vals_in, uint16_t *keys_out, V *vals_out, int64_t n,
-                            int bits, void *ws, size_t ws_bytes, hipStream_t st);
 
 // ------------------------------------------------------------------ scan
 

@@ -9,24 +9,17 @@
 //    the in-degrees gives the new row offsets.
 // 3. Every edge u -> v becomes the key (inv[v] << b) | inv[u] (b bits per id);
 //    one radix sort of these keys lays the edges out row by row with sources
-//    ascending, and the low bits are the new source ids.
+//    ascending, and its last pass writes the low bits, the new source ids.
+//    The kernel that makes the keys also counts the first pass's digits.
 //
 // The sorts are the stable radix passes of segsort.hip and the scan the
 // builder's; clustering runs once per graph, off the iteration's hot path.
 #include <cstring>
 
 #include "common.h"
+#include "radix.h"
 
 namespace cagra {
-
-struct NoValue;
-template <typename K, typename V>
-cagra_status radix_sort_stable(const K *keys_in, const V *vals_in, K *keys_out, V *vals_out, int64_t n, int bits,
-                               void *ws, size_t ws_bytes, hipStream_t st);
-size_t sort_ws_bytes(int64_t n, int bits, int key_bytes, int value_bytes);
-cagra_status scan_add_exclusive(const int32_t *in, int32_t *out, int64_t n, void *ws, size_t ws_bytes,
-                                hipStream_t st);
-size_t scan_add_ws_bytes(int64_t n);
 
 constexpr int kEdgesPerThread = 16;
 
@@ -63,52 +56,114 @@ __global__ void k_cl_relabel(const int32_t *__restrict__ perm, const uint32_t *_
     }
 }
 
-// Last row r with in_offsets[r] <= e (the non-empty row holding edge e).
-__device__ __forceinline__ int32_t row_of_edge(const int32_t *__restrict__ off, int32_t V, int64_t e) {
-    int32_t lo = 0, hi = V;  // off[lo] <= e < off[hi]
-    while (hi - lo > 1) {
-        const int32_t mid = lo + ((hi - lo) >> 1);
-        if ((int64_t)off[mid] <= e) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Edge keys (new destination, new source) for a tile of kKeyThreads *
-// kEdgesPerThread consecutive edges: the tile's sources are staged in LDS with
-// coalesced loads, each thread takes kEdgesPerThread consecutive edges (the
-// first one's row by binary search, then walking the offsets), and the keys
-// leave through LDS with coalesced stores.
+// Edge keys (new destination, new source) for a tile of kKeyTile consecutive
+// edges, edge j * kKeyThreads + thread of the tile in step j (coalesced loads
+// and stores). The tile's first row is found by a cooperative search (every
+// round the workgroup probes kKeyThreads evenly spaced rows, so the interval
+// shrinks by that factor); then the offsets of the rows the tile spans are
+// staged in LDS a window of kOffWin rows at a time, and each edge finds its
+// row by binary search in the window. The tile is also a tile of the sort, so
+// the kernel publishes the counts of the sort's first digit (the low dbits0
+// bits): counts0[d * gridDim.x + tile].
 constexpr int kKeyThreads = 256;
 constexpr int kKeyTile = kKeyThreads * kEdgesPerThread;
+constexpr int kOffWin = 4096;
+constexpr int kMaxDigits0 = 256;
+static_assert(kKeyTile == kRadixTile, "key tiles are the sort's tiles");
 
 __global__ __launch_bounds__(kKeyThreads) void k_cl_edge_keys(const int32_t *__restrict__ in_offsets,
                                                               const int32_t *__restrict__ in_sources, int32_t V,
                                                               int64_t E, const int32_t *__restrict__ inv, int bits,
-                                                              unsigned long long *__restrict__ keys) {
-    __shared__ int32_t src[kKeyTile];
-    __shared__ unsigned long long key[kKeyTile];
-    const int64_t base = (int64_t)blockIdx.x * kKeyTile;
+                                                              int dbits0, unsigned long long *__restrict__ keys,
+                                                              int32_t *__restrict__ counts0) {
+    __shared__ int32_t off[kOffWin + 1];
+    __shared__ int32_t nle[kKeyThreads / 64];
+    __shared__ int32_t h[kMaxDigits0];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ndig = 1 << dbits0;
+    for (int d = tid; d < ndig; d += kKeyThreads) h[d] = 0;  // ordered by the window loop's barriers
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);  // consecutive tiles on one XCD, as in the sort
+    const int64_t base = (int64_t)tile * kKeyTile;
     const int n = (int)(E - base < kKeyTile ? E - base : kKeyTile);
-    for (int i = threadIdx.x; i < n; i += kKeyThreads) src[i] = in_sources[base + i];
-    __syncthreads();
-    const int i0 = threadIdx.x * kEdgesPerThread;
-    if (i0 < n) {
-        const int i1 = i0 + kEdgesPerThread < n ? i0 + kEdgesPerThread : n;
-        int32_t r = row_of_edge(in_offsets, V, base + i0);
-        for (int i = i0; i < i1; ++i) {
-            while ((int64_t)in_offsets[r + 1] <= base + i) ++r;
-            key[i] = ((unsigned long long)(uint32_t)inv[r] << bits) | (unsigned long long)(uint32_t)inv[src[i]];
+    const int64_t last = base + n - 1;
+    // Loads are issued in batches and without branches (lanes past the end
+    // read the tile's last edge), so that their latencies overlap: the
+    // sources now, the offset windows and the new ids further down.
+    int32_t src[kEdgesPerThread];
+#pragma unroll
+    for (int j = 0; j < kEdgesPerThread; ++j) {
+        const int64_t e = base + j * kKeyThreads + tid;
+        src[j] = in_sources[e <= last ? e : last];
+    }
+    // first row: the last r with in_offsets[r] <= base (in_offsets[0] = 0 <= base < E = in_offsets[V])
+    int32_t lo = 0, hi = V;  // in_offsets[lo] <= base < in_offsets[hi]
+    while (hi - lo > 1) {
+        const int32_t m = lo + (int32_t)(((int64_t)(hi - lo) * tid) / kKeyThreads);  // m = lo for thread 0
+        const bool le = (int64_t)in_offsets[m] <= base;
+        const uint64_t bal = __ballot(le);
+        if (lane == 0) nle[w] = (int32_t)__popcll(bal);
+        __syncthreads();
+        int32_t t = -1;
+        for (int x = 0; x < kKeyThreads / 64; ++x) t += nle[x];
+        __syncthreads();
+        // probes are non-decreasing in the thread index, so exactly threads 0..t found in_offsets <= base
+        const int32_t nlo = lo + (int32_t)(((int64_t)(hi - lo) * t) / kKeyThreads);
+        const int32_t nhi = t + 1 < kKeyThreads ? lo + (int32_t)(((int64_t)(hi - lo) * (t + 1)) / kKeyThreads) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    int32_t rw = lo;  // first row of the window
+    int32_t row[kEdgesPerThread] = {};
+    static_assert(kOffWin % kKeyThreads == 0, "window staged in whole rounds");
+    for (;;) {
+        int32_t o[kOffWin / kKeyThreads];
+#pragma unroll
+        for (int k = 0; k < kOffWin / kKeyThreads; ++k) {
+            const int64_t r = (int64_t)rw + k * kKeyThreads + tid;
+            o[k] = in_offsets[r < V ? r : V];
+        }
+        const int64_t rend = (int64_t)rw + kOffWin;
+        const int32_t oend = in_offsets[rend < V ? rend : V];
+#pragma unroll
+        for (int k = 0; k < kOffWin / kKeyThreads; ++k) off[k * kKeyThreads + tid] = o[k];
+        if (tid == 0) off[kOffWin] = oend;
+        __syncthreads();
+        const int64_t wend = off[kOffWin];  // first edge past the window
+#pragma unroll
+        for (int j = 0; j < kEdgesPerThread; ++j) {
+            const int64_t e = base + j * kKeyThreads + tid;
+            if (e <= last && (int64_t)off[0] <= e && e < wend) {
+                int a = 0, b = kOffWin;  // off[a] <= e < off[b]
+                while (b - a > 1) {
+                    const int mid = (a + b) >> 1;
+                    if ((int64_t)off[mid] <= e) a = mid;
+                    else b = mid;
+                }
+                row[j] = rw + a;
+            }
+        }
+        __syncthreads();
+        if (wend > last) break;
+        rw += kOffWin;
+    }
+    // new ids (row[j] stays 0 for lanes past the end)
+    uint32_t nd[kEdgesPerThread], ns[kEdgesPerThread];
+#pragma unroll
+    for (int j = 0; j < kEdgesPerThread; ++j) {
+        nd[j] = (uint32_t)inv[row[j]];
+        ns[j] = (uint32_t)inv[src[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kEdgesPerThread; ++j) {
+        const int64_t e = base + j * kKeyThreads + tid;
+        if (e <= last) {
+            const unsigned long long key = ((unsigned long long)nd[j] << bits) | (unsigned long long)ns[j];
+            keys[e] = key;
+            atomicAdd(&h[(int)(key & (unsigned long long)(ndig - 1))], 1);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kKeyThreads) keys[base + i] = key[i];
-}
-
-__global__ void k_cl_sources(const unsigned long long *__restrict__ keys, int64_t E, unsigned long long mask,
-                             int32_t *__restrict__ in_sources_new) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < E) in_sources_new[e] = (int32_t)(keys[e] & mask);
+    for (int d = tid; d < ndig; d += kKeyThreads) counts0[(int64_t)d * gridDim.x + tile] = h[d];
 }
 
 static int id_bits(int32_t V) {
@@ -122,13 +177,15 @@ static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 // Temporary-storage sizes of the two sorts and the scan.
 struct ClusterTemps {
     size_t vsort = 0, scan = 0, esort = 0;
+    int64_t ncounts0 = 0;  // first-pass digit counts of the edge sort
 };
 
 static cagra_status cluster_temps(int32_t V, int64_t E, ClusterTemps &t) {
     const int bits = id_bits(V);
     t.vsort = sort_ws_bytes(V, 32, 4, 4);
     t.scan = scan_add_ws_bytes((int64_t)V + 1);
-    t.esort = E > 0 ? sort_ws_bytes(E, 2 * bits, 8, 0) : 0;
+    t.esort = E > 0 ? sort_low32_ws_bytes(E, 2 * bits) : 0;
+    t.ncounts0 = E > 0 ? ((int64_t)1 << sort_digit_bits(2 * bits)) * ceil_div(E, kKeyTile) : 0;
     return CAGRA_OK;
 }
 
@@ -140,7 +197,8 @@ static size_t cluster_layout(int32_t V, int64_t E, const ClusterTemps &t) {
     a.take<int32_t>(V);                  // inv
     a.take<int32_t>((int64_t)V + 1);     // cnt
     a.take<unsigned long long>(E);       // edge keys
-    a.take<unsigned long long>(E);       // sorted edge keys
+    a.take<unsigned long long>(E);       // edge keys between sort passes
+    a.take<int32_t>(t.ncounts0);         // first-pass digit counts
     size_t tmp = t.vsort > t.scan ? t.vsort : t.scan;
     if (t.esort > tmp) tmp = t.esort;
     a.take<char>((int64_t)tmp);
@@ -169,11 +227,12 @@ cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offs
     int32_t *inv = ar.take<int32_t>(V);
     int32_t *cnt = ar.take<int32_t>((int64_t)V + 1);
     unsigned long long *ekeys = ar.take<unsigned long long>(E);
-    unsigned long long *ekeys_sorted = ar.take<unsigned long long>(E);
+    unsigned long long *ekeys_tmp = ar.take<unsigned long long>(E);
+    int32_t *counts0 = ar.take<int32_t>(t.ncounts0);
     size_t tmp_bytes = t.vsort > t.scan ? t.vsort : t.scan;
     if (t.esort > tmp_bytes) tmp_bytes = t.esort;
     char *tmp = ar.take<char>((int64_t)tmp_bytes);
-    if (!key || !key_sorted || !id || !inv || !cnt || !ekeys || !ekeys_sorted || !tmp)
+    if (!key || !key_sorted || !id || !inv || !cnt || !tmp || (E > 0 && (!ekeys || !ekeys_tmp || !counts0)))
         return fail(CAGRA_E_BUFFER, "cluster workspace smaller than %zu bytes", need);
 
     // 1. new vertex order
@@ -188,17 +247,15 @@ cagra_status cluster_graph(const cagra_graph *g, int32_t *perm, int32_t *in_offs
     CAGRA_LAUNCH_CHECK();
     if ((s = scan_add_exclusive(cnt, in_offsets_new, (int64_t)V + 1, tmp, tmp_bytes, st)) != CAGRA_OK) return s;
     if (E == 0) return CAGRA_OK;
-    // 3. relabel edges: one sort by (new destination, new source)
+    // 3. relabel edges: one sort by (new destination, new source); its last
+    //    pass writes the new source ids
     const int bits = id_bits(V);
+    const int dbits0 = sort_digit_bits(2 * bits);
+    if (dbits0 > 8) return fail(CAGRA_E_CAPACITY, "first sort digit wider than the key kernel's count table");
     k_cl_edge_keys<<<grid_of(E, kKeyTile), kKeyThreads, 0, st>>>(g->in_offsets, g->in_sources, V, E, inv, bits,
-                                                                 ekeys);
+                                                                 dbits0, ekeys, counts0);
     CAGRA_LAUNCH_CHECK();
-    if ((s = radix_sort_stable<unsigned long long, NoValue>(ekeys, nullptr, ekeys_sorted, nullptr, E, 2 * bits, tmp,
-                                                             tmp_bytes, st)) != CAGRA_OK)
-        return s;
-    k_cl_sources<<<grid_of(E, 256), 256, 0, st>>>(ekeys_sorted, E, (1ull << bits) - 1ull, in_sources_new);
-    CAGRA_LAUNCH_CHECK();
-    return CAGRA_OK;
+    return radix_sort_low32(ekeys, ekeys_tmp, counts0, in_sources_new, E, 2 * bits, bits, tmp, tmp_bytes, st);
 }
 
 }  // namespace cagra
