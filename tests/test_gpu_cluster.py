@@ -1,5 +1,6 @@
 """GPU parity for frequency-based clustering (Section 5): the relabelled graph
-is bit-exact against the oracle, and PageRank on the clustered, segmented graph
+is bit-exact against the oracle, the segmentation of the clustered graph is
+byte-identical to the oracle's, and PageRank on the clustered, segmented graph
 matches the FP64 oracle on the original graph (read through perm)."""
 import json
 import os
@@ -9,6 +10,7 @@ import pytest
 
 import graphgen
 import oracle
+from layout_check import check_layout_vectorized
 from oracle import cluster as oc
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +61,26 @@ def test_cluster_bit_exact(cagra, gi):
 def test_cluster_bit_exact_rmat22(cagra):
     g = graphgen.rmat_graph(22, 16, 2)
     check_bit_exact(cagra, g)
+
+
+@pytest.fixture(scope="module")
+def clustered20(cagra):
+    g = graphgen.rmat_graph(20, 16, 7)
+    dg, out, perm, rg = check_bit_exact(cagra, g)
+    return out, rg
+
+
+@pytest.mark.parametrize("N", [4096, 32768])
+def test_builder_on_clustered_graph_bit_exact(cagra, clustered20, N):
+    """Segmenting the clustered graph: its sources crowd into the first
+    segments, so most steps of the builder's reorder by segment id see one or a
+    few distinct ids. The layout is byte-identical to the oracle's segmentation
+    of the oracle's clustered graph."""
+    out, rg = clustered20
+    seg = cagra.build_segments(out, N, 8192, 262144)
+    ref = oracle.segment(rg, N, 8192)
+    print(f"N={N}: k={seg.k} Q={seg.Q} q={seg.q:.3f}", flush=True)
+    check_layout_vectorized(cagra, rg, seg, ref)
 
 
 @pytest.mark.parametrize("scale,N", [(16, 4096), (20, 32768)])
