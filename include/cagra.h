@@ -591,7 +591,7 @@ cagra_status cagra_degree_features(const cagra_graph *g, const cagra_segments *s
  * [CAGRA_MLP_PARAMS]; norm: float[6] = mean[3], 1/std[3]. GELU with erf from
  * Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7); FP32 arithmetic. The 64 x 64
  * hidden product runs on the matrix cores with the BF16 weights and each FP32
- * activation split into two BF16 parts (hi + lo, within 2^-18 relative),
+ * activation split into two BF16 parts (hi + lo, within 2^-17 relative),
  * accumulated in FP32.
  */
 cagra_status cagra_mlp_forward(const float *features, int64_t n, const uint16_t *weights, const float *norm,

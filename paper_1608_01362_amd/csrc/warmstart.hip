@@ -103,7 +103,7 @@ __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bi
 // z2[4(l/16) + r][16c + l%16] in the accumulators; the output layer is a
 // 16-lane butterfly sum. The weights are BF16 by definition; the FP32
 // activations are not, so each one enters the product as two BF16 operands,
-// hi = bf16(h) and lo = bf16(h - hi) (|h - hi - lo| <= 2^-18 |h|), and both
+// hi = bf16(h) and lo = bf16(h - hi) (|h - hi - lo| <= 2^-17 |h|), and both
 // halves are accumulated: the hidden product keeps FP32-level accuracy for
 // twice the (cheap) matrix instructions.
 // With `rows`, the i-th row processed is rows[i] (features read and output

@@ -24,9 +24,11 @@ def check_layout_vectorized(c, g, seg, ref):
     assert te[0] == 0 and te[nt] == g.E and np.all(np.diff(te) >= 0)
     seg_e = ref.row_ptr[ref.seg_row_begin].astype(np.int64)
     assert np.all(seg_e[ts] <= te[:nt]) and np.all(te[1:] <= seg_e[ts + 1])
+    # tiles start on row starts; an empty tile (an empty last segment) may sit at the end, E = row_ptr[Q]
+    rpe = ref.row_ptr.astype(np.int64)
+    pos = np.searchsorted(rpe, te[:nt])
+    assert np.all(rpe[np.minimum(pos, len(rpe) - 1)] == te[:nt])
     rp = ref.row_ptr[:-1].astype(np.int64)
-    pos = np.searchsorted(rp, te[:nt])
-    assert np.all(rp[np.minimum(pos, len(rp) - 1)] == te[:nt])  # tiles start on row starts
     ln = te[1:] - te[:nt]
     sl = -(-ln // c.TILE_WAVES)
     b = np.minimum(te[:nt, None] + np.arange(c.TILE_WAVES)[None, :] * sl[:, None], te[1:, None])

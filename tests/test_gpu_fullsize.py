@@ -7,7 +7,7 @@
   (N = 32768, B = 8192, tile_edges = 262144): 20 iterations within L1 <= 1e-6 of the
   oracle; one step checked vertex by vertex against the oracle evaluated from the same
   input vector; the residual-threshold run within the contraction bound of the oracle's
-  fixed point; BF16 contributions within d*2^-9/(1-d).
+  fixed point; BF16 contributions within d*2^-8/(1-d).
 """
 import numpy as np
 import pytest
@@ -119,4 +119,4 @@ def test_rmat25_converged_and_bf16(cagra, rmat25, rmat25_dev):
     l1b = float(np.abs(rb.double().cpu().numpy() - ref20).sum())
     rel = np.abs(rb.double().cpu().numpy() - ref20) / ref20
     print(f"bf16 gathers: L1 {l1b:.3e}, max rel {rel.max():.3e}")
-    assert l1b <= D * 2.0 ** -9 / (1 - D)
+    assert l1b <= D * 2.0 ** -8 / (1 - D)

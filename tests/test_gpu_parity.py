@@ -2,7 +2,7 @@
 
 Bars: segment layout and label propagation bit-exact; FP32 PageRank within
 L1 <= 1e-6 of the FP64 oracle after 20 iterations; float gathers/merges within
-FP32 summation bounds; BF16 within the bound d*u/(1-d) (u = 2^-9, the BF16
+FP32 summation bounds; BF16 within the bound d*u/(1-d) (u = 2^-8, the BF16
 unit roundoff) that follows from rounding every contribution once per step.
 """
 import json
@@ -254,7 +254,7 @@ def test_pagerank_bf16_bound(cagra):
     want, _ = oracle.pagerank(g, iters=20)
     l1 = np.abs(_host(r).astype(np.float64) - want).sum()
     print(f"bf16 L1={l1:.3e}")
-    assert l1 <= 0.85 * 2.0 ** -9 / 0.15
+    assert l1 <= 0.85 * 2.0 ** -8 / 0.15
 
 
 @pytest.mark.parametrize("scale,ef,seed,N", [(10, 4, 1, 1), (12, 8, 2, 100), (14, 16, 3, 4096), (14, 4, 6, 1 << 20)])

@@ -34,7 +34,7 @@ def forward_error_bound(p, inter):
     standardization and of every dot product (at most n + 2 roundings for n
     terms), the GELU error of the erf approximation (Abramowitz & Stegun 7.1.26,
     1.5e-7, plus FP32 evaluation: 5e-7 |x| in all), the split of each hidden
-    activation into two BF16 operands (|h - hi - lo| <= 2^-18 |h|), and errors
+    activation into two BF16 operands (|h - hi - lo| <= 2^-17 |h|), and errors
     carried through GELU (|GELU'| <= 1.13) and the next layer's weights."""
     W1, b1, W2, b2, w3, b3 = mlp.unpack(p)
     Z, z1, h1, z2, h2 = inter
@@ -43,7 +43,7 @@ def forward_error_bound(p, inter):
     eg = lambda x: 5e-7 * np.abs(x)  # noqa: E731
     dz1 = 7 * u * (np.abs(Z) @ np.abs(W1).T + np.abs(b1))
     dh1 = gp * dz1 + eg(z1)
-    dz2 = (dh1 + 2.0 ** -18 * np.abs(h1)) @ np.abs(W2).T + 130 * u * (np.abs(h1) @ np.abs(W2).T + np.abs(b2))
+    dz2 = (dh1 + 2.0 ** -17 * np.abs(h1)) @ np.abs(W2).T + 130 * u * (np.abs(h1) @ np.abs(W2).T + np.abs(b2))
     dh2 = gp * dz2 + eg(z2)
     return dh2 @ np.abs(w3) + 66 * u * (np.abs(h2) @ np.abs(w3) + abs(b3)) + 1e-30
 
