@@ -37,17 +37,19 @@ size_t merge_fused_lds_total(int32_t B, int32_t k, int acc_bytes) {
 
 // One wave per block, subgraphs strictly in ascending order. The block's range
 // bounds are staged in LDS first (when they fit), and the entries of the next
-// non-empty subgraph (up to kOrdBatch per range) are loaded while the current
-// one is applied, so the wave does not wait on memory once per subgraph.
+// kOrdDepth - 1 non-empty subgraphs (up to kOrdBatch per range) are in flight
+// while the current one is applied, so the wave does not wait on memory once
+// per subgraph.
 // Entries of one subgraph have distinct destinations, so the lanes of a batch
 // never collide; the order across subgraphs is the program order of the wave.
 constexpr int kOrdLoads = 4;                    // entries per lane per batch
 constexpr int kOrdBatch = kOrdLoads * kWave;    // entries of a range loaded ahead
+constexpr int kOrdDepth = 6;                    // ranges in flight (8 loads each)
 
 template <typename T>
 struct OrdBatch {
     T x[kOrdLoads];
-    int32_t d[kOrdLoads];  // -1: no entry
+    int32_t d[kOrdLoads];  // entries past the range hold the range's first entry again
 };
 
 template <class Op, bool COMP>
@@ -114,34 +116,58 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const uint16_t *__restrict
         }
         return s;
     };
+    // Loads only: nothing here uses their values, so none waits; whether an
+    // entry belongs to the range is decided when it is applied.
     auto issue = [&](int32_t lo, int32_t hi, OrdBatch<T> &q) {
 #pragma unroll
         for (int j = 0; j < kOrdLoads; ++j) {
             const int32_t i = lo + j * kWave + lane;
-            const bool ok = i < hi;
-            const int32_t ii = ok ? i : lo;
+            const int32_t ii = i < hi ? i : lo;
             q.x[j] = partial[ii];
-            const int32_t dd = (int32_t)row_dst_lo[ii];
-            q.d[j] = ok ? dd : -1;
+            q.d[j] = (int32_t)row_dst_lo[ii];
         }
     };
-    int32_t lo, hi, lo2 = 0, hi2 = 0;
-    int32_t s = next(0, lo, hi);
-    OrdBatch<T> cur, nxt;
-    if (s < k) issue(lo, hi, cur);
-    while (s < k) {
-        const int32_t s2 = next(s + 1, lo2, hi2);
-        if (s2 < k) issue(lo2, hi2, nxt);
+    // A ring of kOrdDepth non-empty ranges: the loads of the range kOrdDepth - 1
+    // places ahead are issued before the current one is applied, and ranges
+    // are applied strictly in ascending subgraph order. Every slot issues its
+    // loads (past the last range, of a known entry) so that the waits for one
+    // slot do not cover the slots behind it.
+    int32_t safe_lo = 0, safe_hi = 0;
+    int32_t scan = next(0, safe_lo, safe_hi);  // next subgraph to examine
+    if (scan < k) {  // uniform: the block has entries; safe_lo indexes one of them
+        OrdBatch<T> q[kOrdDepth];
+        int32_t qs[kOrdDepth], qlo[kOrdDepth], qhi[kOrdDepth];
+        auto fetch = [&](OrdBatch<T> &b, int32_t &bs, int32_t &blo, int32_t &bhi) {
+            int32_t l = safe_lo, h = safe_lo;
+            scan = next(scan, l, h);
+            bs = scan;
+            if (scan < k) ++scan;
+            else l = h = safe_lo;
+            blo = l;
+            bhi = h;
+            issue(l, h, b);
+        };
 #pragma unroll
-        for (int j = 0; j < kOrdLoads; ++j)
-            if (cur.d[j] >= 0) ord_apply<Op, COMP>(acc, cmp, cur.d[j], cur.x[j]);
-        // the rest of a long range, still before the next subgraph
-        for (int32_t i = lo + kOrdBatch + lane; i < hi; i += 64) ord_apply<Op, COMP>(acc, cmp, row_dst_lo[i], partial[i]);
-        __builtin_amdgcn_wave_barrier();
-        s = s2;
-        lo = lo2;
-        hi = hi2;
-        cur = nxt;
+        for (int c = 0; c < kOrdDepth - 1; ++c) fetch(q[c], qs[c], qlo[c], qhi[c]);
+        for (bool more = true; more;) {
+#pragma unroll
+            for (int c = 0; c < kOrdDepth; ++c) {
+                constexpr int kLast = kOrdDepth - 1;
+                const int nx = (c + kLast) % kOrdDepth;
+                fetch(q[nx], qs[nx], qlo[nx], qhi[nx]);
+                if (qs[c] >= k) {  // uniform; every later slot is empty too
+                    more = false;
+                    break;
+                }
+#pragma unroll
+                for (int j = 0; j < kOrdLoads; ++j)
+                    if (qlo[c] + j * kWave + lane < qhi[c]) ord_apply<Op, COMP>(acc, cmp, q[c].d[j], q[c].x[j]);
+                // the rest of a long range, still before the next subgraph
+                for (int32_t i = qlo[c] + kOrdBatch + lane; i < qhi[c]; i += 64)
+                    ord_apply<Op, COMP>(acc, cmp, row_dst_lo[i], partial[i]);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
     }
     __builtin_amdgcn_wave_barrier();
     for (int i = lane; i < nv; i += 64) out[vb + i] = COMP ? (T)(acc[i] + cmp[i]) : acc[i];
