@@ -56,11 +56,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *__r
                                                               int32_t *__restrict__ sums) {
     __shared__ int32_t lds[kScanThreads / 64];
     int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // all loads issued before any is used (lanes past the end read the tile's first item)
+    int32_t v[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t j = base + i * kScanThreads + threadIdx.x;
+        v[i] = in[j < n ? j : base];
+    }
     int32_t acc = Op::id();
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         int64_t j = base + i * kScanThreads + threadIdx.x;
-        if (j < n) acc = Op::op(acc, in[j]);
+        acc = Op::op(acc, j < n ? v[i] : Op::id());
     }
     int32_t tot = block_reduce_i32<Op>(acc, lds);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;

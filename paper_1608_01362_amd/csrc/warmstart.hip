@@ -589,9 +589,10 @@ constexpr int kSplitThreads = 256;
 constexpr int kSplitItems = 16;
 constexpr int kSplitSpan = kSplitThreads * kSplitItems;
 
-__device__ __forceinline__ bool needs_network(const int32_t *__restrict__ off, const int32_t *__restrict__ outdeg,
-                                              int64_t v) {
-    return !(off[v + 1] == off[v] && outdeg[v] < kMemoDeg);
+// A vertex goes through the network unless it has no in-edges and an
+// out-degree below kMemoDeg (then the memo holds its output).
+__device__ __forceinline__ bool needs_network(int32_t off_v, int32_t off_next, int32_t outdeg_v) {
+    return !(off_next == off_v && outdeg_v < kMemoDeg);
 }
 
 __global__ __launch_bounds__(kSplitThreads) void k_memo_split_count(const int32_t *__restrict__ off,
@@ -601,13 +602,26 @@ __global__ __launch_bounds__(kSplitThreads) void k_memo_split_count(const int32_
                                                                     int32_t *__restrict__ span_count) {
     __shared__ int32_t wsum[kSplitThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kSplitSpan;
+    // loads issued in one batch (vertices past the end read the span's first)
+    int32_t o0[kSplitItems], o1[kSplitItems], od[kSplitItems];
+#pragma unroll
+    for (int j = 0; j < kSplitItems; ++j) {
+        const int64_t v = base + j * kSplitThreads + threadIdx.x;
+        const int64_t vv = v < V ? v : base;
+        o0[j] = off[vv];
+        o1[j] = off[vv + 1];
+        od[j] = outdeg[vv];
+    }
+    float ym[kSplitItems];
+#pragma unroll
+    for (int j = 0; j < kSplitItems; ++j) ym[j] = ymemo[od[j] < kMemoDeg ? od[j] : 0];
     int32_t c = 0;
 #pragma unroll
     for (int j = 0; j < kSplitItems; ++j) {
         const int64_t v = base + j * kSplitThreads + threadIdx.x;
         if (v < V) {
-            if (needs_network(off, outdeg, v)) ++c;
-            else y[v] = ymemo[outdeg[v]];
+            if (needs_network(o0[j], o1[j], od[j])) ++c;
+            else y[v] = ym[j];
         }
     }
     for (int d = 32; d >= 1; d >>= 1) c += __shfl_down(c, d, 64);
@@ -655,9 +669,18 @@ __global__ __launch_bounds__(kSplitThreads) void k_memo_split_rows(const int32_t
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kSplitSpan;
     int32_t run = span_ofs[blockIdx.x];
+    bool needs[kSplitItems];  // decided for the whole span before the ordered listing
+#pragma unroll
     for (int j = 0; j < kSplitItems; ++j) {
         const int64_t v = base + j * kSplitThreads + threadIdx.x;
-        const bool net = v < V && needs_network(off, outdeg, v);
+        const int64_t vv = v < V ? v : base;
+        const int32_t a = off[vv], b = off[vv + 1], d = outdeg[vv];
+        needs[j] = v < V && needs_network(a, b, d);
+    }
+#pragma unroll
+    for (int j = 0; j < kSplitItems; ++j) {
+        const int64_t v = base + j * kSplitThreads + threadIdx.x;
+        const bool net = needs[j];
         const uint64_t m = __ballot(net);
         if (lane == 0) wc[w] = (int32_t)__popcll(m);
         __syncthreads();
