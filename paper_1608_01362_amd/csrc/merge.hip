@@ -302,8 +302,10 @@ __device__ __forceinline__ void pr_epilogue(const unsigned long long *acc, int32
     const double base = seed < 0 ? (1.0 - dd) / (double)V + dd * scalars_in[0] / (double)V : 0.0;
     const double sbase = (1.0 - dd) + dd * scalars_in[0];
     double dang = 0.0, res = 0.0, mass = 0.0;
-    // EPI vertices per thread per pass, their loads issued together (one memory
-    // round trip per pass, not per vertex); sums keep the vertex order
+    // EPI vertices per thread per pass; sums keep the vertex order. The loads are
+    // conditional, so they go out pair by pair: measured faster than issuing all
+    // of them at once, which crowds the memory queue that the CU's other
+    // workgroup streams its buffer entries through.
     for (int i0 = threadIdx.x; i0 < nv; i0 += kMergeThreads * EPI) {
         float rin[EPI];
         int32_t odv[EPI];
@@ -614,8 +616,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_lp(
     const int b = xcd_remap(blockIdx.x, nb);
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
-    // kEpiBatch labels per thread and pass, loaded together (one memory round
-    // trip per pass) before the accumulators take them
+    // kEpiBatch labels per thread and pass (conditional loads, as in the
+    // PageRank vertex update) before the accumulators take them
     for (int i0 = threadIdx.x; i0 < nv; i0 += kMergeThreads * kEpiBatch) {
         int32_t l[kEpiBatch];
 #pragma unroll

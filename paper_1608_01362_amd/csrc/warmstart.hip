@@ -106,10 +106,11 @@ __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bi
 // hi = bf16(h) and lo = bf16(h - hi) (|h - hi - lo| <= 2^-17 |h|), and both
 // halves are accumulated: the hidden product keeps FP32-level accuracy for
 // twice the (cheap) matrix instructions.
-// With `rows`, the i-th row processed is rows[i] (features read and output
-// written at that row) and the count is n_dev[0] when n_dev is given. Each
+// With kRows, the i-th row processed is rows[i] (features read and output
+// written at that row); the count is n_dev[0] when n_dev is given. Each
 // row's arithmetic does not depend on the other rows of its tile, so a row's
 // output is the same bits whichever rows share its tile.
+template <bool kRows>
 __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__restrict__ feats, int64_t n,
                                                              const uint16_t *__restrict__ wb,
                                                              const float *__restrict__ norm,
@@ -147,13 +148,27 @@ __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__rest
     const int64_t tiles = (n + 15) / 16;
     const int64_t wave = ((int64_t)blockIdx.x * kFwdThreads + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kFwdThreads) >> 6;
+    if (wave >= tiles) return;  // no workgroup-wide synchronization below
+    // The features of the next tile and the row ids of the one after it are
+    // loaded while a tile is computed. Loads past the last row read row n - 1
+    // (their results are not used).
+    // row ids stay 32-bit (and the loads unconditional) until used as addresses
+    auto row_id = [&](int64_t t) -> int32_t {
+        const int64_t ii = t * 16 + jl < n ? t * 16 + jl : n - 1;
+        if constexpr (kRows) return rows[ii];
+        else return (int32_t)ii;
+    };
+    int32_t r_cur = row_id(wave);
+    float f0 = feats[(int64_t)r_cur * 3 + 0], f1 = feats[(int64_t)r_cur * 3 + 1], f2 = feats[(int64_t)r_cur * 3 + 2];
+    int32_t r_nxt = row_id(wave + nwaves);
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
-        const int64_t i = tile * 16 + jl;
-        const bool live = i < n;
-        const int64_t r = live && rows ? (int64_t)rows[i] : i;
-        const float x0 = live ? (feats[r * 3 + 0] - m0) * s0 : 0.0f;
-        const float x1 = live ? (feats[r * 3 + 1] - m1) * s1 : 0.0f;
-        const float x2 = live ? (feats[r * 3 + 2] - m2) * s2 : 0.0f;
+        const float *fn = feats + (int64_t)r_nxt * 3;
+        const float g0 = fn[0], g1 = fn[1], g2 = fn[2];
+        const int32_t r_nn = row_id(tile + 2 * nwaves);
+        const bool live = tile * 16 + jl < n;
+        const float x0 = live ? (f0 - m0) * s0 : 0.0f;
+        const float x1 = live ? (f1 - m1) * s1 : 0.0f;
+        const float x2 = live ? (f2 - m2) * s2 : 0.0f;
         bf16x8 A[2], Alo[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
@@ -181,13 +196,22 @@ __global__ __launch_bounds__(kFwdThreads) void k_mlp_forward(const float *__rest
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int m = 8; m >= 1; m >>= 1) part[q] += __shfl_xor(part[q], m, 16);
+        // row id of output row 4 kq + q: held by the lane of this group with jl = 4 kq + q
+        int32_t dest[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dest[q] = __shfl(r_cur, 16 * kq + 4 * kq + q);
         if (jl == 0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t io = tile * 16 + 4 * kq + q;
-                if (io < n) y[rows ? (int64_t)rows[io] : io] = part[q] + b3;
+                if (io < n) y[(int64_t)dest[q]] = part[q] + b3;
             }
         }
+        f0 = g0;
+        f1 = g1;
+        f2 = g2;
+        r_cur = r_nxt;
+        r_nxt = r_nn;
     }
 }
 
@@ -346,7 +370,7 @@ static unsigned forward_grid(int64_t n) {
 cagra_status launch_mlp_forward(const float *feats, int64_t n, const uint16_t *wb, const float *norm, float *y,
                                 hipStream_t st) {
     if (n == 0) return CAGRA_OK;
-    k_mlp_forward<<<forward_grid(n), kFwdThreads, 0, st>>>(feats, n, wb, norm, y, nullptr, nullptr);
+    k_mlp_forward<false><<<forward_grid(n), kFwdThreads, 0, st>>>(feats, n, wb, norm, y, nullptr, nullptr);
     CAGRA_LAUNCH_CHECK();
     return CAGRA_OK;
 }
@@ -669,14 +693,20 @@ __global__ __launch_bounds__(kSplitThreads) void k_memo_split_rows(const int32_t
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kSplitSpan;
     int32_t run = span_ofs[blockIdx.x];
-    bool needs[kSplitItems];  // decided for the whole span before the ordered listing
+    // the span's loads in one batch, then the decisions, then the ordered listing
+    int32_t o0[kSplitItems], o1[kSplitItems], od[kSplitItems];
 #pragma unroll
     for (int j = 0; j < kSplitItems; ++j) {
         const int64_t v = base + j * kSplitThreads + threadIdx.x;
         const int64_t vv = v < V ? v : base;
-        const int32_t a = off[vv], b = off[vv + 1], d = outdeg[vv];
-        needs[j] = v < V && needs_network(a, b, d);
+        o0[j] = off[vv];
+        o1[j] = off[vv + 1];
+        od[j] = outdeg[vv];
     }
+    bool needs[kSplitItems];
+#pragma unroll
+    for (int j = 0; j < kSplitItems; ++j)
+        needs[j] = base + j * kSplitThreads + threadIdx.x < V && needs_network(o0[j], o1[j], od[j]);
 #pragma unroll
     for (int j = 0; j < kSplitItems; ++j) {
         const int64_t v = base + j * kSplitThreads + threadIdx.x;
@@ -743,7 +773,7 @@ cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *se
     if ((s = launch_features(g, seg, w.feats, w.feat_ws, st)) != CAGRA_OK) return s;
     k_memo_feats<<<(unsigned)ceil_div(kMemoDeg, 256), 256, 0, st>>>(w.memo_f);
     CAGRA_LAUNCH_CHECK();
-    k_mlp_forward<<<forward_grid(kMemoDeg), kFwdThreads, 0, st>>>(w.memo_f, kMemoDeg, wb, norm, w.memo_y, nullptr,
+    k_mlp_forward<false><<<forward_grid(kMemoDeg), kFwdThreads, 0, st>>>(w.memo_f, kMemoDeg, wb, norm, w.memo_y, nullptr,
                                                                  nullptr);
     CAGRA_LAUNCH_CHECK();
     const int32_t nspans = (int32_t)ceil_div(V, kSplitSpan);
@@ -753,7 +783,7 @@ cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *se
     CAGRA_LAUNCH_CHECK();
     k_memo_split_rows<<<nspans, kSplitThreads, 0, st>>>(g->in_offsets, g->out_degree, V, w.spans, w.rows);
     CAGRA_LAUNCH_CHECK();
-    k_mlp_forward<<<forward_grid(V), kFwdThreads, 0, st>>>(w.feats, V, wb, norm, w.y, w.rows, w.count);
+    k_mlp_forward<true><<<forward_grid(V), kFwdThreads, 0, st>>>(w.feats, V, wb, norm, w.y, w.rows, w.count);
     CAGRA_LAUNCH_CHECK();
     if ((s = launch_softmax(w.y, V, rank0, scal, w.soft_ws, st)) != CAGRA_OK) return s;
     return CAGRA_OK;
