@@ -414,63 +414,109 @@ cagra_status launch_adam(float *master, uint16_t *wb, float *m, float *v, const 
 
 // ------------------------------------------------------------------ start vector
 
-constexpr int kSoftSpan = 65536;
+// Spans of kSoftSpan outputs per workgroup, kSoftItems per thread with their
+// loads issued together; the per-span partials are combined by one workgroup
+// in a fixed order (so the start vector is the same bits on every run).
+constexpr int kSoftThreads = 256;
+constexpr int kSoftItems = 16;
+constexpr int kSoftSpan = kSoftThreads * kSoftItems;
 
-__global__ __launch_bounds__(256) void k_soft_max(const float *__restrict__ y, int32_t V, double *__restrict__ blk) {
-    __shared__ double red[4];
-    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan, hi = lo + kSoftSpan < V ? lo + kSoftSpan : V;
+__global__ __launch_bounds__(kSoftThreads) void k_soft_max(const float *__restrict__ y, int32_t V,
+                                                           double *__restrict__ blk) {
+    __shared__ double red[2 * kSoftThreads / 64];
+    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan;
+    float x[kSoftItems];
+#pragma unroll
+    for (int j = 0; j < kSoftItems; ++j) {
+        const int64_t v = lo + j * kSoftThreads + threadIdx.x;
+        x[j] = y[v < V ? v : lo];
+    }
     double mx = -INFINITY, bad = 0.0;
-    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) {
-        const float x = y[v];
-        if (!isfinite(x)) bad += 1.0;
-        else mx = fmax(mx, (double)x);
+#pragma unroll
+    for (int j = 0; j < kSoftItems; ++j) {
+        if (lo + j * kSoftThreads + threadIdx.x >= V) continue;
+        if (!isfinite(x[j])) bad += 1.0;
+        else mx = fmax(mx, (double)x[j]);
     }
     for (int d = 32; d >= 1; d >>= 1) {
         mx = fmax(mx, __shfl_down(mx, d, 64));
         bad += __shfl_down(bad, d, 64);
     }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    double m2 = red[0];
-    for (int i = 1; i < 4; ++i) m2 = fmax(m2, red[i]);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bad;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        blk[blockIdx.x * 2 + 0] = m2;
-        blk[blockIdx.x * 2 + 1] = red[0] + red[1] + red[2] + red[3];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * w] = mx;
+        red[2 * w + 1] = bad;
     }
-}
-
-// scal[0] = max, scal[1] = count of non-finite outputs (fixed order)
-__global__ void k_soft_max_final(const double *__restrict__ blk, int32_t nblk, double *__restrict__ scal) {
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double mx = -INFINITY, bad = 0.0;
-        for (int b = 0; b < nblk; ++b) {
-            mx = fmax(mx, blk[b * 2]);
-            bad += blk[b * 2 + 1];
+        double m2 = red[0], b2 = red[1];
+        for (int i = 1; i < kSoftThreads / 64; ++i) {
+            m2 = fmax(m2, red[2 * i]);
+            b2 += red[2 * i + 1];
         }
-        scal[0] = mx;
-        scal[1] = bad;
+        blk[blockIdx.x * 2 + 0] = m2;
+        blk[blockIdx.x * 2 + 1] = b2;
     }
 }
 
-__global__ __launch_bounds__(256) void k_soft_sum(const float *__restrict__ y, int32_t V,
-                                                  const double *__restrict__ scal, double *__restrict__ blk) {
-    __shared__ double red[4];
-    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan, hi = lo + kSoftSpan < V ? lo + kSoftSpan : V;
+// scal[0] = max, scal[1] = count of non-finite outputs: one workgroup, thread t
+// combining partials t, t + 256, ... in order, then a fixed reduction tree
+__global__ __launch_bounds__(kSoftThreads) void k_soft_max_final(const double *__restrict__ blk, int32_t nblk,
+                                                                 double *__restrict__ scal) {
+    __shared__ double red[2 * kSoftThreads / 64];
+    double mx = -INFINITY, bad = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kSoftThreads) {
+        mx = fmax(mx, blk[b * 2]);
+        bad += blk[b * 2 + 1];
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        mx = fmax(mx, __shfl_down(mx, d, 64));
+        bad += __shfl_down(bad, d, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * w] = mx;
+        red[2 * w + 1] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m2 = red[0], b2 = red[1];
+        for (int i = 1; i < kSoftThreads / 64; ++i) {
+            m2 = fmax(m2, red[2 * i]);
+            b2 += red[2 * i + 1];
+        }
+        scal[0] = m2;
+        scal[1] = b2;
+    }
+}
+
+__global__ __launch_bounds__(kSoftThreads) void k_soft_sum(const float *__restrict__ y, int32_t V,
+                                                           const double *__restrict__ scal, double *__restrict__ blk) {
+    __shared__ double red[kSoftThreads / 64];
+    const int64_t lo = (int64_t)blockIdx.x * kSoftSpan;
     const double mx = scal[0];
+    float x[kSoftItems];
+#pragma unroll
+    for (int j = 0; j < kSoftItems; ++j) {
+        const int64_t v = lo + j * kSoftThreads + threadIdx.x;
+        x[j] = y[v < V ? v : lo];
+    }
     double s = 0.0;
-    for (int64_t v = lo + threadIdx.x; v < hi; v += 256) s += exp((double)y[v] - mx);
-    s = block_sum_f64<256>(s, red);
+#pragma unroll
+    for (int j = 0; j < kSoftItems; ++j)
+        if (lo + j * kSoftThreads + threadIdx.x < V) s += exp((double)x[j] - mx);
+    s = block_sum_f64<kSoftThreads>(s, red);
     if (threadIdx.x == 0) blk[blockIdx.x] = s;
 }
 
-// scal[2] = sum of exp(y - max) over all vertices
-__global__ void k_soft_sum_final(const double *__restrict__ blk, int32_t nblk, double *__restrict__ scal) {
+// scal[2] = sum of exp(y - max) over all vertices (fixed order, as above)
+__global__ __launch_bounds__(kSoftThreads) void k_soft_sum_final(const double *__restrict__ blk, int32_t nblk,
+                                                                 double *__restrict__ scal) {
+    __shared__ double red[kSoftThreads / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kSoftThreads) s += blk[b];
+    s = block_sum_f64<kSoftThreads>(s, red);
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += blk[b];
         scal[2] = s;
         scal[3] = 0.0;
     }
@@ -792,13 +838,13 @@ cagra_status launch_learned_start(const cagra_graph *g, const cagra_segments *se
 cagra_status launch_softmax(const float *y, int32_t V, float *r0, double *scal, void *ws, hipStream_t st) {
     const int32_t nblk = (int32_t)ceil_div(V, kSoftSpan);
     double *blk = (double *)ws;
-    k_soft_max<<<nblk, 256, 0, st>>>(y, V, blk);
+    k_soft_max<<<nblk, kSoftThreads, 0, st>>>(y, V, blk);
     CAGRA_LAUNCH_CHECK();
-    k_soft_max_final<<<1, 64, 0, st>>>(blk, nblk, scal);
+    k_soft_max_final<<<1, kSoftThreads, 0, st>>>(blk, nblk, scal);
     CAGRA_LAUNCH_CHECK();
-    k_soft_sum<<<nblk, 256, 0, st>>>(y, V, scal, blk);
+    k_soft_sum<<<nblk, kSoftThreads, 0, st>>>(y, V, scal, blk);
     CAGRA_LAUNCH_CHECK();
-    k_soft_sum_final<<<1, 64, 0, st>>>(blk, nblk, scal);
+    k_soft_sum_final<<<1, kSoftThreads, 0, st>>>(blk, nblk, scal);
     CAGRA_LAUNCH_CHECK();
     k_soft_write<<<(unsigned)ceil_div(V, 256), 256, 0, st>>>(y, V, scal, r0);
     CAGRA_LAUNCH_CHECK();

@@ -13,7 +13,11 @@ limit, N >= V). Each case checks, against the FP64 oracle:
 - every third case, one personalized step (restart vertex s) from e_s against
   the oracle's personalized PageRank, within the same bound where the answer
   is non-zero and exactly zero elsewhere;
-- one label-propagation step from a random labelling, exactly.
+- one label-propagation step from a random labelling, exactly;
+- the standalone paper-order merge of random buffer values: the FP32 sum
+  bit-identical to an FP32 evaluation in the paper's order (per destination,
+  subgraphs ascending), the compensated sum within one rounding of the exact
+  sum, and the integer minimum exactly.
 """
 import numpy as np
 import pytest
@@ -26,6 +30,17 @@ pytestmark = pytest.mark.gpu
 
 NCASES = 160
 EDGE16 = 32768
+
+
+def fp32_paper_order_merge(ref, partial32):
+    """Section 3.3 merge in FP32, subgraphs ascending; a subgraph holds each
+    destination at most once, so one subgraph is one vector update."""
+    out = np.zeros(ref.V, dtype=np.float32)
+    for s in range(ref.k):
+        lo, hi = ref.seg_row_begin[s], ref.seg_row_begin[s + 1]
+        d = ref.row_dst[lo:hi]
+        out[d] = (out[d] + partial32[lo:hi]).astype(np.float32)
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -122,3 +137,20 @@ def test_random_case(cagra, case):
     want_lab = oracle.segmented_labelprop_step(ref, lab)
     assert np.array_equal(lab_out.cpu().numpy(), want_lab)
     assert int(changed.item()) == int(np.count_nonzero(want_lab != lab))
+
+    # the standalone paper-order merge of random buffer values
+    if seg.Q > 0:
+        p = (rng.random(seg.Q) * np.exp(rng.normal(0, 3, seg.Q))).astype(np.float32)
+        pd = torch.from_numpy(p).cuda()
+        out = torch.empty(g.V, dtype=torch.float32, device="cuda")
+        cagra.merge(seg, cagra.SUM_F32, pd, out)
+        assert np.array_equal(out.cpu().numpy(), fp32_paper_order_merge(ref, p))
+        cagra.merge(seg, cagra.SUM_F32_COMP, pd, out)
+        exact = oracle.merge(ref, p.astype(np.float64), oracle.SUM)
+        assert np.all(np.abs(out.cpu().numpy().astype(np.float64) - exact) <= 2.0 ** -23 * exact * 1.01 + 1e-38)
+        li = rng.integers(-2 ** 31, 2 ** 31 - 1, seg.Q).astype(np.int32)
+        oi = torch.empty(g.V, dtype=torch.int32, device="cuda")
+        cagra.merge(seg, cagra.MIN_I32, torch.from_numpy(li).cuda(), oi)
+        want = oracle.merge(ref, li.astype(np.float64), oracle.MIN)
+        want = np.where(np.isinf(want), 2 ** 31 - 1, want).astype(np.int64)
+        assert np.array_equal(oi.cpu().numpy().astype(np.int64), want)
