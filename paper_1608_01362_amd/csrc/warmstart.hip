@@ -2,7 +2,7 @@
 // 3 -> 64 -> 64 -> 1 GELU network with BF16 weights and FP32 accumulation
 // (forward, backward and Adam, all on the GPU), and the start vector
 // r0 = softmax(y) (the network predicts log(V * r)). The plain iteration from
-// this vector remains the judge of convergence.
+// this vector still decides convergence.
 //
 // Parameter vector (4481 values): W1[64][3], b1[64], W2[64][64] (row j =
 // output j), b2[64], w3[64], b3.
