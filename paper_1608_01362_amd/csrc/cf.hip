@@ -18,6 +18,7 @@ constexpr int kCfK = CAGRA_CF_FACTORS;
 constexpr int kCfWaves = CAGRA_TILE_WAVES;
 constexpr int kCfThreads = kCfWaves * kWave;
 constexpr int kCfBatch = 16;         // source rows loaded ahead per wave
+constexpr int kCfMergeBatch = 8;    // merge rows / vertices per wave whose loads are in flight together
 constexpr int kEdgesPerThread = 16;  // edge-value permutation
 
 static_assert(kCfK == kWave, "one factor per lane");
@@ -201,18 +202,41 @@ __global__ __launch_bounds__(kCfThreads) void k_merge_cf(const int32_t *__restri
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < nv * kCfK; i += kCfThreads) acc[i] = 0.0f;
     __syncthreads();
+    // kCfMergeBatch rows (then vertices) per wave and pass, their loads issued
+    // before any is used (past the range: its first row again, unused); a
+    // subgraph's rows have distinct destinations, and the barrier after each
+    // subgraph keeps the subgraphs in ascending order for every destination
     for (int32_t s = 0; s < k; ++s) {
         const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
-        for (int32_t i = lo + w; i < hi; i += kCfWaves) {
-            const int32_t d = (int32_t)(row_dst[i] - vb);
-            acc[d * kCfK + lane] += partial[(int64_t)i * kCfK + lane];
+        for (int32_t i0 = lo + w; i0 < hi; i0 += kCfWaves * kCfMergeBatch) {
+            int32_t d[kCfMergeBatch];
+            float x[kCfMergeBatch];
+#pragma unroll
+            for (int j = 0; j < kCfMergeBatch; ++j) {
+                const int32_t i = i0 + j * kCfWaves;
+                const int32_t ii = i < hi ? i : lo;
+                d[j] = row_dst[ii];
+                x[j] = partial[(int64_t)ii * kCfK + lane];
+            }
+#pragma unroll
+            for (int j = 0; j < kCfMergeBatch; ++j)
+                if (i0 + j * kCfWaves < hi) acc[(int32_t)(d[j] - vb) * kCfK + lane] += x[j];
         }
         __syncthreads();
     }
-    for (int i = w; i < nv; i += kCfWaves) {
-        const int64_t o = (vb + i) * kCfK + lane;
-        const float x = x_in[o];
-        x_out[o] = x + gamma * (acc[i * kCfK + lane] - lambda * x);
+    for (int i0 = w; i0 < nv; i0 += kCfWaves * kCfMergeBatch) {
+        float xo[kCfMergeBatch];
+#pragma unroll
+        for (int j = 0; j < kCfMergeBatch; ++j) {
+            const int i = i0 + j * kCfWaves;
+            xo[j] = x_in[(vb + (i < nv ? i : 0)) * kCfK + lane];
+        }
+#pragma unroll
+        for (int j = 0; j < kCfMergeBatch; ++j) {
+            const int i = i0 + j * kCfWaves;
+            if (i >= nv) break;
+            x_out[(vb + i) * kCfK + lane] = xo[j] + gamma * (acc[i * kCfK + lane] - lambda * xo[j]);
+        }
     }
 }
 

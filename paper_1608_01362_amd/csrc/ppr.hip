@@ -21,6 +21,7 @@ constexpr int kCols = CAGRA_PPR_COLS;
 constexpr int kPprWaves = CAGRA_TILE_WAVES;
 constexpr int kPprThreads = kPprWaves * kWave;
 constexpr int kBatch = 16;  // source rows loaded ahead per wave
+constexpr int kMergeBatch = 8;  // merge rows / vertices per wave whose loads are in flight together
 
 template <typename W>
 __global__ __launch_bounds__(kPprThreads) void k_gather_cols(const W *__restrict__ edge_src, int64_t E,
@@ -114,11 +115,25 @@ __global__ __launch_bounds__(kPprThreads) void k_merge_ppr(
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < nv * kCols; i += kPprThreads) acc[i] = 0.0f;
     __syncthreads();
+    // kMergeBatch rows per wave and pass, their loads issued before any is
+    // applied (rows past the range re-read its first row, unused); a
+    // subgraph's rows have distinct destinations, and the barrier after each
+    // subgraph keeps the subgraphs in ascending order for every destination
     for (int32_t s = 0; s < k; ++s) {
         const int32_t lo = block_ptr[(int64_t)b * k + s], hi = block_ptr[(int64_t)(b + 1) * k + s];
-        for (int32_t i = lo + w; i < hi; i += kPprWaves) {
-            const int32_t d = (int32_t)(row_dst[i] - vb);
-            acc[d * kCols + lane] += partial[(int64_t)i * kCols + lane];
+        for (int32_t i0 = lo + w; i0 < hi; i0 += kPprWaves * kMergeBatch) {
+            int32_t d[kMergeBatch];
+            float x[kMergeBatch];
+#pragma unroll
+            for (int j = 0; j < kMergeBatch; ++j) {
+                const int32_t i = i0 + j * kPprWaves;
+                const int32_t ii = i < hi ? i : lo;
+                d[j] = row_dst[ii];
+                x[j] = partial[(int64_t)ii * kCols + lane];
+            }
+#pragma unroll
+            for (int j = 0; j < kMergeBatch; ++j)
+                if (i0 + j * kPprWaves < hi) acc[(int32_t)(d[j] - vb) * kCols + lane] += x[j];
         }
         __syncthreads();
     }
@@ -127,17 +142,34 @@ __global__ __launch_bounds__(kPprThreads) void k_merge_ppr(
     const int32_t seed = live ? seeds[lane] : -1;
     const double Dj = live ? scalars_in[lane * 4 + 0] : 0.0;
     double dang = 0.0, res = 0.0, mass = 0.0;
-    for (int i = w; i < nv; i += kPprWaves) {
-        const int64_t v = vb + i;
-        double r = dd * (double)acc[i * kCols + lane];
-        if (v == seed) r += (1.0 - dd) + dd * Dj;
-        const float rf = live ? (float)r : 0.0f;
-        rank_out[v * kCols + lane] = rf;
-        const int32_t od = outdeg[v];
-        contrib_out[v * kCols + lane] = od > 0 ? rf / (float)od : 0.0f;
-        if (od == 0) dang += (double)rf;
-        res += fabs((double)rf - (double)rank_in[v * kCols + lane]);
-        mass += (double)rf;
+    // kMergeBatch vertices per wave and pass, their loads issued together
+    // (vertices past the block re-read its first, unused); the sums keep the
+    // vertex order
+    for (int i0 = w; i0 < nv; i0 += kPprWaves * kMergeBatch) {
+        float rin[kMergeBatch];
+        int32_t odv[kMergeBatch];
+#pragma unroll
+        for (int j = 0; j < kMergeBatch; ++j) {
+            const int i = i0 + j * kPprWaves;
+            const int64_t v = vb + (i < nv ? i : 0);
+            rin[j] = rank_in[v * kCols + lane];
+            odv[j] = outdeg[v];
+        }
+#pragma unroll
+        for (int j = 0; j < kMergeBatch; ++j) {
+            const int i = i0 + j * kPprWaves;
+            if (i >= nv) break;
+            const int64_t v = vb + i;
+            double r = dd * (double)acc[i * kCols + lane];
+            if (v == seed) r += (1.0 - dd) + dd * Dj;
+            const float rf = live ? (float)r : 0.0f;
+            rank_out[v * kCols + lane] = rf;
+            const int32_t od = odv[j];
+            contrib_out[v * kCols + lane] = od > 0 ? rf / (float)od : 0.0f;
+            if (od == 0) dang += (double)rf;
+            res += fabs((double)rf - (double)rin[j]);
+            mass += (double)rf;
+        }
     }
     // per-column partial sums over the waves, in wave order
     double *out = blk + (int64_t)b * kCols * 4;
