@@ -430,9 +430,18 @@ cagra_status cagra_pagerank_merge(const cagra_graph *g, const cagra_segments *se
  * PageRank power iteration to a residual threshold (the Section 4 program's
  * loop of EdgeMap and VertexMap, run until the L1 change falls below tol),
  * driven from the host: cagra_pagerank_init, then cagra_pagerank_iter steps;
- * after every check_every-th step the scalars are read back (the call
- * SYNCHRONIZES the stream there) and the loop stops at the first L1 residual
- * below tol.
+ * after every check_every-th step the scalars are read back and the loop stops
+ * at the first L1 residual below tol. The start vector's scalars are read
+ * synchronously; after that the step following a check is queued before the
+ * host waits for the check's scalars (through pinned host memory), unless the
+ * residual trend predicts that the check may end the loop or switch the
+ * precision. When a check ends the loop or switches, the step queued past it
+ * is dropped: every result (iterate, counts, scalars) is the one a loop that
+ * waited at each check would give; only the other buffer of each pair may hold
+ * the dropped step's values. The call SYNCHRONIZES the stream before it
+ * returns. The read-back uses 4 KiB of pinned host memory and two events per
+ * concurrent solve, allocated on a device's first solve and kept until the
+ * process ends.
  *   rank0, rank1       float[V] pair; rank0 holds the start vector on entry
  *   contrib0, contrib1 contribution pair: float[V] for CAGRA_F32 or when
  *                      switch_tol > 0, uint16[V] for CAGRA_BF16 otherwise
@@ -523,6 +532,39 @@ cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, dou
                             const int32_t *seeds, const float *rank_in, const float *contrib_in,
                             const double *scalars_in, float *partial, float *rank_out, float *contrib_out,
                             double *scalars_out, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Batched personalized PageRank to a residual threshold (the Section 4 loop,
+ * every column at once): cagra_ppr_init from the seeds, then cagra_ppr_iter
+ * steps until every column's L1 residual (scalars [4j+1]) read back after a
+ * check is below tol. The host loop is the one of cagra_pagerank_solve (one
+ * iteration queued past each check; results as if it waited at every check;
+ * the stream is synchronized before the call returns).
+ *   rank0, rank1, contrib0, contrib1   float[V][64] pairs (rank0 and contrib0
+ *                                      receive the start vectors)
+ *   scalars            double[2 * 64 * 4]: the two scalar sets of the pair
+ *   seeds, partial, workspace as for cagra_ppr_iter (workspace of
+ *                      cagra_ppr_workspace_bytes)
+ * The result is in rank[host_result->final_buf] (and contrib[...]). Returns
+ * CAGRA_OK when every column converged, CAGRA_E_NOT_CONVERGED when max_iters
+ * steps ran without that (host_result still describes the last iterate), or
+ * the status of a failed step.
+ */
+typedef struct {
+    double damping;        /* d in [0, 1] */
+    double tol;            /* stopping threshold on every column's L1 residual, > 0 */
+    int32_t max_iters;     /* iteration cap, >= 1 */
+    int32_t check_every;   /* read the residuals back every this many iterations, >= 1 */
+} cagra_ppr_params;
+typedef struct {
+    int32_t iters;         /* iterations run */
+    int32_t final_buf;     /* 0 or 1: which buffer of each pair holds the result */
+    double residual;       /* largest column residual of the last read-back (inf before the first) */
+} cagra_ppr_result;
+cagra_status cagra_ppr_solve(const cagra_graph *g, const cagra_segments *seg, const cagra_ppr_params *params,
+                             int32_t ncols, const int32_t *seeds, float *rank0, float *rank1, float *contrib0,
+                             float *contrib1, double *scalars, float *partial, void *workspace,
+                             size_t workspace_bytes, cagra_ppr_result *host_result, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Many independent graphs in one launch per kernel                          */

@@ -54,7 +54,7 @@ EXPORTS = [
     "cagra_validate_workspace_bytes", "cagra_validate_graph",
     "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_noalloc_scratch_bytes", "cagra_pagerank_iter_noalloc",
     "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
-    "cagra_ppr_iter", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
+    "cagra_ppr_iter", "cagra_ppr_solve", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
     "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
     "cagra_warm_start_vector", "cagra_mlp_targets", "cagra_feature_norm_workspace_bytes", "cagra_feature_norm",
@@ -70,6 +70,14 @@ class CPrParams(ctypes.Structure):
 class CPrResult(ctypes.Structure):
     _fields_ = [("iters", _c_i32), ("iters_bf16", _c_i32), ("final_buf", _c_i32), ("residual", _c_dbl),
                 ("scalars", _c_dbl * 4)]
+
+
+class CPprParams(ctypes.Structure):
+    _fields_ = [("damping", _c_dbl), ("tol", _c_dbl), ("max_iters", _c_i32), ("check_every", _c_i32)]
+
+
+class CPprResult(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("final_buf", _c_i32), ("residual", _c_dbl)]
 
 
 class CMulti(ctypes.Structure):
@@ -180,6 +188,8 @@ def lib():
             "cagra_ppr_init": ([GP, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
             "cagra_ppr_iter": ([GP, SP, _c_dbl, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                 _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_ppr_solve": ([GP, SP, ctypes.POINTER(CPprParams), _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                 _c_vp, _c_vp, _c_vp, _c_size, ctypes.POINTER(CPprResult), st], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -478,6 +488,13 @@ class SolveResult:
     converged: bool
 
 
+@dataclass
+class PprSolveResult:
+    iters: int
+    residual: float       # largest column residual of the last check
+    converged: bool
+
+
 def pagerank_solve(dg: DeviceGraph, seg: Segments, tol: float = 1e-6, max_iters: int = 100, damping: float = 0.85,
                    contrib_type: int = F32, switch_tol: float = 0.0, rank0=None, check_every: int = 1,
                    stream=None, state: "SolveBuffers | None" = None, restart: int = -1) -> SolveResult:
@@ -681,7 +698,8 @@ class PPRState:
         V = dg.V
         self.rank = [torch.empty(V * PPR_COLS, dtype=torch.float32, device=dev) for _ in range(2)]
         self.contrib = [torch.empty(V * PPR_COLS, dtype=torch.float32, device=dev) for _ in range(2)]
-        self.scalars = [torch.zeros(PPR_COLS * 4, dtype=torch.float64, device=dev) for _ in range(2)]
+        self._sc = torch.zeros(2 * PPR_COLS * 4, dtype=torch.float64, device=dev)  # the pair, back to back
+        self.scalars = [self._sc[:PPR_COLS * 4], self._sc[PPR_COLS * 4:]]
         self.partial = torch.empty(max(seg.Q, 1) * PPR_COLS, dtype=torch.float32, device=dev)
         n = lib().cagra_ppr_workspace_bytes(ctypes.byref(seg.c))
         self.ws = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -701,6 +719,22 @@ class PPRState:
                                     _ptr(self.contrib[b]), _ptr(self.scalars[b]), _ptr(self.ws), self.ws.numel(),
                                     _stream(stream)), "cagra_ppr_iter")
         self.cur = b
+
+    def solve(self, tol: float = 1e-6, max_iters: int = 100, damping: float = 0.85, check_every: int = 1,
+              stream=None) -> "PprSolveResult":
+        """cagra_ppr_solve: from the seed vectors until every column's L1 residual
+        is below tol; the current vectors are then the result. converged is
+        False when max_iters ran out (CAGRA_E_NOT_CONVERGED)."""
+        p = CPprParams(damping, tol, max_iters, check_every)
+        r = CPprResult()
+        st = lib().cagra_ppr_solve(ctypes.byref(self.dg.c), ctypes.byref(self.seg.c), ctypes.byref(p), self.ncols,
+                                   _ptr(self.seeds), _ptr(self.rank[0]), _ptr(self.rank[1]), _ptr(self.contrib[0]),
+                                   _ptr(self.contrib[1]), _ptr(self._sc), _ptr(self.partial), _ptr(self.ws),
+                                   self.ws.numel(), ctypes.byref(r), _stream(stream))
+        if st not in (OK, E_NOT_CONVERGED):
+            _check(st, "cagra_ppr_solve")
+        self.cur = int(r.final_buf)
+        return PprSolveResult(int(r.iters), float(r.residual), st == OK)
 
     def ranks(self):
         """[V, ncols] view of the current vectors."""

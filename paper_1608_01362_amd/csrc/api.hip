@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "solve_loop.h"
 
 namespace cagra {
 
@@ -442,6 +443,71 @@ static cagra_status read_scalars(const double *d_scalars, double (&h)[4], hipStr
     return CAGRA_OK;
 }
 
+}  // extern "C"
+
+namespace cagra {
+// The PageRank parts of the pipelined solve: iterations of cagra_pagerank_iter
+// on the buffer pairs, the residual and range count of its scalars, and the
+// BF16-to-FP32 switch.
+struct PageRankSolveOps {
+    struct State {
+        int32_t iters, iters_bf16, cur, ct;
+    };
+    const cagra_graph *g;
+    const cagra_segments *seg;
+    const cagra_pr_params *p;
+    float *rank[2];
+    void *contrib[2];
+    double *sc[2];
+    float *partial;
+    void *ws;
+    hipStream_t st;
+    cagra_pr_result *res;
+    State at{0, 0, 0, CAGRA_F32};
+
+    State state() const { return at; }
+    void restore(const State &s) { at = s; }
+    int32_t iters() const { return at.iters; }
+    cagra_status step() {
+        cagra_status s;
+        const int c = at.cur;
+        if ((s = launch_gather(seg, CAGRA_SUM_F32, at.ct, contrib[c], partial, st)) != CAGRA_OK) return s;
+        if ((s = launch_merge_pr(g, seg, p->damping, p->restart_vertex, at.ct, rank[c], sc[c], partial, rank[1 - c],
+                                 contrib[1 - c], sc[1 - c], ws, st)) != CAGRA_OK)
+            return s;
+        at.cur = 1 - c;
+        ++at.iters;
+        if (at.ct == CAGRA_BF16) ++at.iters_bf16;
+        return CAGRA_OK;
+    }
+    const double *dev_scalars() const { return sc[at.cur]; }
+    size_t scalar_doubles() const { return 4; }
+    bool switch_pending(int32_t ct) const { return ct == CAGRA_BF16 && p->switch_tol > 0.0; }
+    Verdict judge(const State &a, const double *h, double *resid, cagra_status *err) const {
+        for (int c = 0; c < 4; ++c) res->scalars[c] = h[c];
+        res->residual = *resid = h[1];
+        if (h[3] != 0.0) {
+            *err = fail(CAGRA_E_RANGE, "iteration %d: %g merge blocks held non-finite buffer values or an absolute "
+                        "buffer mass beyond the exact fixed-point range", a.iters, h[3]);
+            return Verdict::kError;
+        }
+        if (h[1] < p->tol) return Verdict::kConverged;
+        if (switch_pending(a.ct) && h[1] < p->switch_tol) return Verdict::kSwitch;
+        return Verdict::kContinue;
+    }
+    bool may_end(double pred) const {
+        return pred < 2.0 * p->tol || (switch_pending(at.ct) && pred < 2.0 * p->switch_tol);
+    }
+    cagra_status switch_precision() {
+        // finish in FP32: contributions rebuilt from the current ranks
+        at.ct = CAGRA_F32;
+        return launch_pr_init(g, at.ct, rank[at.cur], contrib[at.cur], sc[at.cur], ws, st);
+    }
+};
+}  // namespace cagra
+
+extern "C" {
+
 cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *seg, const cagra_pr_params *p,
                                   float *rank0, float *rank1, void *contrib0, void *contrib1, double *scalars,
                                   float *partial, void *workspace, size_t workspace_bytes,
@@ -458,50 +524,24 @@ cagra_status cagra_pagerank_solve(const cagra_graph *g, const cagra_segments *se
     if (!rank0 || !rank1 || !contrib0 || !contrib1 || !scalars || (seg->Q > 0 && !partial))
         return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     if (rank0 == rank1 || contrib0 == contrib1) return fail(CAGRA_E_INVALID, "the two buffers of a pair must differ");
-    float *rank[2] = {rank0, rank1};
-    void *contrib[2] = {contrib0, contrib1};
-    double *sc[2] = {scalars, scalars + 4};
     *host_result = cagra_pr_result{};
-    int32_t ct = p->contrib_type;
-    if ((s = launch_pr_init(g, ct, rank0, contrib0, sc[0], workspace, stream)) != CAGRA_OK) return s;
+    PageRankSolveOps ops{g, seg, p, {rank0, rank1}, {contrib0, contrib1}, {scalars, scalars + 4}, partial, workspace,
+                         stream, host_result};
+    ops.at.ct = p->contrib_type;
+    if ((s = launch_pr_init(g, ops.at.ct, rank0, contrib0, scalars, workspace, stream)) != CAGRA_OK) return s;
     double h[4];
-    if ((s = read_scalars(sc[0], h, stream)) != CAGRA_OK) return s;
+    if ((s = read_scalars(scalars, h, stream)) != CAGRA_OK) return s;
     for (int c = 0; c < 4; ++c) host_result->scalars[c] = h[c];
     host_result->residual = INFINITY;
     if (h[3] != 0.0) return fail(CAGRA_E_RANGE, "the start vector holds %.0f non-finite values", h[3]);
-    int cur = 0;
-    bool converged = false;
-    while (host_result->iters < p->max_iters) {
-        if ((s = launch_gather(seg, CAGRA_SUM_F32, ct, contrib[cur], partial, stream)) != CAGRA_OK) return s;
-        if ((s = launch_merge_pr(g, seg, p->damping, p->restart_vertex, ct, rank[cur], sc[cur], partial, rank[1 - cur],
-                                 contrib[1 - cur], sc[1 - cur], workspace, stream)) != CAGRA_OK)
-            return s;
-        cur = 1 - cur;
-        host_result->final_buf = cur;
-        host_result->iters++;
-        if (ct == CAGRA_BF16) host_result->iters_bf16++;
-        if (host_result->iters % p->check_every != 0 && host_result->iters < p->max_iters) continue;
-        if ((s = read_scalars(sc[cur], h, stream)) != CAGRA_OK) return s;
-        for (int c = 0; c < 4; ++c) host_result->scalars[c] = h[c];
-        host_result->residual = h[1];
-        if (h[3] != 0.0)
-            return fail(CAGRA_E_RANGE, "iteration %d: %g merge blocks held non-finite buffer values or an absolute "
-                        "buffer mass beyond the exact fixed-point range", host_result->iters, h[3]);
-        if (h[1] < p->tol) {
-            converged = true;
-            break;
-        }
-        if (ct == CAGRA_BF16 && p->switch_tol > 0.0 && h[1] < p->switch_tol) {
-            // finish in FP32: contributions rebuilt from the current ranks
-            ct = CAGRA_F32;
-            if ((s = launch_pr_init(g, ct, rank[cur], contrib[cur], sc[cur], workspace, stream)) != CAGRA_OK)
-                return s;
-        }
-    }
-    if (!converged)
+    s = pipelined_solve(ops, p->max_iters, p->check_every, stream);
+    host_result->iters = ops.at.iters;
+    host_result->iters_bf16 = ops.at.iters_bf16;
+    host_result->final_buf = ops.at.cur;
+    if (s == CAGRA_E_NOT_CONVERGED)
         return fail(CAGRA_E_NOT_CONVERGED, "no L1 residual below %g within %d iterations (last %g)", p->tol,
                     p->max_iters, host_result->residual);
-    return CAGRA_OK;
+    return s;
 }
 
 cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labels_in, int32_t *partial,
@@ -664,6 +704,96 @@ cagra_status cagra_ppr_iter(const cagra_graph *g, const cagra_segments *seg, dou
                     workspace_bytes);
     return launch_ppr_iter(g, seg, damping, ncols, seeds, rank_in, contrib_in, scalars_in, partial, rank_out,
                            contrib_out, scalars_out, (double *)workspace, stream);
+}
+
+}  // extern "C"
+
+namespace cagra {
+// The batched personalized PageRank parts of the pipelined solve: iterations
+// of cagra_ppr_iter on the buffer pairs; a check converges when every
+// column's L1 residual is below tol (a NaN residual never is).
+struct PprSolveOps {
+    struct State {
+        int32_t iters, cur;
+    };
+    const cagra_graph *g;
+    const cagra_segments *seg;
+    const cagra_ppr_params *p;
+    int32_t ncols;
+    const int32_t *seeds;
+    float *rank[2];
+    float *contrib[2];
+    double *sc[2];
+    float *partial;
+    double *ws;
+    hipStream_t st;
+    cagra_ppr_result *res;
+    State at{0, 0};
+
+    State state() const { return at; }
+    void restore(const State &s) { at = s; }
+    int32_t iters() const { return at.iters; }
+    cagra_status step() {
+        const int c = at.cur;
+        cagra_status s = launch_ppr_iter(g, seg, p->damping, ncols, seeds, rank[c], contrib[c], sc[c], partial,
+                                         rank[1 - c], contrib[1 - c], sc[1 - c], ws, st);
+        if (s != CAGRA_OK) return s;
+        at.cur = 1 - c;
+        ++at.iters;
+        return CAGRA_OK;
+    }
+    const double *dev_scalars() const { return sc[at.cur]; }
+    size_t scalar_doubles() const { return (size_t)ncols * 4; }
+    Verdict judge(const State &, const double *h, double *resid, cagra_status *) const {
+        double worst = 0.0;
+        for (int j = 0; j < ncols; ++j) {
+            const double r = h[j * 4 + 1];
+            if (!(r <= worst)) worst = r;  // NaN sticks
+            if (isnan(r)) break;
+        }
+        res->residual = *resid = worst;
+        return worst < p->tol ? Verdict::kConverged : Verdict::kContinue;
+    }
+    bool may_end(double pred) const { return pred < 2.0 * p->tol; }
+    cagra_status switch_precision() { return CAGRA_OK; }
+};
+}  // namespace cagra
+
+extern "C" {
+
+cagra_status cagra_ppr_solve(const cagra_graph *g, const cagra_segments *seg, const cagra_ppr_params *p,
+                             int32_t ncols, const int32_t *seeds, float *rank0, float *rank1, float *contrib0,
+                             float *contrib1, double *scalars, float *partial, void *workspace,
+                             size_t workspace_bytes, cagra_ppr_result *host_result, hipStream_t stream) {
+    cagra_status s;
+    if (!p || !host_result) return fail(CAGRA_E_INVALID, "params or host_result is NULL");
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (seg->V != g->V || seg->E != g->E) return fail(CAGRA_E_INVALID, "segments belong to a different graph");
+    if (!(p->damping >= 0.0 && p->damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
+    if (!(p->tol > 0.0)) return fail(CAGRA_E_INVALID, "tol must be > 0");
+    if (p->max_iters < 1 || p->check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
+    if (ncols < 1 || ncols > CAGRA_PPR_COLS) return fail(CAGRA_E_INVALID, "ncols must be in [1, %d]", CAGRA_PPR_COLS);
+    if (seg->B > kMaxPprBlock) return fail(CAGRA_E_CAPACITY, "batched merge needs B <= %d (got %d)", kMaxPprBlock, seg->B);
+    if (!seeds || !rank0 || !rank1 || !contrib0 || !contrib1 || !scalars || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (rank0 == rank1 || contrib0 == contrib1) return fail(CAGRA_E_INVALID, "the two buffers of a pair must differ");
+    if (!workspace || workspace_bytes < cagra_ppr_workspace_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", cagra_ppr_workspace_bytes(seg),
+                    workspace_bytes);
+    *host_result = cagra_ppr_result{};
+    host_result->residual = INFINITY;
+    PprSolveOps ops{g, seg, p, ncols, seeds, {rank0, rank1}, {contrib0, contrib1},
+                    {scalars, scalars + CAGRA_PPR_COLS * 4}, partial, (double *)workspace, stream, host_result};
+    if ((s = launch_ppr_init(g, ncols, seeds, rank0, contrib0, scalars, (double *)workspace, stream)) != CAGRA_OK)
+        return s;
+    s = pipelined_solve(ops, p->max_iters, p->check_every, stream);
+    host_result->iters = ops.at.iters;
+    host_result->final_buf = ops.at.cur;
+    if (s == CAGRA_E_NOT_CONVERGED)
+        return fail(CAGRA_E_NOT_CONVERGED, "a column's L1 residual is still %g >= %g after %d iterations",
+                    host_result->residual, p->tol, p->max_iters);
+    return s;
 }
 
 size_t cagra_push_workspace_bytes(const cagra_segments *seg_t) {

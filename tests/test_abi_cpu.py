@@ -265,3 +265,38 @@ def test_pagerank_solve_validation(cagra):
     assert call(P(), sc=None) == cagra.E_INVALID
     assert call(P(), wsb=ws - 1) == cagra.E_BUFFER
     assert L.cagra_last_error()
+
+
+def test_ppr_solve_validation(cagra):
+    """cagra_ppr_solve rejects bad arguments before any HIP call."""
+    L = cagra.lib()
+    s = _fake_built(cagra)
+    g = _graph(cagra, V=100, E=50)
+    ws = L.cagra_ppr_workspace_bytes(ctypes.byref(s))
+    res = cagra.CPprResult()
+
+    def call(p, ncols=4, seeds=9, r0=1, r1=2, c0=3, c1=4, sc=5, part=6, wsp=7, wsb=ws, result=res, seg=s, gr=g):
+        return L.cagra_ppr_solve(ctypes.byref(gr), ctypes.byref(seg), None if p is None else ctypes.byref(p), ncols,
+                                 seeds, r0, r1, c0, c1, sc, part, wsp, wsb,
+                                 None if result is None else ctypes.byref(result), None)
+
+    def P(damping=0.85, tol=1e-6, max_iters=100, check_every=1):
+        return cagra.CPprParams(damping, tol, max_iters, check_every)
+    assert call(None) == cagra.E_INVALID
+    assert call(P(), result=None) == cagra.E_INVALID
+    assert call(P(tol=0.0)) == cagra.E_INVALID
+    assert call(P(tol=float("nan"))) == cagra.E_INVALID
+    assert call(P(max_iters=0)) == cagra.E_INVALID
+    assert call(P(check_every=0)) == cagra.E_INVALID
+    assert call(P(damping=-0.1)) == cagra.E_INVALID
+    assert call(P(), ncols=0) == cagra.E_INVALID
+    assert call(P(), ncols=cagra.PPR_COLS + 1) == cagra.E_INVALID
+    assert call(P(), seeds=None) == cagra.E_INVALID
+    assert call(P(), r1=1) == cagra.E_INVALID                   # rank pair aliased
+    assert call(P(), c1=3) == cagra.E_INVALID                   # contribution pair aliased
+    assert call(P(), sc=None) == cagra.E_INVALID
+    assert call(P(), wsb=ws - 1) == cagra.E_BUFFER
+    assert call(P(), seg=_fake_built(cagra, B=1024, V=2048, N=1024)) == cagra.E_INVALID  # another graph's
+    assert call(P(), seg=_fake_built(cagra, B=1024, V=2048, N=1024),
+                gr=_graph(cagra, V=2048, E=50)) == cagra.E_CAPACITY  # B above 512
+    assert L.cagra_last_error()

@@ -166,3 +166,73 @@ def test_solve_on_degenerate_graphs(cagra, name):
     assert np.allclose(got, 1.0 / g.V, rtol=1e-6, atol=0)
     ref, _ = oracle.pagerank(g, iters=1)
     assert np.abs(got - ref).sum() <= 1e-6
+
+
+def _waiting_loop(cagra, dg, seg, tol, max_iters, check_every, ct, switch_tol, restart):
+    """The solve written as a loop that waits for the scalars at every check
+    (step by step through PageRankState); returns what the solve reports."""
+    st = cagra.PageRankState(dg, seg, ct, restart=restart)
+    st.start()
+    it = it_bf16 = 0
+    sc = None
+    while it < max_iters:
+        st.step()
+        it += 1
+        it_bf16 += ct == cagra.BF16
+        if it % check_every and it < max_iters:
+            continue
+        sc = st.scalars_now.cpu().numpy()
+        if sc[1] < tol:
+            return st.rank_now.clone(), it, it_bf16, sc, True
+        if ct == cagra.BF16 and switch_tol > 0 and sc[1] < switch_tol:
+            fin = cagra.PageRankState(dg, seg, cagra.F32, restart=restart)
+            fin.start(st.rank_now)  # FP32 contributions from the current ranks
+            st, ct = fin, cagra.F32
+    return st.rank_now.clone(), it, it_bf16, sc, False
+
+
+SOLVE_CASES = [
+    # (tol, max_iters, check_every, contrib type, switch_tol, restart)
+    (1e-6, 100, 1, "F32", 0.0, -1),
+    (1e-7, 100, 3, "F32", 0.0, -1),
+    (1e-1, 100, 1, "F32", 0.0, -1),      # the first check ends the loop (the step queued past it is dropped)
+    (1e-6, 5, 1, "F32", 0.0, -1),        # the cap
+    (1e-6, 7, 4, "F32", 0.0, -1),        # the cap between two multiples of check_every
+    (1e-6, 100, 1, "BF16", 1e-4, -1),    # the switch rolls back the step queued past its check
+    (1e-6, 100, 2, "BF16", 1e-4, -1),
+    (1e-6, 100, 1, "BF16", 0.0, -1),
+    (1e-6, 100, 1, "F32", 0.0, "hub"),   # personalized
+]
+
+
+@pytest.mark.parametrize("case", range(len(SOLVE_CASES)))
+def test_pipelined_solve_equals_the_waiting_loop(cagra, cfg1, case):
+    """The solve queues the step after a check before it reads the check back
+    and rolls back when the check ends the loop or switches the precision: its
+    iterate, counts and scalars equal those of a loop that waits at every check,
+    bit for bit."""
+    g, dg, seg = cfg1
+    tol, max_iters, every, ctn, sw, restart = SOLVE_CASES[case]
+    ct = getattr(cagra, ctn)
+    if restart == "hub":
+        restart = int(np.argmax(g.out_degree))
+    r = cagra.pagerank_solve(dg, seg, tol=tol, max_iters=max_iters, check_every=every, contrib_type=ct,
+                             switch_tol=sw, restart=restart)
+    rank, it, it_bf16, sc, conv = _waiting_loop(cagra, dg, seg, tol, max_iters, every, ct, sw, restart)
+    print(f"case {case}: {r.iters} iterations ({r.iters_bf16} bf16), converged {r.converged}, "
+          f"residual {r.residual:.3e}")
+    assert (r.converged, r.iters, r.iters_bf16) == (conv, it, it_bf16)
+    assert r.residual == sc[1] and list(r.scalars) == list(sc)
+    assert np.array_equal(r.rank.cpu().numpy(), rank.cpu().numpy())
+
+
+def test_pipelined_solve_switch_at_the_cap(cagra, cfg1):
+    """A switch read at the cap's check rebuilds the contributions and stops
+    there, as the waiting loop does."""
+    g, dg, seg = cfg1
+    full = cagra.pagerank_solve(dg, seg, tol=1e-6, contrib_type=cagra.BF16, switch_tol=1e-4)
+    cap = full.iters_bf16  # the check that switched
+    r = cagra.pagerank_solve(dg, seg, tol=1e-6, max_iters=cap, contrib_type=cagra.BF16, switch_tol=1e-4)
+    rank, it, it_bf16, sc, conv = _waiting_loop(cagra, dg, seg, 1e-6, cap, 1, cagra.BF16, 1e-4, -1)
+    assert not r.converged and not conv and r.iters == it == cap and r.iters_bf16 == it_bf16 == cap
+    assert np.array_equal(r.rank.cpu().numpy(), rank.cpu().numpy())

@@ -105,3 +105,40 @@ def test_single_seed_solve_to_residual(cagra):
     assert res.converged
     star = oracle.ppr(g, s, 300)
     assert np.abs(res.rank.double().cpu().numpy() - star).sum() <= 0.85 / 0.15 * 1e-6 + 1e-6
+
+
+@pytest.mark.parametrize("tol,max_iters,every", [(1e-6, 100, 1), (1e-7, 100, 2), (1e-1, 100, 1), (1e-6, 6, 1),
+                                                 (1e-6, 9, 4)])
+def test_ppr_solve_equals_the_waiting_loop(cagra, tol, max_iters, every):
+    """cagra_ppr_solve (the step after a check queued before the check is read
+    back) stops where a loop that waits at every check stops, with the same
+    vectors bit for bit; converged columns are within the contraction bound of
+    the oracle's personalized PageRank."""
+    import torch
+    g = graphgen.rmat_graph(12, 8, 7)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 1024, 512, 4096)
+    seeds = seeds_for(g, 64, 3)
+    st = cagra.PPRState(dg, seg, seeds)
+    r = st.solve(tol=tol, max_iters=max_iters, check_every=every)
+    got = st.ranks().clone()
+    w = cagra.PPRState(dg, seg, seeds)
+    w.start()
+    it, worst, conv = 0, float("inf"), False
+    while it < max_iters:
+        w.step()
+        it += 1
+        if it % every and it < max_iters:
+            continue
+        worst = float(w.scalars_now[:, 1].max().item())
+        if worst < tol:
+            conv = True
+            break
+    print(f"ppr solve: {r.iters} iterations, residual {r.residual:.3e}, converged {r.converged}")
+    assert (r.converged, r.iters) == (conv, it) and r.residual == worst
+    assert torch.equal(got, w.ranks())
+    if conv and tol <= 1e-6:
+        R = got.double().cpu().numpy()
+        for j in range(0, 64, 21):
+            want = oracle.ppr(g, int(seeds[j]), 200)
+            assert np.abs(R[:, j] - want).sum() <= 0.85 / 0.15 * tol + 1e-6, j
