@@ -497,6 +497,34 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
                                   int32_t *labels_out, int32_t *changed_out, void *workspace,
                                   size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Label propagation to its fixed point (the Section 4 program repeated until
+ * no label changes): cagra_labelprop_iter steps from labels0, with the change
+ * count read back after every check_every-th step; the loop stops at the
+ * first check that reads 0, or after max_iters steps. The host loop is the one
+ * of cagra_pagerank_solve: the step after a check is queued before the check
+ * is read back (unless the change counts predict that the check may read 0),
+ * and when the check ends the loop that step is dropped, so the labels and
+ * the count are those of a loop that waited at every check. The stream is
+ * synchronized before the call returns.
+ *   labels0, labels1   int32[V] pair; labels0 holds the start labels on entry
+ *                      (the vertex ids for connected components)
+ *   partial, workspace as for cagra_labelprop_iter; changed: device int32[1]
+ * The result is in labels[host_result->final_buf]. Returns CAGRA_OK when a
+ * check read no change (host_result->iters counts that last step),
+ * CAGRA_E_NOT_CONVERGED when max_iters steps ran without that, or the status
+ * of a failed step.
+ */
+typedef struct {
+    int32_t iters;         /* steps run, the last (unchanged) one included */
+    int32_t final_buf;     /* 0 or 1: which buffer of the pair holds the result */
+    int32_t changed;       /* change count of the last check read back (-1 before the first) */
+} cagra_lp_result;
+cagra_status cagra_labelprop_solve(const cagra_segments *seg, int32_t max_iters, int32_t check_every,
+                                   int32_t *labels0, int32_t *labels1, int32_t *partial, int32_t *changed,
+                                   void *workspace, size_t workspace_bytes, cagra_lp_result *host_result,
+                                   hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Personalized PageRank for many restart vertices (segmented SpMM)          */
 /* ------------------------------------------------------------------------ */

@@ -53,7 +53,7 @@ EXPORTS = [
     "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
     "cagra_validate_workspace_bytes", "cagra_validate_graph",
     "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_noalloc_scratch_bytes", "cagra_pagerank_iter_noalloc",
-    "cagra_labelprop_iter", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
+    "cagra_labelprop_iter", "cagra_labelprop_solve", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
     "cagra_ppr_iter", "cagra_ppr_solve", "cagra_multi_query", "cagra_multi_setup", "cagra_multi_pagerank_start",
     "cagra_multi_pagerank_step", "cagra_features_workspace_bytes", "cagra_degree_features", "cagra_mlp_forward",
     "cagra_mlp_grad_workspace_bytes", "cagra_mlp_grad", "cagra_adam_step", "cagra_warm_start_workspace_bytes",
@@ -70,6 +70,10 @@ class CPrParams(ctypes.Structure):
 class CPrResult(ctypes.Structure):
     _fields_ = [("iters", _c_i32), ("iters_bf16", _c_i32), ("final_buf", _c_i32), ("residual", _c_dbl),
                 ("scalars", _c_dbl * 4)]
+
+
+class CLpResult(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("final_buf", _c_i32), ("changed", _c_i32)]
 
 
 class CPprParams(ctypes.Structure):
@@ -153,6 +157,8 @@ def lib():
             "cagra_pagerank_merge": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                       _c_vp, _c_size, st], ctypes.c_int),
             "cagra_labelprop_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_labelprop_solve": ([SP, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size,
+                                       ctypes.POINTER(CLpResult), st], ctypes.c_int),
             "cagra_noalloc_scratch_bytes": ([], _c_size),
             "cagra_pagerank_iter_noalloc": ([GP, SP, _c_dbl, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                              _c_vp, _c_vp, st], ctypes.c_int),
@@ -565,24 +571,26 @@ def pagerank(dg: DeviceGraph, seg: Segments, iters: int = 20, damping: float = 0
     return stt.rank_now.clone(), None, iters
 
 
-def labelprop(seg: Segments, max_iters: int = 1 << 20):
-    """Min-label propagation to the fixed point; returns (labels tensor, iterations
-    including the final one without changes)."""
+def labelprop(seg: Segments, max_iters: int = 1 << 20, check_every: int = 1, labels0=None, stream=None):
+    """cagra_labelprop_solve: min-label propagation from the vertex ids (or
+    labels0) to the fixed point; returns (labels tensor, iterations including the
+    final one without changes). At the cap (CAGRA_E_NOT_CONVERGED) the labels so
+    far and max_iters are returned."""
     import torch
     dev = _dev()
     V = seg.c.V
-    lab = [torch.arange(V, dtype=torch.int32, device=dev), torch.empty(V, dtype=torch.int32, device=dev)]
+    lab = [torch.arange(V, dtype=torch.int32, device=dev) if labels0 is None else labels0.to(torch.int32).clone(),
+           torch.empty(V, dtype=torch.int32, device=dev)]
     partial = torch.empty(max(seg.Q, 1), dtype=torch.int32, device=dev)
     changed = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = iter_workspace(seg)
-    cur, it = 0, 0
-    while it < max_iters:
-        labelprop_iter(seg, lab[cur], partial, lab[1 - cur], changed, ws)
-        cur = 1 - cur
-        it += 1
-        if int(changed.item()) == 0:
-            break
-    return lab[cur], it
+    r = CLpResult()
+    st = lib().cagra_labelprop_solve(ctypes.byref(seg.c), max_iters, check_every, _ptr(lab[0]), _ptr(lab[1]),
+                                     _ptr(partial), _ptr(changed), _ptr(ws), ws.numel(), ctypes.byref(r),
+                                     _stream(stream))
+    if st not in (OK, E_NOT_CONVERGED):
+        _check(st, "cagra_labelprop_solve")
+    return lab[r.final_buf], int(r.iters)
 
 
 # --------------------------------------------------------------------------- push direction

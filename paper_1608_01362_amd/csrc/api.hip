@@ -480,10 +480,11 @@ struct PageRankSolveOps {
         if (at.ct == CAGRA_BF16) ++at.iters_bf16;
         return CAGRA_OK;
     }
-    const double *dev_scalars() const { return sc[at.cur]; }
-    size_t scalar_doubles() const { return 4; }
+    const void *dev_check() const { return sc[at.cur]; }
+    size_t check_bytes() const { return 4 * sizeof(double); }
     bool switch_pending(int32_t ct) const { return ct == CAGRA_BF16 && p->switch_tol > 0.0; }
-    Verdict judge(const State &a, const double *h, double *resid, cagra_status *err) const {
+    Verdict judge(const State &a, const void *hv, double *resid, cagra_status *err) const {
+        const double *h = static_cast<const double *>(hv);
         for (int c = 0; c < 4; ++c) res->scalars[c] = h[c];
         res->residual = *resid = h[1];
         if (h[3] != 0.0) {
@@ -558,6 +559,80 @@ cagra_status cagra_labelprop_iter(const cagra_segments *seg, const int32_t *labe
                     workspace_bytes);
     if ((s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, labels_in, partial, stream)) != CAGRA_OK) return s;
     return launch_merge_lp(seg, labels_in, partial, labels_out, changed_out, workspace, stream);
+}
+
+}  // extern "C"
+
+namespace cagra {
+// The label-propagation parts of the pipelined solve: steps of
+// cagra_labelprop_iter on the label pair; a check converges when the step
+// changed no label (its count, read back, is zero).
+struct LabelpropSolveOps {
+    struct State {
+        int32_t iters, cur;
+    };
+    const cagra_segments *seg;
+    int32_t *lab[2];
+    int32_t *partial;
+    int32_t *changed;
+    void *ws;
+    hipStream_t st;
+    cagra_lp_result *res;
+    State at{0, 0};
+
+    State state() const { return at; }
+    void restore(const State &s) { at = s; }
+    int32_t iters() const { return at.iters; }
+    cagra_status step() {
+        const int c = at.cur;
+        cagra_status s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, lab[c], partial, st);
+        if (s != CAGRA_OK) return s;
+        if ((s = launch_merge_lp(seg, lab[c], partial, lab[1 - c], changed, ws, st)) != CAGRA_OK) return s;
+        at.cur = 1 - c;
+        ++at.iters;
+        return CAGRA_OK;
+    }
+    const void *dev_check() const { return changed; }
+    size_t check_bytes() const { return sizeof(int32_t); }
+    Verdict judge(const State &, const void *hv, double *resid, cagra_status *) const {
+        const int32_t n = *static_cast<const int32_t *>(hv);
+        res->changed = n;
+        *resid = (double)n;
+        return n == 0 ? Verdict::kConverged : Verdict::kContinue;
+    }
+    bool may_end(double pred) const { return pred < 2.0; }
+    cagra_status switch_precision() { return CAGRA_OK; }
+};
+}  // namespace cagra
+
+extern "C" {
+
+cagra_status cagra_labelprop_solve(const cagra_segments *seg, int32_t max_iters, int32_t check_every,
+                                   int32_t *labels0, int32_t *labels1, int32_t *partial, int32_t *changed,
+                                   void *workspace, size_t workspace_bytes, cagra_lp_result *host_result,
+                                   hipStream_t stream) {
+    cagra_status s;
+    if (!host_result) return fail(CAGRA_E_INVALID, "host_result is NULL");
+    if ((s = check_built(seg)) != CAGRA_OK) return s;
+    if (max_iters < 1 || check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
+    if (!labels0 || !labels1 || !changed || (seg->Q > 0 && !partial))
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (labels0 == labels1) return fail(CAGRA_E_INVALID, "the two label buffers must differ");
+    if (merge_fused_lds_total(seg->B, seg->k, 4) > CAGRA_LDS_BYTES)
+        return fail(CAGRA_E_CAPACITY, "B=%d with k=%d exceeds the merge kernel's LDS", seg->B, seg->k);
+    if (!workspace || workspace_bytes < iter_ws_bytes(seg))
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", iter_ws_bytes(seg),
+                    workspace_bytes);
+    *host_result = cagra_lp_result{};
+    host_result->changed = -1;
+    LabelpropSolveOps ops{seg, {labels0, labels1}, partial, changed, workspace, stream, host_result};
+    s = pipelined_solve(ops, max_iters, check_every, stream);
+    host_result->iters = ops.at.iters;
+    host_result->final_buf = ops.at.cur;
+    if (s == CAGRA_E_NOT_CONVERGED)
+        return fail(CAGRA_E_NOT_CONVERGED, "labels still changed (%d) after %d iterations", host_result->changed,
+                    max_iters);
+    return s;
 }
 
 size_t cagra_features_workspace_bytes(const cagra_segments *seg) {
@@ -742,9 +817,10 @@ struct PprSolveOps {
         ++at.iters;
         return CAGRA_OK;
     }
-    const double *dev_scalars() const { return sc[at.cur]; }
-    size_t scalar_doubles() const { return (size_t)ncols * 4; }
-    Verdict judge(const State &, const double *h, double *resid, cagra_status *) const {
+    const void *dev_check() const { return sc[at.cur]; }
+    size_t check_bytes() const { return (size_t)ncols * 4 * sizeof(double); }
+    Verdict judge(const State &, const void *hv, double *resid, cagra_status *) const {
+        const double *h = static_cast<const double *>(hv);
         double worst = 0.0;
         for (int j = 0; j < ncols; ++j) {
             const double r = h[j * 4 + 1];

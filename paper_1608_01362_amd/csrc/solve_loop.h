@@ -24,14 +24,14 @@
 
 namespace cagra {
 
-// Pinned host slots and events through which a solve reads its scalars back.
-// Created per device on first use, kept until the process ends, and lent to
-// one solve at a time (concurrent solves take distinct ones).
-constexpr int kReadbackDoubles = CAGRA_PPR_COLS * 4;  // the largest scalar set read back at once
+// Pinned host slots and events through which a solve reads its check values
+// back. Created per device on first use, kept until the process ends, and lent
+// to one solve at a time (concurrent solves take distinct ones).
+constexpr size_t kReadbackBytes = CAGRA_PPR_COLS * 4 * sizeof(double);  // the largest set read back at once
 
 struct Readback {
     int dev = -1;
-    double *host = nullptr;  // two slots of kReadbackDoubles
+    unsigned char *host = nullptr;  // two slots of kReadbackBytes
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -69,7 +69,7 @@ class ReadbackLease {
         }
         Readback *r = new Readback;
         r->dev = dev;
-        hipError_t e = hipHostMalloc((void **)&r->host, 2 * kReadbackDoubles * sizeof(double), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&r->host, 2 * kReadbackBytes, hipHostMallocDefault);
         for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&r->ev[i], hipEventDisableTiming);
         if (e != hipSuccess) {
             for (int i = 0; i < 2; ++i)
@@ -102,12 +102,13 @@ inline double predict_residual(double r_last, double r_prev) {
 //       back to;
 //   int32_t iters() const                              iterations queued;
 //   cagra_status step()                                queues one iteration;
-//   const double *dev_scalars() const, size_t scalar_doubles() const
-//                                                      the scalars to read back
-//                                                      after the current iterate;
-//   Verdict judge(const State &at, const double *h, double *residual,
-//                 cagra_status *err)                   decides from the scalars
-//                                                      h read back at position at
+//   const void *dev_check() const, size_t check_bytes() const
+//                                                      the device values to read
+//                                                      back after the current
+//                                                      iterate (<= kReadbackBytes);
+//   Verdict judge(const State &at, const void *h, double *residual,
+//                 cagra_status *err)                   decides from the values h
+//                                                      read back at position at
 //                                                      (kError sets *err);
 //   bool may_end(double predicted) const               whether a check with this
 //                                                      residual may end or switch;
@@ -139,9 +140,8 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
         cagra_status t = ops.step();
         if (t != CAGRA_OK) return t;
         if (!is_check(ops.iters())) return CAGRA_OK;
-        double *dst = rb->host + (size_t)slot * kReadbackDoubles;
-        CAGRA_HIP_CHECK(hipMemcpyAsync(dst, ops.dev_scalars(), ops.scalar_doubles() * sizeof(double),
-                                       hipMemcpyDeviceToHost, st));
+        unsigned char *dst = rb->host + (size_t)slot * kReadbackBytes;
+        CAGRA_HIP_CHECK(hipMemcpyAsync(dst, ops.dev_check(), ops.check_bytes(), hipMemcpyDeviceToHost, st));
         CAGRA_HIP_CHECK(hipEventRecord(rb->ev[slot], st));
         q[nq++] = Check{ops.state(), slot};
         slot ^= 1;
@@ -161,7 +161,7 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
             break;
         }
         double resid = INFINITY;
-        const Verdict v = ops.judge(q[0].at, rb->host + (size_t)q[0].slot * kReadbackDoubles, &resid, &err);
+        const Verdict v = ops.judge(q[0].at, rb->host + (size_t)q[0].slot * kReadbackBytes, &resid, &err);
         r_prev = r_last;
         r_last = resid;
         if (v == Verdict::kContinue) {

@@ -300,3 +300,24 @@ def test_ppr_solve_validation(cagra):
     assert call(P(), seg=_fake_built(cagra, B=1024, V=2048, N=1024),
                 gr=_graph(cagra, V=2048, E=50)) == cagra.E_CAPACITY  # B above 512
     assert L.cagra_last_error()
+
+
+def test_labelprop_solve_validation(cagra):
+    """cagra_labelprop_solve rejects bad arguments before any HIP call."""
+    L = cagra.lib()
+    s = _fake_built(cagra)
+    ws = L.cagra_iter_workspace_bytes(ctypes.byref(s))
+    res = cagra.CLpResult()
+
+    def call(mi=100, every=1, l0=1, l1=2, part=3, ch=4, wsp=5, wsb=ws, result=res):
+        return L.cagra_labelprop_solve(ctypes.byref(s), mi, every, l0, l1, part, ch, wsp, wsb,
+                                       None if result is None else ctypes.byref(result), None)
+    assert call(result=None) == cagra.E_INVALID
+    assert call(mi=0) == cagra.E_INVALID
+    assert call(every=0) == cagra.E_INVALID
+    assert call(l0=None) == cagra.E_INVALID
+    assert call(ch=None) == cagra.E_INVALID
+    assert call(l1=1) == cagra.E_INVALID                        # label pair aliased
+    assert call(wsb=ws - 1) == cagra.E_BUFFER
+    assert call(wsp=None) == cagra.E_BUFFER
+    assert L.cagra_last_error()

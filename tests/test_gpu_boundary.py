@@ -236,3 +236,43 @@ def test_pipelined_solve_switch_at_the_cap(cagra, cfg1):
     rank, it, it_bf16, sc, conv = _waiting_loop(cagra, dg, seg, 1e-6, cap, 1, cagra.BF16, 1e-4, -1)
     assert not r.converged and not conv and r.iters == it == cap and r.iters_bf16 == it_bf16 == cap
     assert np.array_equal(r.rank.cpu().numpy(), rank.cpu().numpy())
+
+
+@pytest.mark.parametrize("max_iters,every", [(1 << 20, 1), (1 << 20, 3), (3, 1), (5, 2)])
+def test_labelprop_solve_equals_the_waiting_loop(cagra, max_iters, every):
+    """cagra_labelprop_solve stops where a loop of cagra_labelprop_iter steps
+    that reads the change count at every check stops, with the same labels;
+    the fixed point is the oracle's connected-component labelling."""
+    import torch
+    g = graphgen.symmetrize(graphgen.rmat_graph(12, 4, 3))
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 1024, 512, 4096)
+    lab, it = cagra.labelprop(seg, max_iters=max_iters, check_every=every)
+    cur = torch.arange(g.V, dtype=torch.int32, device="cuda")
+    nxt = torch.empty_like(cur)
+    partial = torch.empty(max(seg.Q, 1), dtype=torch.int32, device="cuda")
+    changed = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = cagra.iter_workspace(seg)
+    n = 0
+    while n < max_iters:
+        cagra.labelprop_iter(seg, cur, partial, nxt, changed, ws)
+        cur, nxt = nxt, cur
+        n += 1
+        if n % every and n < max_iters:
+            continue
+        if int(changed.item()) == 0:
+            break
+    print(f"labelprop solve: {it} iterations (waiting loop {n})")
+    assert it == n and torch.equal(lab, cur)
+    if max_iters > 100:
+        want, _ = oracle.labelprop(g)
+        assert np.array_equal(lab.cpu().numpy(), want)
+
+
+def test_labelprop_solve_without_edges(cagra):
+    """No edges: the first step changes nothing and ends the loop."""
+    g = graphgen.from_edge_list(40, [])
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 16, 16, 64)
+    lab, it = cagra.labelprop(seg)
+    assert it == 1 and np.array_equal(lab.cpu().numpy(), np.arange(40))
