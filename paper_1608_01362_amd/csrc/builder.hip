@@ -83,11 +83,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *in, 
     __shared__ int32_t tile[kScanTile + kScanTile / 32];
     __shared__ int32_t wsum[kScanThreads / 64];
     int64_t base = (int64_t)blockIdx.x * kScanTile;
+    {
+        // all loads issued before any is stored (lanes past the end read the tile's first item)
+        int32_t v[kScanItems];
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        int p = i * kScanThreads + threadIdx.x;
-        int64_t j = base + p;
-        tile[pad_idx(p)] = j < n ? in[j] : Op::id();
+        for (int i = 0; i < kScanItems; ++i) {
+            int64_t j = base + i * kScanThreads + threadIdx.x;
+            v[i] = in[j < n ? j : base];
+        }
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            int p = i * kScanThreads + threadIdx.x;
+            tile[pad_idx(p)] = base + p < n ? v[i] : Op::id();
+        }
     }
     __syncthreads();
     int32_t vals[kScanItems];
@@ -198,26 +206,52 @@ __global__ void k_mark_rows(const int32_t *__restrict__ off, int32_t V, int32_t 
     }
 }
 
-__device__ __forceinline__ bool is_run_start(const int32_t *src, const int32_t *mark, int64_t e, int32_t N) {
-    if (e == 0 || mark[e] != 0) return true;
-    return (src[e] / N) != (src[e - 1] / N);
+// Edges per thread in the edge passes below. Each thread loads its edges (and
+// their predecessors) at indices clamped into [0, E) before it uses any of
+// them, so the loads are in flight together instead of one dependent round
+// trip per edge; threads past E drop their results.
+constexpr int kBItems = 8;
+constexpr int kBThreads = 256;
+
+__device__ __forceinline__ int64_t clamp_edge(int64_t e, int64_t E) { return e < E ? e : E - 1; }
+
+// Edge e starts a run (a subgraph row) when it is the first edge, the first
+// in-edge of its destination (mark != 0), or its source lies in another
+// segment than its predecessor's.
+__device__ __forceinline__ bool run_start(int64_t e, int32_t m, int32_t u, int32_t u_prev, int32_t N) {
+    return e == 0 || m != 0 || (u / N) != (u_prev / N);
 }
 
 // Query pass: per-segment edge counts and the number of runs (rows).
-__global__ __launch_bounds__(256) void k_count(const int32_t *__restrict__ src, const int32_t *__restrict__ mark,
-                                               int64_t E, int32_t N, int32_t k, int use_lds,
-                                               int32_t *__restrict__ seg_edges, unsigned long long *runs) {
+__global__ __launch_bounds__(kBThreads) void k_count(const int32_t *__restrict__ src,
+                                                     const int32_t *__restrict__ mark, int64_t E, int32_t N,
+                                                     int32_t k, int use_lds, int32_t *__restrict__ seg_edges,
+                                                     unsigned long long *runs) {
     extern __shared__ int32_t hist[];
     if (use_lds) {
         for (int s = threadIdx.x; s < k; s += blockDim.x) hist[s] = 0;
         __syncthreads();
     }
     unsigned long long nr = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-        int32_t s = src[e] / N;
-        if (use_lds) atomicAdd(&hist[s], 1);
-        else atomicAdd(&seg_edges[s], 1);
-        nr += is_run_start(src, mark, e, N) ? 1 : 0;
+    const int64_t stride = (int64_t)gridDim.x * kBThreads * kBItems;
+    for (int64_t e0 = (int64_t)blockIdx.x * kBThreads * kBItems + threadIdx.x; e0 < E; e0 += stride) {
+        int32_t m[kBItems], u[kBItems], up[kBItems];
+#pragma unroll
+        for (int j = 0; j < kBItems; ++j) {
+            const int64_t ec = clamp_edge(e0 + j * kBThreads, E);
+            m[j] = mark[ec];
+            u[j] = src[ec];
+            up[j] = src[ec > 0 ? ec - 1 : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < kBItems; ++j) {
+            const int64_t e = e0 + j * kBThreads;
+            if (e >= E) break;
+            const int32_t s = u[j] / N;
+            if (use_lds) atomicAdd(&hist[s], 1);
+            else atomicAdd(&seg_edges[s], 1);
+            nr += run_start(e, m[j], u[j], up[j], N) ? 1 : 0;
+        }
     }
     for (int d = 32; d >= 1; d >>= 1) nr += __shfl_down(nr, d, 64);
     if ((threadIdx.x & 63) == 0 && nr) atomicAdd(runs, nr);
@@ -228,26 +262,53 @@ __global__ __launch_bounds__(256) void k_count(const int32_t *__restrict__ src, 
     }
 }
 
-__global__ void k_flags(const int32_t *__restrict__ src, const int32_t *__restrict__ mark, int64_t E, int32_t N,
-                        int32_t *__restrict__ flag) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < E) flag[e] = is_run_start(src, mark, e, N) ? 1 : 0;
+__global__ __launch_bounds__(kBThreads) void k_flags(const int32_t *__restrict__ src,
+                                                     const int32_t *__restrict__ mark, int64_t E, int32_t N,
+                                                     int32_t *__restrict__ flag) {
+    const int64_t e0 = (int64_t)blockIdx.x * kBThreads * kBItems + threadIdx.x;
+    int32_t m[kBItems], u[kBItems], up[kBItems];
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t ec = clamp_edge(e0 + j * kBThreads, E);
+        m[j] = mark[ec];
+        u[j] = src[ec];
+        up[j] = src[ec > 0 ? ec - 1 : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t e = e0 + j * kBThreads;
+        if (e < E) flag[e] = run_start(e, m[j], u[j], up[j], N) ? 1 : 0;
+    }
 }
 
 // runincl[e] = 1 + run index of edge e; dstp1[e] = 1 + destination of edge e.
-__global__ void k_runs(const int32_t *__restrict__ src, const int32_t *__restrict__ dstp1,
-                       const int32_t *__restrict__ runincl, int64_t E, int32_t N, int32_t *__restrict__ run_first,
-                       int32_t *__restrict__ run_seg, int32_t *__restrict__ run_dst) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int32_t ri = runincl[e];
-    if (e == 0 || runincl[e - 1] != ri) {
-        int32_t r = ri - 1;
-        run_first[r] = (int32_t)e;
-        run_seg[r] = src[e] / N;
-        run_dst[r] = dstp1[e] - 1;
+__global__ __launch_bounds__(kBThreads) void k_runs(const int32_t *__restrict__ src,
+                                                    const int32_t *__restrict__ dstp1,
+                                                    const int32_t *__restrict__ runincl, int64_t E, int32_t N,
+                                                    int32_t *__restrict__ run_first, int32_t *__restrict__ run_seg,
+                                                    int32_t *__restrict__ run_dst) {
+    const int64_t e0 = (int64_t)blockIdx.x * kBThreads * kBItems + threadIdx.x;
+    int32_t ri[kBItems], rp[kBItems], u[kBItems], d[kBItems];
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t ec = clamp_edge(e0 + j * kBThreads, E);
+        ri[j] = runincl[ec];
+        rp[j] = runincl[ec > 0 ? ec - 1 : 0];
+        u[j] = src[ec];
+        d[j] = dstp1[ec];
     }
-    if (e == E - 1) run_first[ri] = (int32_t)E;
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t e = e0 + j * kBThreads;
+        if (e >= E) break;
+        if (e == 0 || rp[j] != ri[j]) {
+            const int32_t r = ri[j] - 1;
+            run_first[r] = (int32_t)e;
+            run_seg[r] = u[j] / N;
+            run_dst[r] = d[j] - 1;
+        }
+        if (e == E - 1) run_first[ri[j]] = (int32_t)E;
+    }
 }
 
 // Sort inputs of the runs: key = segment, value = destination << 32 | length.
@@ -263,15 +324,28 @@ __global__ void k_run_kv(const int32_t *__restrict__ run_first, const int32_t *_
 // Sort inputs of the edges: key = segment of the source, value = the edge word
 // (local source index, row-start flag on the first edge of each run).
 template <typename W>
-__global__ void k_edge_kv(const int32_t *__restrict__ src, const int32_t *__restrict__ runincl, int64_t E,
-                          int32_t N, uint16_t *__restrict__ key, W *__restrict__ val) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    const int32_t u = src[e], s = u / N;
-    const uint32_t local = (uint32_t)(u - s * N);
-    const bool start = e == 0 || runincl[e - 1] != runincl[e];
-    key[e] = (uint16_t)s;
-    val[e] = (W)(start ? (local | EdgeWord<W>::kFlag) : local);
+__global__ __launch_bounds__(kBThreads) void k_edge_kv(const int32_t *__restrict__ src,
+                                                       const int32_t *__restrict__ runincl, int64_t E, int32_t N,
+                                                       uint16_t *__restrict__ key, W *__restrict__ val) {
+    const int64_t e0 = (int64_t)blockIdx.x * kBThreads * kBItems + threadIdx.x;
+    int32_t u[kBItems], ri[kBItems], rp[kBItems];
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t ec = clamp_edge(e0 + j * kBThreads, E);
+        u[j] = src[ec];
+        ri[j] = runincl[ec];
+        rp[j] = runincl[ec > 0 ? ec - 1 : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const int64_t e = e0 + j * kBThreads;
+        if (e >= E) break;
+        const int32_t s = u[j] / N;
+        const uint32_t local = (uint32_t)(u[j] - s * N);
+        const bool start = e == 0 || rp[j] != ri[j];
+        key[e] = (uint16_t)s;
+        val[e] = (W)(start ? (local | EdgeWord<W>::kFlag) : local);
+    }
 }
 
 // Rows from the sorted runs; row_len[Q] = 0 closes the offsets' scan.
@@ -471,9 +545,9 @@ cagra_status query_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
         k_mark_rows<<<grid_for(V, 256), 256, 0, st>>>(g->in_offsets, V, mark);
         CAGRA_LAUNCH_CHECK();
         int use_lds = k <= 16384 ? 1 : 0;
-        unsigned grid = grid_for(E, 256 * 64);
+        unsigned grid = grid_for(E, kBThreads * kBItems * 8);
         if (grid > 4096) grid = 4096;
-        k_count<<<grid, 256, use_lds ? k * sizeof(int32_t) : 0, st>>>(g->in_sources, mark, E, N, k, use_lds,
+        k_count<<<grid, kBThreads, use_lds ? k * sizeof(int32_t) : 0, st>>>(g->in_sources, mark, E, N, k, use_lds,
                                                                       seg_edges, runs);
         CAGRA_LAUNCH_CHECK();
         unsigned long long hr = 0;
@@ -560,11 +634,12 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
     CAGRA_LAUNCH_CHECK();
     k_mark_rows<<<grid_for(V, 256), 256, 0, st>>>(g->in_offsets, V, mark);
     CAGRA_LAUNCH_CHECK();
-    k_flags<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, mark, E, N, flag);
+    k_flags<<<grid_for(E, kBThreads * kBItems), kBThreads, 0, st>>>(g->in_sources, mark, E, N, flag);
     CAGRA_LAUNCH_CHECK();
     if ((s = scan_i32<ScanMax>(mark, mark, E, true, ar, st)) != CAGRA_OK) return s;
     if ((s = scan_i32<ScanAdd>(flag, flag, E, true, ar, st)) != CAGRA_OK) return s;
-    k_runs<<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, mark, flag, E, N, run_first, run_seg, run_dst);
+    k_runs<<<grid_for(E, kBThreads * kBItems), kBThreads, 0, st>>>(g->in_sources, mark, flag, E, N, run_first,
+                                                                   run_seg, run_dst);
     CAGRA_LAUNCH_CHECK();
     // 2. stable radix sorts by segment: runs (with destination and length) and edges (with their words)
     const int bits = nbits_for(k);
@@ -574,13 +649,15 @@ cagra_status build_segments(const cagra_graph *g, cagra_segments *seg, void *ws,
         CAGRA_OK)
         return s;
     if (w16) {
-        k_edge_kv<uint16_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint16_t *)eval);
+        k_edge_kv<uint16_t><<<grid_for(E, kBThreads * kBItems), kBThreads, 0, st>>>(g->in_sources, flag, E, N, ekey,
+                                                                                    (uint16_t *)eval);
         CAGRA_LAUNCH_CHECK();
         if ((s = seg_sort_pairs<uint16_t>(ekey, (const uint16_t *)eval, ekey_s, (uint16_t *)seg->edge_src, E, bits,
                                           stmp, tmp_bytes, st)) != CAGRA_OK)
             return s;
     } else {
-        k_edge_kv<uint32_t><<<grid_for(E, 256), 256, 0, st>>>(g->in_sources, flag, E, N, ekey, (uint32_t *)eval);
+        k_edge_kv<uint32_t><<<grid_for(E, kBThreads * kBItems), kBThreads, 0, st>>>(g->in_sources, flag, E, N, ekey,
+                                                                                    (uint32_t *)eval);
         CAGRA_LAUNCH_CHECK();
         if ((s = seg_sort_pairs<uint32_t>(ekey, (const uint32_t *)eval, ekey_s, (uint32_t *)seg->edge_src, E, bits,
                                           stmp, tmp_bytes, st)) != CAGRA_OK)
