@@ -483,18 +483,18 @@ struct PageRankSolveOps {
     const void *dev_check() const { return sc[at.cur]; }
     size_t check_bytes() const { return 4 * sizeof(double); }
     bool switch_pending(int32_t ct) const { return ct == CAGRA_BF16 && p->switch_tol > 0.0; }
-    Verdict judge(const State &a, const void *hv, double *resid, cagra_status *err) const {
+    CheckOutcome decide(const State &a, const void *hv, double *resid, cagra_status *err) const {
         const double *h = static_cast<const double *>(hv);
         for (int c = 0; c < 4; ++c) res->scalars[c] = h[c];
         res->residual = *resid = h[1];
         if (h[3] != 0.0) {
             *err = fail(CAGRA_E_RANGE, "iteration %d: %g merge blocks held non-finite buffer values or an absolute "
                         "buffer mass beyond the exact fixed-point range", a.iters, h[3]);
-            return Verdict::kError;
+            return CheckOutcome::kError;
         }
-        if (h[1] < p->tol) return Verdict::kConverged;
-        if (switch_pending(a.ct) && h[1] < p->switch_tol) return Verdict::kSwitch;
-        return Verdict::kContinue;
+        if (h[1] < p->tol) return CheckOutcome::kConverged;
+        if (switch_pending(a.ct) && h[1] < p->switch_tol) return CheckOutcome::kSwitch;
+        return CheckOutcome::kContinue;
     }
     bool may_end(double pred) const {
         return pred < 2.0 * p->tol || (switch_pending(at.ct) && pred < 2.0 * p->switch_tol);
@@ -594,11 +594,11 @@ struct LabelpropSolveOps {
     }
     const void *dev_check() const { return changed; }
     size_t check_bytes() const { return sizeof(int32_t); }
-    Verdict judge(const State &, const void *hv, double *resid, cagra_status *) const {
+    CheckOutcome decide(const State &, const void *hv, double *resid, cagra_status *) const {
         const int32_t n = *static_cast<const int32_t *>(hv);
         res->changed = n;
         *resid = (double)n;
-        return n == 0 ? Verdict::kConverged : Verdict::kContinue;
+        return n == 0 ? CheckOutcome::kConverged : CheckOutcome::kContinue;
     }
     bool may_end(double pred) const { return pred < 2.0; }
     cagra_status switch_precision() { return CAGRA_OK; }
@@ -819,7 +819,7 @@ struct PprSolveOps {
     }
     const void *dev_check() const { return sc[at.cur]; }
     size_t check_bytes() const { return (size_t)ncols * 4 * sizeof(double); }
-    Verdict judge(const State &, const void *hv, double *resid, cagra_status *) const {
+    CheckOutcome decide(const State &, const void *hv, double *resid, cagra_status *) const {
         const double *h = static_cast<const double *>(hv);
         double worst = 0.0;
         for (int j = 0; j < ncols; ++j) {
@@ -828,7 +828,7 @@ struct PprSolveOps {
             if (isnan(r)) break;
         }
         res->residual = *resid = worst;
-        return worst < p->tol ? Verdict::kConverged : Verdict::kContinue;
+        return worst < p->tol ? CheckOutcome::kConverged : CheckOutcome::kContinue;
     }
     bool may_end(double pred) const { return pred < 2.0 * p->tol; }
     cagra_status switch_precision() { return CAGRA_OK; }

@@ -87,7 +87,7 @@ class ReadbackLease {
     Readback *rb_ = nullptr;
 };
 
-enum class Verdict { kContinue, kConverged, kSwitch, kError };
+enum class CheckOutcome { kContinue, kConverged, kSwitch, kError };
 
 // The residual expected at the next check: the last one read back times the
 // last ratio between consecutive checks (at most 1); infinite before any.
@@ -106,7 +106,7 @@ inline double predict_residual(double r_last, double r_prev) {
 //                                                      the device values to read
 //                                                      back after the current
 //                                                      iterate (<= kReadbackBytes);
-//   Verdict judge(const State &at, const void *h, double *residual,
+//   CheckOutcome decide(const State &at, const void *h, double *residual,
 //                 cagra_status *err)                   decides from the values h
 //                                                      read back at position at
 //                                                      (kError sets *err);
@@ -161,10 +161,10 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
             break;
         }
         double resid = INFINITY;
-        const Verdict v = ops.judge(q[0].at, rb->host + (size_t)q[0].slot * kReadbackBytes, &resid, &err);
+        const CheckOutcome v = ops.decide(q[0].at, rb->host + (size_t)q[0].slot * kReadbackBytes, &resid, &err);
         r_prev = r_last;
         r_last = resid;
-        if (v == Verdict::kContinue) {
+        if (v == CheckOutcome::kContinue) {
             if (q[0].at.iters >= max_iters) break;  // the cap's check (nothing is queued after it)
             q[0] = q[1];
             --nq;
@@ -172,11 +172,11 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
         }
         ops.restore(q[0].at);  // back to the checked iterate; anything queued after it is dropped
         nq = 0;
-        if (v == Verdict::kConverged) {
+        if (v == CheckOutcome::kConverged) {
             converged = true;
             break;
         }
-        if (v == Verdict::kError) break;
+        if (v == CheckOutcome::kError) break;
         if ((err = ops.switch_precision()) != CAGRA_OK) break;
         if (ops.iters() >= max_iters) break;  // switched at the cap's check
     }
