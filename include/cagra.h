@@ -525,6 +525,28 @@ cagra_status cagra_labelprop_solve(const cagra_segments *seg, int32_t max_iters,
                                    void *workspace, size_t workspace_bytes, cagra_lp_result *host_result,
                                    hipStream_t stream);
 
+/*
+ * The fixed-point loops of cagra_pagerank_solve and cagra_labelprop_solve
+ * with push-direction steps (cagra_pagerank_push_iter,
+ * cagra_labelprop_push_iter): same loop, same stopping rules, same results
+ * as a loop of those steps that waits at every check; the stream is
+ * synchronized before the call returns. cagra_pagerank_push_solve takes
+ * cagra_pr_params with contrib_type CAGRA_F32, switch_tol 0 and
+ * restart_vertex -1 (the push iteration has FP32 contributions and the
+ * uniform teleport); its contribution pair is float[V] and vals, workspace
+ * are those of the push steps (the workspace must also hold the
+ * cagra_pagerank_init temporaries). The result is in buffer
+ * host_result->final_buf of each pair.
+ */
+cagra_status cagra_pagerank_push_solve(const cagra_graph *g, const cagra_segments *seg_t, const cagra_pr_params *params,
+                                       float *rank0, float *rank1, float *contrib0, float *contrib1, double *scalars,
+                                       float *vals, void *workspace, size_t workspace_bytes,
+                                       cagra_pr_result *host_result, hipStream_t stream);
+cagra_status cagra_labelprop_push_solve(const cagra_segments *seg_t, int32_t max_iters, int32_t check_every,
+                                        int32_t *labels0, int32_t *labels1, int32_t *vals, int32_t *changed,
+                                        void *workspace, size_t workspace_bytes, cagra_lp_result *host_result,
+                                        hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Personalized PageRank for many restart vertices (segmented SpMM)          */
 /* ------------------------------------------------------------------------ */

@@ -51,6 +51,7 @@ EXPORTS = [
     "cagra_bc_forward_level", "cagra_bc_backward_level", "cagra_query_workspace_bytes", "cagra_build_segments", "cagra_iter_workspace_bytes",
     "cagra_segment_gather", "cagra_merge", "cagra_pagerank_init", "cagra_pagerank_iter",
     "cagra_push_workspace_bytes", "cagra_pagerank_push_iter", "cagra_labelprop_push_iter",
+    "cagra_pagerank_push_solve", "cagra_labelprop_push_solve",
     "cagra_validate_workspace_bytes", "cagra_validate_graph",
     "cagra_pagerank_merge", "cagra_pagerank_solve", "cagra_noalloc_scratch_bytes", "cagra_pagerank_iter_noalloc",
     "cagra_labelprop_iter", "cagra_labelprop_solve", "cagra_ppr_workspace_bytes", "cagra_ppr_init",
@@ -170,6 +171,10 @@ def lib():
             "cagra_pagerank_push_iter": ([GP, SP, _c_dbl, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
                                           _c_size, st], ctypes.c_int),
             "cagra_labelprop_push_iter": ([SP, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
+            "cagra_pagerank_push_solve": ([GP, SP, ctypes.POINTER(CPrParams), _c_vp, _c_vp, _c_vp, _c_vp, _c_vp,
+                                           _c_vp, _c_vp, _c_size, ctypes.POINTER(CPrResult), st], ctypes.c_int),
+            "cagra_labelprop_push_solve": ([SP, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_size,
+                                            ctypes.POINTER(CLpResult), st], ctypes.c_int),
             "cagra_ppr_workspace_bytes": ([SP], _c_size),
             "cagra_features_workspace_bytes": ([SP], _c_size),
             "cagra_degree_features": ([GP, SP, _c_vp, _c_vp, _c_size, st], ctypes.c_int),
@@ -626,7 +631,8 @@ class PushPageRankState:
         self.dg, self.seg_t = dg, seg_t
         self.rank = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
         self.contrib = [torch.empty(V, dtype=torch.float32, device=dev) for _ in range(2)]
-        self.scalars = [torch.zeros(4, dtype=torch.float64, device=dev) for _ in range(2)]
+        self._sc = torch.zeros(8, dtype=torch.float64, device=dev)  # the pair, back to back
+        self.scalars = [self._sc[:4], self._sc[4:]]
         self.vals = torch.empty(max(seg_t.Q, 1), dtype=torch.float32, device=dev)
         self.ws = push_workspace(seg_t)
         self.cur = 0
@@ -654,20 +660,28 @@ class PushPageRankState:
         return self.scalars[self.cur]
 
 
-def pagerank_push(dg: DeviceGraph, seg_t: Segments, iters: int = 20, damping: float = 0.85, tol: float = 0.0):
-    """Push-direction power iteration; returns (rank tensor, residual list or None, steps)."""
+def pagerank_push(dg: DeviceGraph, seg_t: Segments, iters: int = 20, damping: float = 0.85, tol: float = 0.0,
+                  check_every: int = 1):
+    """Push-direction power iteration; fixed `iters` steps (tol 0), or through
+    cagra_pagerank_push_solve to the first L1 residual < tol read back every
+    `check_every` steps (at most `iters`). Returns (rank tensor, residual list or
+    None, steps): the list is None in fixed mode, else [last residual read]."""
     stt = PushPageRankState(dg, seg_t)
+    if tol > 0:
+        p = CPrParams(damping, tol, 0.0, -1, iters, check_every, F32)
+        r = CPrResult()
+        stt.rank[0].fill_(1.0 / dg.V)
+        st = lib().cagra_pagerank_push_solve(ctypes.byref(dg.c), ctypes.byref(seg_t.c), ctypes.byref(p),
+                                             _ptr(stt.rank[0]), _ptr(stt.rank[1]), _ptr(stt.contrib[0]),
+                                             _ptr(stt.contrib[1]), _ptr(stt._sc), _ptr(stt.vals), _ptr(stt.ws),
+                                             stt.ws.numel(), ctypes.byref(r), None)
+        if st not in (OK, E_NOT_CONVERGED):
+            _check(st, "cagra_pagerank_push_solve")
+        return stt.rank[r.final_buf].clone(), [float(r.residual)], int(r.iters)
     stt.start()
-    res, steps = [], 0
     for _ in range(iters):
         stt.step(damping)
-        steps += 1
-        if tol > 0:
-            r = float(stt.scalars_now[1].item())
-            res.append(r)
-            if r < tol:
-                break
-    return stt.rank_now.clone(), (res if tol > 0 else None), steps
+    return stt.rank_now.clone(), None, iters
 
 
 def labelprop_push(seg_t: Segments, max_iters: int = 1 << 20):
@@ -680,14 +694,12 @@ def labelprop_push(seg_t: Segments, max_iters: int = 1 << 20):
     vals = torch.empty(max(seg_t.Q, 1), dtype=torch.int32, device=dev)
     changed = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = push_workspace(seg_t)
-    cur, it = 0, 0
-    while it < max_iters:
-        labelprop_push_iter(seg_t, lab[cur], vals, lab[1 - cur], changed, ws)
-        cur = 1 - cur
-        it += 1
-        if int(changed.item()) == 0:
-            break
-    return lab[cur], it
+    r = CLpResult()
+    st = lib().cagra_labelprop_push_solve(ctypes.byref(seg_t.c), max_iters, 1, _ptr(lab[0]), _ptr(lab[1]),
+                                          _ptr(vals), _ptr(changed), _ptr(ws), ws.numel(), ctypes.byref(r), None)
+    if st not in (OK, E_NOT_CONVERGED):
+        _check(st, "cagra_labelprop_push_solve")
+    return lab[r.final_buf], int(r.iters)
 
 
 # --------------------------------------------------------------------------- batched personalized PageRank

@@ -464,6 +464,7 @@ struct PageRankSolveOps {
     hipStream_t st;
     cagra_pr_result *res;
     State at{0, 0, 0, CAGRA_F32};
+    bool push = false;  // push direction: seg is the reverse graph's segmentation, partial its vals
 
     State state() const { return at; }
     void restore(const State &s) { at = s; }
@@ -471,6 +472,14 @@ struct PageRankSolveOps {
     cagra_status step() {
         cagra_status s;
         const int c = at.cur;
+        if (push) {
+            if ((s = launch_pr_push(g, seg, p->damping, rank[c], static_cast<const float *>(contrib[c]), sc[c], partial,
+                                    rank[1 - c], static_cast<float *>(contrib[1 - c]), sc[1 - c], ws, st)) != CAGRA_OK)
+                return s;
+            at.cur = 1 - c;
+            ++at.iters;
+            return CAGRA_OK;
+        }
         if ((s = launch_gather(seg, CAGRA_SUM_F32, at.ct, contrib[c], partial, st)) != CAGRA_OK) return s;
         if ((s = launch_merge_pr(g, seg, p->damping, p->restart_vertex, at.ct, rank[c], sc[c], partial, rank[1 - c],
                                  contrib[1 - c], sc[1 - c], ws, st)) != CAGRA_OK)
@@ -579,12 +588,20 @@ struct LabelpropSolveOps {
     hipStream_t st;
     cagra_lp_result *res;
     State at{0, 0};
+    bool push = false;  // push direction: seg is the reverse graph's segmentation, partial its vals
 
     State state() const { return at; }
     void restore(const State &s) { at = s; }
     int32_t iters() const { return at.iters; }
     cagra_status step() {
         const int c = at.cur;
+        if (push) {
+            cagra_status s = launch_lp_push(seg, lab[c], partial, lab[1 - c], changed, ws, st);
+            if (s != CAGRA_OK) return s;
+            at.cur = 1 - c;
+            ++at.iters;
+            return CAGRA_OK;
+        }
         cagra_status s = launch_gather(seg, CAGRA_MIN_I32, CAGRA_I32, lab[c], partial, st);
         if (s != CAGRA_OK) return s;
         if ((s = launch_merge_lp(seg, lab[c], partial, lab[1 - c], changed, ws, st)) != CAGRA_OK) return s;
@@ -916,6 +933,69 @@ cagra_status cagra_labelprop_push_iter(const cagra_segments *seg_t, const int32_
     if ((s = check_push(seg_t, 4, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
     if (!labels_in || !labels_out || !changed_out) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
     return launch_lp_push(seg_t, labels_in, vals, labels_out, changed_out, workspace, stream);
+}
+
+cagra_status cagra_pagerank_push_solve(const cagra_graph *g, const cagra_segments *seg_t, const cagra_pr_params *p,
+                                       float *rank0, float *rank1, float *contrib0, float *contrib1, double *scalars,
+                                       float *vals, void *workspace, size_t workspace_bytes,
+                                       cagra_pr_result *host_result, hipStream_t stream) {
+    cagra_status s;
+    if (!p || !host_result) return fail(CAGRA_E_INVALID, "params or host_result is NULL");
+    if ((s = check_graph(g, true)) != CAGRA_OK) return s;
+    if ((s = check_push(seg_t, 8, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (seg_t->V != g->V || seg_t->E != g->E)
+        return fail(CAGRA_E_INVALID, "segments belong to a graph of another size");
+    if (!(p->damping >= 0.0 && p->damping <= 1.0)) return fail(CAGRA_E_INVALID, "damping must be in [0, 1]");
+    if (!(p->tol > 0.0)) return fail(CAGRA_E_INVALID, "tol must be > 0");
+    if (p->max_iters < 1 || p->check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
+    if (p->contrib_type != CAGRA_F32 || p->switch_tol != 0.0 || p->restart_vertex != -1)
+        return fail(CAGRA_E_INVALID, "the push solve runs FP32 contributions, no switch, uniform teleport");
+    if (!rank0 || !rank1 || !contrib0 || !contrib1 || !scalars)
+        return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (rank0 == rank1 || contrib0 == contrib1) return fail(CAGRA_E_INVALID, "the two buffers of a pair must differ");
+    const size_t need_init = (size_t)init_blocks(g->V) * 4 * sizeof(double) + 256;
+    if (workspace_bytes < need_init)
+        return fail(CAGRA_E_BUFFER, "workspace needs %zu bytes (got %zu)", need_init, workspace_bytes);
+    *host_result = cagra_pr_result{};
+    PageRankSolveOps ops{g, seg_t, p, {rank0, rank1}, {contrib0, contrib1}, {scalars, scalars + 4}, vals, workspace,
+                         stream, host_result};
+    ops.push = true;
+    if ((s = launch_pr_init(g, CAGRA_F32, rank0, contrib0, scalars, workspace, stream)) != CAGRA_OK) return s;
+    double h[4];
+    if ((s = read_scalars(scalars, h, stream)) != CAGRA_OK) return s;
+    for (int c = 0; c < 4; ++c) host_result->scalars[c] = h[c];
+    host_result->residual = INFINITY;
+    if (h[3] != 0.0) return fail(CAGRA_E_RANGE, "the start vector holds %.0f non-finite values", h[3]);
+    s = pipelined_solve(ops, p->max_iters, p->check_every, stream);
+    host_result->iters = ops.at.iters;
+    host_result->final_buf = ops.at.cur;
+    if (s == CAGRA_E_NOT_CONVERGED)
+        return fail(CAGRA_E_NOT_CONVERGED, "no L1 residual below %g within %d iterations (last %g)", p->tol,
+                    p->max_iters, host_result->residual);
+    return s;
+}
+
+cagra_status cagra_labelprop_push_solve(const cagra_segments *seg_t, int32_t max_iters, int32_t check_every,
+                                        int32_t *labels0, int32_t *labels1, int32_t *vals, int32_t *changed,
+                                        void *workspace, size_t workspace_bytes, cagra_lp_result *host_result,
+                                        hipStream_t stream) {
+    cagra_status s;
+    if (!host_result) return fail(CAGRA_E_INVALID, "host_result is NULL");
+    if ((s = check_push(seg_t, 4, vals, workspace_bytes, workspace)) != CAGRA_OK) return s;
+    if (max_iters < 1 || check_every < 1) return fail(CAGRA_E_INVALID, "max_iters and check_every must be >= 1");
+    if (!labels0 || !labels1 || !changed) return fail(CAGRA_E_INVALID, "a vector argument is NULL");
+    if (labels0 == labels1) return fail(CAGRA_E_INVALID, "the two label buffers must differ");
+    *host_result = cagra_lp_result{};
+    host_result->changed = -1;
+    LabelpropSolveOps ops{seg_t, {labels0, labels1}, vals, changed, workspace, stream, host_result};
+    ops.push = true;
+    s = pipelined_solve(ops, max_iters, check_every, stream);
+    host_result->iters = ops.at.iters;
+    host_result->final_buf = ops.at.cur;
+    if (s == CAGRA_E_NOT_CONVERGED)
+        return fail(CAGRA_E_NOT_CONVERGED, "labels still changed (%d) after %d iterations", host_result->changed,
+                    max_iters);
+    return s;
 }
 
 size_t cagra_validate_workspace_bytes(void) { return validate_ws_bytes(); }

@@ -321,3 +321,47 @@ def test_labelprop_solve_validation(cagra):
     assert call(wsb=ws - 1) == cagra.E_BUFFER
     assert call(wsp=None) == cagra.E_BUFFER
     assert L.cagra_last_error()
+
+
+def test_push_solve_validation(cagra):
+    """The push-direction solves reject bad arguments before any HIP call."""
+    L = cagra.lib()
+    s = _fake_built(cagra)
+    g = _graph(cagra, V=100, E=50)
+    ws = L.cagra_push_workspace_bytes(ctypes.byref(s))
+    res = cagra.CPrResult()
+
+    def P(**kw):
+        d = dict(damping=0.85, tol=1e-6, switch_tol=0.0, restart=-1, max_iters=100, check_every=1,
+                 contrib_type=cagra.F32)
+        d.update(kw)
+        return cagra.CPrParams(d["damping"], d["tol"], d["switch_tol"], d["restart"], d["max_iters"],
+                               d["check_every"], d["contrib_type"])
+
+    def call(p, r0=1, r1=2, c0=3, c1=4, sc=5, vals=6, wsp=7, wsb=ws, result=res):
+        return L.cagra_pagerank_push_solve(ctypes.byref(g), ctypes.byref(s), None if p is None else ctypes.byref(p),
+                                           r0, r1, c0, c1, sc, vals, wsp, wsb,
+                                           None if result is None else ctypes.byref(result), None)
+    assert call(None) == cagra.E_INVALID
+    assert call(P(), result=None) == cagra.E_INVALID
+    assert call(P(tol=0.0)) == cagra.E_INVALID
+    assert call(P(max_iters=0)) == cagra.E_INVALID
+    assert call(P(contrib_type=cagra.BF16)) == cagra.E_INVALID    # push gathers FP32 contributions
+    assert call(P(switch_tol=1e-3)) == cagra.E_INVALID
+    assert call(P(restart=3)) == cagra.E_INVALID                  # uniform teleport only
+    assert call(P(), r1=1) == cagra.E_INVALID
+    assert call(P(), sc=None) == cagra.E_INVALID
+    assert call(P(), vals=None) == cagra.E_INVALID
+    assert call(P(), wsb=ws - 1) == cagra.E_BUFFER
+    lres = cagra.CLpResult()
+
+    def lcall(mi=100, every=1, l0=1, l1=2, vals=3, ch=4, wsp=5, wsb=ws, result=lres):
+        return L.cagra_labelprop_push_solve(ctypes.byref(s), mi, every, l0, l1, vals, ch, wsp, wsb,
+                                            None if result is None else ctypes.byref(result), None)
+    assert lcall(result=None) == cagra.E_INVALID
+    assert lcall(mi=0) == cagra.E_INVALID
+    assert lcall(l1=1) == cagra.E_INVALID
+    assert lcall(ch=None) == cagra.E_INVALID
+    assert lcall(vals=None) == cagra.E_INVALID
+    assert lcall(wsb=ws - 1) == cagra.E_BUFFER
+    assert L.cagra_last_error()

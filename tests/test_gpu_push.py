@@ -171,3 +171,53 @@ def test_labelprop_push_bit_exact(cagra, scale, ef, seed, N, B, T):
     want, it_ref = oracle.labelprop(gs)
     assert np.array_equal(lab.cpu().numpy(), want)
     assert it == it_ref
+
+
+@pytest.mark.parametrize("tol,max_iters,every", [(1e-6, 100, 1), (1e-7, 100, 3), (1e-6, 4, 1), (1e-1, 100, 1)])
+def test_push_solve_equals_the_waiting_loop(cagra, tol, max_iters, every):
+    """cagra_pagerank_push_solve stops where a loop of push steps that reads the
+    residual at every check stops, with the same ranks bit for bit; converged,
+    it is within the contraction bound of the oracle's fixed point."""
+    g = graphgen.rmat_graph(12, 8, 5)
+    dg, dgt, seg_t = push_segs(cagra, g, 1024, 512, 4096)
+    r, res, it = cagra.pagerank_push(dg, seg_t, iters=max_iters, tol=tol, check_every=every)
+    st = cagra.PushPageRankState(dg, seg_t)
+    st.start()
+    n, resid = 0, float("inf")
+    while n < max_iters:
+        st.step(D)
+        n += 1
+        if n % every and n < max_iters:
+            continue
+        resid = float(st.scalars_now[1].item())
+        if resid < tol:
+            break
+    print(f"push solve: {it} iterations (waiting loop {n}), residual {res[0]:.3e}")
+    assert it == n and res[0] == resid
+    assert np.array_equal(r.cpu().numpy(), st.rank_now.cpu().numpy())
+    if resid < tol and tol <= 1e-6:
+        star, _ = oracle.pagerank(g, iters=400, tol=1e-14)
+        assert np.abs(r.double().cpu().numpy() - star).sum() <= D / (1 - D) * tol + 1e-6
+
+
+def test_labelprop_push_solve_equals_the_waiting_loop(cagra):
+    """cagra_labelprop_push_solve: the labels and count of a loop of push
+    steps that reads the change count after every step."""
+    import torch
+    gs = graphgen.symmetrize(graphgen.rmat_graph(12, 4, 6))
+    dg = cagra.DeviceGraph.from_host(gs)
+    seg = cagra.build_segments(dg, 1024, 512, 4096)
+    lab, it = cagra.labelprop_push(seg)
+    cur = torch.arange(gs.V, dtype=torch.int32, device="cuda")
+    nxt = torch.empty_like(cur)
+    vals = torch.empty(max(seg.Q, 1), dtype=torch.int32, device="cuda")
+    ch = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = cagra.push_workspace(seg)
+    n = 0
+    while True:
+        cagra.labelprop_push_iter(seg, cur, vals, nxt, ch, ws)
+        cur, nxt = nxt, cur
+        n += 1
+        if int(ch.item()) == 0:
+            break
+    assert it == n and torch.equal(lab, cur)
