@@ -129,7 +129,7 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
     cagra_status s = lease.acquire();
     if (s != CAGRA_OK) return s;
     Readback *rb = lease.get();
-    Check q[2];
+    Check q[2] = {};
     int nq = 0, slot = 0;
     double r_last = INFINITY, r_prev = INFINITY;
     cagra_status err = CAGRA_OK;
@@ -166,7 +166,7 @@ cagra_status pipelined_solve(Ops &ops, int32_t max_iters, int32_t check_every, h
         r_last = resid;
         if (v == CheckOutcome::kContinue) {
             if (q[0].at.iters >= max_iters) break;  // the cap's check (nothing is queued after it)
-            q[0] = q[1];
+            if (nq == 2) q[0] = q[1];
             --nq;
             continue;
         }
