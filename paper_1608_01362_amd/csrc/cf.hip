@@ -4,10 +4,12 @@
 // Merge = vector sum, VertexUpdate x_v + gamma (g_v - lambda x_v): gradient
 // descent on 1/2 sum_ratings (r - <x_u, x_i>)^2 + lambda/2 sum |x|^2.
 //
-// Layout as for batched personalized PageRank: [V][64] FP32 vertex vectors,
-// lane j of a wave owns factor j, so each source row is one 256-byte load and
-// each buffer row one 256-byte store; the dot product of an edge is a DPP
-// reduction across the wave. Segments are sized for L2 or the Infinity Cache
+// Layout as for batched personalized PageRank: [V][64] FP32 vertex vectors.
+// In the gather a 16-lane group handles one edge at a time, lane i owning
+// factors 4i..4i+3, so each source row is one 16-byte load per lane and each
+// buffer row one 16-byte store per lane; the dot product of an edge is four
+// FMAs and a DPP reduction across the group's 16 lanes. In the merge lane j of
+// a wave owns factor j. Segments are sized for L2 or the Infinity Cache
 // (256 bytes per vertex). Edge values travel in the segmented edge order,
 // produced once by k_edge_values.
 #include "common.h"
@@ -17,7 +19,6 @@ namespace cagra {
 constexpr int kCfK = CAGRA_CF_FACTORS;
 constexpr int kCfWaves = CAGRA_TILE_WAVES;
 constexpr int kCfThreads = kCfWaves * kWave;
-constexpr int kCfBatch = 16;         // source rows loaded ahead per wave
 constexpr int kCfMergeBatch = 8;    // merge rows / vertices per wave whose loads are in flight together
 constexpr int kEdgesPerThread = 16;  // edge-value permutation
 
@@ -85,102 +86,182 @@ cagra_status launch_edge_values(const cagra_graph *g, const cagra_segments *seg,
 
 // ---------------------------------------------------------------- gather
 
-// Sum over the 64 lanes, returned to every lane.
-__device__ __forceinline__ float wave_sum_all(float x) {
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, true));  // row_shr:1
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, true));  // row_shr:2
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, true));  // row_shr:4
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, true));  // row_shr:8
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false));  // row_bcast:15
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false));  // row_bcast:31
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+// Lanes of an edge group: the 16 lanes of one DPP row, 4 factors each (one
+// 16-byte load of a 256-byte vertex row per lane).
+constexpr int kGroup = 16;
+constexpr int kGroupsPerWave = kWave / kGroup;
+constexpr int kCfGroups = kCfWaves * kGroupsPerWave;
+constexpr int kGroupBatch = 4;  // edges per window: source rows a group loads together
+static_assert(kGroupBatch == 4, "the broadcasts below are written out for four edges");
+static_assert(kCfK == kGroup * 4, "four factors per lane of a group");
+
+// Sum over the 16 lanes of a DPP row, returned to each of them: pairs, quads
+// (quad_perm), halves (row_half_mirror), the row (row_mirror).
+__device__ __forceinline__ float row16_sum(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));   // [1,0,3,2]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xf, 0xf, false));   // [2,3,0,1]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf, 0xf, false));  // half mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf, 0xf, false));  // mirror
+    return x;
 }
 
-// One tile per workgroup; each wave streams an equal share of the tile's edges.
-// A row's partial gradient is written when the row closes inside the share;
-// rows that continue across shares are completed after a barrier in wave order.
+// Lane j of each 16-lane group, to every lane of the group (ds_swizzle bit
+// mode: lane id bits 4 kept, bits 0-3 set to j, within each 32-lane half).
+template <int J>
+__device__ __forceinline__ int32_t group_bcast(int32_t v) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x10 | (J << 5));
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+    return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
+}
+
+// One tile per workgroup; each wave takes an equal share of the tile's edges
+// and each of its four 16-lane groups an equal part of the share, walked one
+// edge at a time (lane i holds factors 4i..4i+3). A row's partial gradient is
+// written when the row closes inside the part; rows that continue across parts
+// are completed after a barrier in part order. The row open at a part's start
+// is the share's open row advanced by the row starts before the part.
 template <typename W>
 __global__ __launch_bounds__(kCfThreads) void k_cf_gather(
     const W *__restrict__ edge_src, const float *__restrict__ vals, const int32_t *__restrict__ tile_edge,
     const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const int32_t *__restrict__ row_dst,
     const float *__restrict__ X, int32_t N, int32_t ntiles, float *__restrict__ partial,
     double *__restrict__ tile_sq) {
-    __shared__ float fix_head[kCfWaves][kCfK];
-    __shared__ float fix_last[kCfWaves][kCfK];
-    __shared__ int32_t fix_row[kCfWaves];
-    __shared__ int32_t fix_has[kCfWaves];
-    __shared__ double red_sq[kCfWaves];
+    __shared__ float4 fix_head[kCfGroups][kGroup];
+    __shared__ float4 fix_last[kCfGroups][kGroup];
+    __shared__ int32_t fix_row[kCfGroups];
+    __shared__ int32_t fix_has[kCfGroups];
+    __shared__ double red_sq[kCfGroups];
 
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int64_t e0 = tile_edge[t], e1 = tile_edge[t + 1];
+    if (e0 >= e1) {  // an empty tile (uniform over the workgroup): nothing to read
+        if (threadIdx.x == 0) tile_sq[t] = 0.0;
+        return;
+    }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane >> 4, sub = lane & 15, G = w * kGroupsPerWave + g;
     const int64_t vbase = (int64_t)tile_seg[t] * N;
     const int64_t sl = (e1 - e0 + kCfWaves - 1) / kCfWaves;
     int64_t w0 = e0 + w * sl;
     if (w0 > e1) w0 = e1;
     int64_t w1 = w0 + sl;
     if (w1 > e1) w1 = e1;
-    int32_t row = span_row[(int64_t)t * kCfWaves + w] - 1;  // row open at the share's start
+    // the group's part [a, b) of the share
+    const int64_t gl = (w1 - w0 + kGroupsPerWave - 1) / kGroupsPerWave;
+    int64_t a = w0 + g * gl;
+    if (a > w1) a = w1;
+    int64_t b = a + gl;
+    if (b > w1) b = w1;
+    // row starts in [w0, a) for each group: the wave counts them in 64-edge
+    // chunks up to the last group's start
+    int32_t before = 0;
+    {
+        int64_t a_last = w0 + (kGroupsPerWave - 1) * gl;
+        if (a_last > w1) a_last = w1;
+        int32_t c1 = 0, c2 = 0, c3 = 0;
+        for (int64_t c0 = w0; c0 < a_last; c0 += kWave) {
+            const int64_t e = c0 + lane;
+            const bool f = e < a_last && ((uint32_t)edge_src[e < a_last ? e : c0] & EdgeWord<W>::kFlag);
+            const uint64_t m = __ballot(f);
+            // positions below each group's start
+            const int64_t s1 = w0 + gl - c0, s2 = w0 + 2 * gl - c0, s3 = w0 + 3 * gl - c0;
+            auto below = [&](int64_t n) -> int32_t {
+                if (n <= 0) return 0;
+                if (n >= 64) return __builtin_popcountll(m);
+                return __builtin_popcountll(m & ((1ull << n) - 1ull));
+            };
+            c1 += below(s1);
+            c2 += below(s2);
+            c3 += below(s3);
+        }
+        before = g == 0 ? 0 : (g == 1 ? c1 : (g == 2 ? c2 : c3));
+    }
+    int32_t row = span_row[(int64_t)t * kCfWaves + w] - 1 + before;  // row open at the part's start
     int32_t seen = 0;
-    float acc = 0.0f, head = 0.0f, xv = 0.0f;
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f), xv = acc;
+    float sqf = 0.0f;
     double sq = 0.0;
-    // the share starts inside a row (never the case for wave 0: tiles start on rows)
-    if (w0 < w1 && !((uint32_t)edge_src[w0] & EdgeWord<W>::kFlag))
-        xv = X[(int64_t)row_dst[row] * kCfK + lane];
-    const float *xs = X + vbase * kCfK + lane;
+    const float4 *X4 = reinterpret_cast<const float4 *>(X);
+    // the part starts inside a row (never the case for the tile's first part: tiles start on rows)
+    if (a < b && !((uint32_t)edge_src[a] & EdgeWord<W>::kFlag)) xv = X4[(int64_t)row_dst[row] * kGroup + sub];
+    const float4 *xs = X4 + vbase * kGroup + sub;
 
-    for (int64_t b0 = w0; b0 < w1; b0 += kWave) {
-        const int64_t e = b0 + lane;
-        const uint32_t word = e < w1 ? (uint32_t)edge_src[e] : 0u;
-        const float val = e < w1 ? vals[e] : 0.0f;
-        const int n = (int)(w1 - b0 < kWave ? w1 - b0 : kWave);
-        for (int jb = 0; jb < n; jb += kCfBatch) {
-            uint32_t wv[kCfBatch];
-            float x[kCfBatch];
+    // lane j < kGroupBatch of the group holds the word and rating of edge
+    // o + j of the current window; the next window's are loaded one window ahead
+    auto edge_at = [&](int64_t o) -> int64_t {
+        const int64_t ej = a + o + (sub & (kGroupBatch - 1));
+        const int64_t ec = ej < b ? ej : (a < b ? a : e0);
+        return ec < e1 ? ec : e0;
+    };
+    int64_t ecur = edge_at(0);
+    int32_t word = (int32_t)(uint32_t)edge_src[ecur];
+    float val = vals[ecur];
+    for (int64_t o = 0; o < gl; o += kGroupBatch) {
+        const int64_t enxt = edge_at(o + kGroupBatch);
+        const int32_t word_n = (int32_t)(uint32_t)edge_src[enxt];
+        const float val_n = vals[enxt];
+        uint32_t wv[kGroupBatch];
+        float rv[kGroupBatch];
+        float4 x[kGroupBatch];
+        const int32_t vi = __float_as_int(val);
 #pragma unroll
-            for (int u = 0; u < kCfBatch; ++u) {
-                wv[u] = (uint32_t)__builtin_amdgcn_readlane((int32_t)word, jb + u);
-                x[u] = xs[(int64_t)(wv[u] & EdgeWord<W>::kIndex) * kCfK];
-            }
+        for (int j = 0; j < kGroupBatch; ++j) {
+            wv[j] = (uint32_t)(j == 0 ? group_bcast<0>(word) : j == 1 ? group_bcast<1>(word)
+                                : j == 2 ? group_bcast<2>(word) : group_bcast<3>(word));
+            rv[j] = __int_as_float(j == 0 ? group_bcast<0>(vi) : j == 1 ? group_bcast<1>(vi)
+                                   : j == 2 ? group_bcast<2>(vi) : group_bcast<3>(vi));
+            x[j] = xs[(int64_t)(wv[j] & EdgeWord<W>::kIndex) * kGroup];
+        }
 #pragma unroll
-            for (int u = 0; u < kCfBatch; ++u) {
-                if (jb + u < n) {
-                    if (wv[u] & EdgeWord<W>::kFlag) {  // a row starts: the open row is complete
-                        if (seen) partial[(int64_t)row * kCfK + lane] = acc;
-                        else head = acc;
-                        seen = 1;
-                        ++row;
-                        acc = 0.0f;
-                        xv = X[(int64_t)row_dst[row] * kCfK + lane];
-                    }
-                    const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), jb + u));
-                    const float err = r - wave_sum_all(x[u] * xv);
-                    acc = fmaf(err, x[u], acc);
-                    sq += (double)err * (double)err;
+        for (int j = 0; j < kGroupBatch; ++j) {
+            if (a + o + j < b) {
+                if (wv[j] & EdgeWord<W>::kFlag) {  // a row starts: the open row is complete
+                    if (seen) reinterpret_cast<float4 *>(partial)[(int64_t)row * kGroup + sub] = acc;
+                    else fix_head[G][sub] = acc;  // the part's head: the row open at its start
+                    seen = 1;
+                    ++row;
+                    acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    xv = X4[(int64_t)row_dst[row] * kGroup + sub];
                 }
+                const float err = rv[j] - row16_sum(dot4(x[j], xv));
+                acc.x = fmaf(err, x[j].x, acc.x);
+                acc.y = fmaf(err, x[j].y, acc.y);
+                acc.z = fmaf(err, x[j].z, acc.z);
+                acc.w = fmaf(err, x[j].w, acc.w);
+                sqf = fmaf(err, err, sqf);
             }
         }
+        sq += (double)sqf;  // FP32 over at most kGroupBatch errors, FP64 across windows
+        sqf = 0.0f;
+        word = word_n;
+        val = val_n;
     }
-    fix_head[w][lane] = seen ? head : acc;
-    fix_last[w][lane] = acc;
-    if (lane == 0) {
-        fix_row[w] = row;
-        fix_has[w] = seen;
-        red_sq[w] = sq;
+    if (!seen) fix_head[G][sub] = acc;  // no row closed: all of it continues the open row
+    fix_last[G][sub] = acc;
+    if (sub == 0) {
+        fix_row[G] = row;
+        fix_has[G] = seen;
+        red_sq[G] = sq;
     }
     __syncthreads();
-    if (fix_has[w]) {
-        float tot = fix_last[w][lane];
-        for (int x2 = w + 1; x2 < kCfWaves; ++x2) {
-            tot += fix_head[x2][lane];
+    if (fix_has[G]) {
+        float4 tot = fix_last[G][sub];
+        for (int x2 = G + 1; x2 < kCfGroups; ++x2) {
+            const float4 h = fix_head[x2][sub];
+            tot.x += h.x;
+            tot.y += h.y;
+            tot.z += h.z;
+            tot.w += h.w;
             if (fix_has[x2]) break;
         }
-        partial[(int64_t)fix_row[w] * kCfK + lane] = tot;
+        reinterpret_cast<float4 *>(partial)[(int64_t)fix_row[G] * kGroup + sub] = tot;
     }
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int x2 = 0; x2 < kCfWaves; ++x2) s += red_sq[x2];
-        tile_sq[t] = s;
+        double s2 = 0.0;
+        for (int x2 = 0; x2 < kCfGroups; ++x2) s2 += red_sq[x2];
+        tile_sq[t] = s2;
     }
 }
 
