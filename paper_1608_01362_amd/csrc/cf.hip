@@ -13,6 +13,7 @@
 // (256 bytes per vertex). Edge values travel in the segmented edge order,
 // produced once by k_edge_values.
 #include "common.h"
+#include "rowgroup.h"
 
 namespace cagra {
 
@@ -86,13 +87,8 @@ cagra_status launch_edge_values(const cagra_graph *g, const cagra_segments *seg,
 
 // ---------------------------------------------------------------- gather
 
-// Lanes of an edge group: the 16 lanes of one DPP row, 4 factors each (one
-// 16-byte load of a 256-byte vertex row per lane).
-constexpr int kGroup = 16;
-constexpr int kGroupsPerWave = kWave / kGroup;
 constexpr int kCfGroups = kCfWaves * kGroupsPerWave;
 constexpr int kGroupBatch = 4;  // edges per window: source rows a group loads together
-static_assert(kGroupBatch == 4, "the broadcasts below are written out for four edges");
 static_assert(kCfK == kGroup * 4, "four factors per lane of a group");
 
 // Sum over the 16 lanes of a DPP row, returned to each of them: pairs, quads
@@ -103,13 +99,6 @@ __device__ __forceinline__ float row16_sum(float x) {
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf, 0xf, false));  // half mirror
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf, 0xf, false));  // mirror
     return x;
-}
-
-// Lane j of each 16-lane group, to every lane of the group (ds_swizzle bit
-// mode: lane id bits 4 kept, bits 0-3 set to j, within each 32-lane half).
-template <int J>
-__device__ __forceinline__ int32_t group_bcast(int32_t v) {
-    return __builtin_amdgcn_ds_swizzle(v, 0x10 | (J << 5));
 }
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) {
@@ -148,36 +137,9 @@ __global__ __launch_bounds__(kCfThreads) void k_cf_gather(
     if (w0 > e1) w0 = e1;
     int64_t w1 = w0 + sl;
     if (w1 > e1) w1 = e1;
-    // the group's part [a, b) of the share
-    const int64_t gl = (w1 - w0 + kGroupsPerWave - 1) / kGroupsPerWave;
-    int64_t a = w0 + g * gl;
-    if (a > w1) a = w1;
-    int64_t b = a + gl;
-    if (b > w1) b = w1;
-    // row starts in [w0, a) for each group: the wave counts them in 64-edge
-    // chunks up to the last group's start
-    int32_t before = 0;
-    {
-        int64_t a_last = w0 + (kGroupsPerWave - 1) * gl;
-        if (a_last > w1) a_last = w1;
-        int32_t c1 = 0, c2 = 0, c3 = 0;
-        for (int64_t c0 = w0; c0 < a_last; c0 += kWave) {
-            const int64_t e = c0 + lane;
-            const bool f = e < a_last && ((uint32_t)edge_src[e < a_last ? e : c0] & EdgeWord<W>::kFlag);
-            const uint64_t m = __ballot(f);
-            // positions below each group's start
-            const int64_t s1 = w0 + gl - c0, s2 = w0 + 2 * gl - c0, s3 = w0 + 3 * gl - c0;
-            auto below = [&](int64_t n) -> int32_t {
-                if (n <= 0) return 0;
-                if (n >= 64) return __builtin_popcountll(m);
-                return __builtin_popcountll(m & ((1ull << n) - 1ull));
-            };
-            c1 += below(s1);
-            c2 += below(s2);
-            c3 += below(s3);
-        }
-        before = g == 0 ? 0 : (g == 1 ? c1 : (g == 2 ? c2 : c3));
-    }
+    const GroupPart part = group_part<W>(edge_src, w0, w1, g, lane);
+    const int64_t a = part.a, b = part.b, gl = part.len;
+    const int32_t before = part.before;
     int32_t row = span_row[(int64_t)t * kCfWaves + w] - 1 + before;  // row open at the part's start
     int32_t seen = 0;
     float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f), xv = acc;
@@ -190,16 +152,12 @@ __global__ __launch_bounds__(kCfThreads) void k_cf_gather(
 
     // lane j < kGroupBatch of the group holds the word and rating of edge
     // o + j of the current window; the next window's are loaded one window ahead
-    auto edge_at = [&](int64_t o) -> int64_t {
-        const int64_t ej = a + o + (sub & (kGroupBatch - 1));
-        const int64_t ec = ej < b ? ej : (a < b ? a : e0);
-        return ec < e1 ? ec : e0;
-    };
-    int64_t ecur = edge_at(0);
+    static_assert(kGroupBatch == 4, "windows of four edges (group_window_edge, group_bcast4)");
+    int64_t ecur = group_window_edge(part, 0, sub, e0, e1);
     int32_t word = (int32_t)(uint32_t)edge_src[ecur];
     float val = vals[ecur];
     for (int64_t o = 0; o < gl; o += kGroupBatch) {
-        const int64_t enxt = edge_at(o + kGroupBatch);
+        const int64_t enxt = group_window_edge(part, o + kGroupBatch, sub, e0, e1);
         const int32_t word_n = (int32_t)(uint32_t)edge_src[enxt];
         const float val_n = vals[enxt];
         uint32_t wv[kGroupBatch];
@@ -208,10 +166,8 @@ __global__ __launch_bounds__(kCfThreads) void k_cf_gather(
         const int32_t vi = __float_as_int(val);
 #pragma unroll
         for (int j = 0; j < kGroupBatch; ++j) {
-            wv[j] = (uint32_t)(j == 0 ? group_bcast<0>(word) : j == 1 ? group_bcast<1>(word)
-                                : j == 2 ? group_bcast<2>(word) : group_bcast<3>(word));
-            rv[j] = __int_as_float(j == 0 ? group_bcast<0>(vi) : j == 1 ? group_bcast<1>(vi)
-                                   : j == 2 ? group_bcast<2>(vi) : group_bcast<3>(vi));
+            wv[j] = (uint32_t)group_bcast4(word, j);
+            rv[j] = __int_as_float(group_bcast4(vi, j));
             x[j] = xs[(int64_t)(wv[j] & EdgeWord<W>::kIndex) * kGroup];
         }
 #pragma unroll
