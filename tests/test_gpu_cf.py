@@ -114,3 +114,26 @@ def test_graph_without_ratings(cagra):
     st.step(0.1, 0.5)
     assert np.allclose(st.x_now.cpu().numpy(), X0 * (1 - 0.1 * 0.5), rtol=1e-6)
     assert float(st.sq.item()) == 0.0
+
+
+@pytest.mark.parametrize("N,B,T", [(1, 4, 64), (2, 64, 64), (37, 7, 100), (4096, 512, 64)])
+def test_one_step_short_rows_and_parts(cagra, N, B, T):
+    """Segments of one or two sources (rows of one or two edges: nearly every
+    edge starts a row) and 64-edge tiles (a wave's share splits into parts of
+    zero to a few edges): the gather's per-part open rows and the completion of
+    rows across parts, within the same FP32 bound."""
+    import torch
+    g, vals, U, I = graphgen.bipartite_ratings(7, 4, 4, 2)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, N, B, T)
+    sv = cagra.segment_edge_values(dg, seg, torch.from_numpy(vals).cuda())
+    X0 = cf.init_factors(g.V, K, 9, scale=0.3)
+    st = cagra.CFState(dg, seg, sv, torch.from_numpy(X0).cuda())
+    gamma, lam = 0.01, 0.05
+    st.step(gamma, lam)
+    got = st.x_now.cpu().numpy().astype(np.float64)
+    X64 = X0.astype(np.float64)
+    want, sq = cf.step(g, vals, X64, gamma, lam)
+    tol = step_bound(g, vals, X64, gamma) + 2.0 ** -23 * np.abs(want) + 1e-12
+    assert np.all(np.abs(got - want) <= tol), float(np.max(np.abs(got - want) / tol))
+    assert float(st.sq.item()) == pytest.approx(sq, rel=1e-5)
