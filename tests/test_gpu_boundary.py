@@ -276,3 +276,35 @@ def test_labelprop_solve_without_edges(cagra):
     seg = cagra.build_segments(dg, 16, 16, 64)
     lab, it = cagra.labelprop(seg)
     assert it == 1 and np.array_equal(lab.cpu().numpy(), np.arange(40))
+
+
+def test_labelprop_solve_from_given_labels(cagra):
+    """cagra_labelprop_solve from a caller's labelling (a random permutation):
+    the same labels and count as the waiting loop from that labelling, and
+    the fixed point gives every vertex the smallest start label of its
+    component."""
+    import torch
+    g = graphgen.symmetrize(graphgen.rmat_graph(11, 4, 8))
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 512, 256, 1024)
+    lab0 = torch.from_numpy(np.random.default_rng(3).permutation(g.V).astype(np.int32)).cuda()
+    lab, it = cagra.labelprop(seg, labels0=lab0)
+    cur, nxt = lab0.clone(), torch.empty_like(lab0)
+    partial = torch.empty(max(seg.Q, 1), dtype=torch.int32, device="cuda")
+    changed = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = cagra.iter_workspace(seg)
+    n = 0
+    while True:
+        cagra.labelprop_iter(seg, cur, partial, nxt, changed, ws)
+        cur, nxt = nxt, cur
+        n += 1
+        if int(changed.item()) == 0:
+            break
+    assert it == n and torch.equal(lab, cur)
+    comp, _ = oracle.labelprop(g)  # component ids: the smallest vertex id of each component
+    l0 = lab0.cpu().numpy()
+    want = np.empty(g.V, dtype=np.int64)
+    for c in np.unique(comp):
+        members = comp == c
+        want[members] = l0[members].min()
+    assert np.array_equal(lab.cpu().numpy().astype(np.int64), want)

@@ -142,3 +142,24 @@ def test_ppr_solve_equals_the_waiting_loop(cagra, tol, max_iters, every):
         for j in range(0, 64, 21):
             want = oracle.ppr(g, int(seeds[j]), 200)
             assert np.abs(R[:, j] - want).sum() <= 0.85 / 0.15 * tol + 1e-6, j
+
+
+def test_ppr_solve_partial_batch_matches_full_batch_columns(cagra):
+    """cagra_ppr_solve over 5 seeds: the columns stop where the 5-column
+    waiting loop stops, columns past ncols stay zero, and each column equals
+    the same column of a 64-seed solve stopped at the same iteration."""
+    import torch
+    g = graphgen.rmat_graph(11, 16, 9)
+    dg = cagra.DeviceGraph.from_host(g)
+    seg = cagra.build_segments(dg, 512, 256, 1024)
+    seeds = seeds_for(g, 64, 5)
+    st5 = cagra.PPRState(dg, seg, seeds[:5])
+    r5 = st5.solve(tol=1e-6)
+    full = st5.rank[st5.cur].view(g.V, 64)
+    assert r5.converged and torch.count_nonzero(full[:, 5:]) == 0
+    st64 = cagra.PPRState(dg, seg, seeds)
+    st64.start()
+    for _ in range(r5.iters):
+        st64.step()
+    assert torch.equal(st5.ranks(), st64.ranks()[:, :5])  # columns are independent lanes
+    assert float(st64.scalars_now[:5, 1].max().item()) == r5.residual
