@@ -226,7 +226,15 @@ __device__ __forceinline__ void load_chunk(v4i (&r)[kLoads<W>], __amdgpu_buffer_
     for (int j = 0; j < kLoads<W>; ++j) r[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, off + 16 * j, 0, kNonTemporal);
 }
 
-constexpr int kStages = 4;  // chunks in flight per wave (three ahead of the one processed)
+// Chunks in flight per wave (all but one ahead of the one processed). The
+// LDS-staged gather with 16-bit words runs one workgroup per CU whatever its
+// registers, so it keeps STAGED16_DEPTH chunks in flight; the other forms keep
+// four, which holds them within the registers of two workgroups per CU.
+#ifndef STAGED16_DEPTH
+#define STAGED16_DEPTH 8
+#endif
+template <bool STAGED, typename W>
+constexpr int kStages = (STAGED && sizeof(W) == 2) ? STAGED16_DEPTH : 4;
 
 template <class Op, typename VT, bool STAGED, typename W>
 __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int64_t Q,
@@ -280,15 +288,16 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
     const int64_t len = w1 - ebase;
     const int32_t share = (int32_t)(w1 - w0);
     const uint32_t lane_off = (uint32_t)(lane * kEPT * kWB);
-    v4i R[kStages][kLoads<W>];
+    constexpr int kSt = kStages<STAGED, W>;
+    v4i R[kSt][kLoads<W>];
 #pragma unroll
-    for (int c = 0; c < kStages - 1; ++c) load_chunk<W>(R[c], ein, (uint32_t)(c * kChunk * kWB) + lane_off);
-    for (int64_t cc = 0; cc < len; cc += kStages * kChunk) {
+    for (int c = 0; c < kSt - 1; ++c) load_chunk<W>(R[c], ein, (uint32_t)(c * kChunk * kWB) + lane_off);
+    for (int64_t cc = 0; cc < len; cc += kSt * kChunk) {
 #pragma unroll
-        for (int c = 0; c < kStages; ++c) {
+        for (int c = 0; c < kSt; ++c) {
             if (cc + c * kChunk >= len) break;  // uniform: len and cc are wave-wide
-            load_chunk<W>(R[(c + kStages - 1) % kStages], ein,
-                          (uint32_t)((cc + (c + kStages - 1) * kChunk) * kWB) + lane_off);
+            load_chunk<W>(R[(c + kSt - 1) % kSt], ein,
+                          (uint32_t)((cc + (c + kSt - 1) * kChunk) * kWB) + lane_off);
             const int32_t rel0 = (int32_t)(ebase + cc + c * kChunk - w0);
             if (rel0 >= 0 && rel0 + kChunk <= share)
                 process_chunk<Op, VT, STAGED, W, true>(R[c], rel0, share, seg_vals, gvals, stage, out, S);
