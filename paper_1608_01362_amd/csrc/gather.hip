@@ -226,17 +226,17 @@ __device__ __forceinline__ void load_chunk(v4i (&r)[kLoads<W>], __amdgpu_buffer_
     for (int j = 0; j < kLoads<W>; ++j) r[j] = __builtin_amdgcn_raw_buffer_load_b128(ein, off + 16 * j, 0, kNonTemporal);
 }
 
-// Chunks in flight per wave (all but one ahead of the one processed). The
-// LDS-staged gather with 16-bit words runs one workgroup per CU whatever its
-// registers, so it keeps STAGED16_DEPTH chunks in flight; the other forms keep
-// four, which holds them within the registers of two workgroups per CU.
-#ifndef STAGED16_DEPTH
-#define STAGED16_DEPTH 8
-#endif
-template <bool STAGED, typename W>
-constexpr int kStages = (STAGED && sizeof(W) == 2) ? STAGED16_DEPTH : 4;
+// Chunks of edge words each wave keeps in flight (all but one ahead of the one
+// processed). The LDS-staged gather with 16-bit words over long tiles keeps
+// kStagesDeep: its shares are dozens of chunks long and it runs one workgroup
+// per CU whatever its registers. Short tiles (the multi-graph runs, small
+// graphs) and the other forms keep kStagesDefault: there a deeper prologue
+// mostly loads past the share, or two workgroups per CU must fit in registers.
+constexpr int kStagesDeep = 8;
+constexpr int kStagesDefault = 4;
+constexpr int32_t kDeepTileEdges = 131072;  // tiles at least this long take kStagesDeep
 
-template <class Op, typename VT, bool STAGED, typename W>
+template <class Op, typename VT, bool STAGED, typename W, int DEPTH>
 __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int64_t Q,
                                             const int32_t *__restrict__ tile_edge,
                                             const int32_t *__restrict__ tile_seg,
@@ -288,7 +288,7 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
     const int64_t len = w1 - ebase;
     const int32_t share = (int32_t)(w1 - w0);
     const uint32_t lane_off = (uint32_t)(lane * kEPT * kWB);
-    constexpr int kSt = kStages<STAGED, W>;
+    constexpr int kSt = DEPTH;
     v4i R[kSt][kLoads<W>];
 #pragma unroll
     for (int c = 0; c < kSt - 1; ++c) load_chunk<W>(R[c], ein, (uint32_t)(c * kChunk * kWB) + lane_off);
@@ -331,7 +331,7 @@ __device__ __forceinline__ void gather_tile(const W *__restrict__ edge_src, int6
     }
 }
 
-template <class Op, typename VT, bool STAGED, typename W>
+template <class Op, typename VT, bool STAGED, typename W, int DEPTH>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
     const W *__restrict__ edge_src, int64_t E, int64_t Q, const int32_t *__restrict__ tile_edge,
     const int32_t *__restrict__ tile_seg, const int32_t *__restrict__ span_row, const VT *__restrict__ values,
@@ -339,8 +339,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     const uint32_t *__restrict__ seg_active) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     (void)E;
-    gather_tile<Op, VT, STAGED, W>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
-                                   xcd_remap(blockIdx.x, ntiles), partial, smem, seg_active);
+    gather_tile<Op, VT, STAGED, W, DEPTH>(edge_src, Q, tile_edge, tile_seg, span_row, values, V, N,
+                                          xcd_remap(blockIdx.x, ntiles), partial, smem, seg_active);
 }
 
 // Persistent form over many graphs: workgroups stride over a global tile list.
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_multi_gather(const MultiDesc
         __syncthreads();  // LDS reuse across tiles
         const int gi = tile_graph[gt];
         const MultiDesc &d = desc[gi];
-        gather_tile<OpSum, float, true, uint16_t>(static_cast<const uint16_t *>(d.edge_src), d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
+        gather_tile<OpSum, float, true, uint16_t, kStagesDefault>(static_cast<const uint16_t *>(d.edge_src), d.Q, d.tile_edge, d.tile_seg, d.tile_span_row,
                                         d.contrib[parity], d.V, d.N, (int)(gt - d.tile_base), d.partial, smem,
                                         nullptr);
     }
@@ -372,7 +372,9 @@ template <class Op, typename VT, bool STAGED, typename W>
 static cagra_status launch_gather_w(const cagra_segments *seg, const VT *values, typename Op::T *partial,
                                     const uint32_t *seg_active, hipStream_t st) {
     if (seg->ntiles == 0) return CAGRA_OK;
-    auto kern = k_gather<Op, VT, STAGED, W>;
+    auto kern = k_gather<Op, VT, STAGED, W, kStagesDefault>;
+    if constexpr (STAGED && sizeof(W) == 2)
+        if (seg->tile_edges >= kDeepTileEdges) kern = k_gather<Op, VT, STAGED, W, kStagesDeep>;
     const size_t lds = kStageBytes + (STAGED ? (size_t)seg->N * sizeof(VT) : 0);
     if (cagra_status a_ = ensure_dynamic_lds((const void *)kern)) return a_;
     kern<<<seg->ntiles, kGatherThreads, lds, st>>>(static_cast<const W *>(seg->edge_src), seg->E, seg->Q,
