@@ -49,6 +49,11 @@ constexpr int kUpdThreads = 256;
 // expand items per XCD group (R-MAT 25 push iteration: 4 -> 2.814, 8 -> 2.790,
 // 16 -> 2.783 ms; fewer block boundaries cross XCDs)
 constexpr int32_t kExpandGroup = 16;
+constexpr int kExpandStage = 8;    // staged source values per thread per batch
+// windows per pass of the expand (R-MAT 25 push iteration, N = 20,480: 8 -> 2.786,
+// 16 -> 2.731 ms with the batched staging; non-temporal stores of the values
+// 3.15 ms; 32 windows need more than 64 VGPRs and halve the occupancy)
+constexpr int kExpandUnroll = 16;
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
@@ -151,7 +156,17 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
 
     const int64_t vb = (int64_t)b * B;
     const int32_t nv = (int32_t)((int64_t)V - vb < B ? (int64_t)V - vb : B);
-    for (int i = threadIdx.x; i < nv; i += kMergeThreads) xs[i] = x[vb + i];
+    // all of a thread's loads are issued before its first LDS write (nv >= 1)
+    for (int i0 = 0; i0 < nv; i0 += kExpandStage * kMergeThreads) {
+        uint32_t v[kExpandStage];
+#pragma unroll
+        for (int u = 0; u < kExpandStage; ++u) v[u] = x[vb + min(i0 + u * kMergeThreads + (int)threadIdx.x, nv - 1)];
+#pragma unroll
+        for (int u = 0; u < kExpandStage; ++u) {
+            const int i = i0 + u * kMergeThreads + (int)threadIdx.x;
+            if (i < nv) xs[i] = v[u];
+        }
+    }
     // the barrier inside load_block_ranges also publishes the staged values
     const int32_t P = load_block_ranges(block_ptr, b, k, ofs, pre, tmp);
     const int32_t F0 = (int32_t)((int64_t)P * j / S), F1 = (int32_t)((int64_t)P * (j + 1) / S);
@@ -163,11 +178,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
     if (fa >= fb) return;  // uniform over the wave
     int32_t sw = __builtin_amdgcn_readfirstlane(run_of(pre, k, fa));
     int32_t i_safe = __builtin_amdgcn_readfirstlane(ofs[sw]) + fa;
-    for (int32_t f0 = fa; f0 < fb; f0 += kWave * kUnroll) {
-        int32_t idx[kUnroll], d[kUnroll];
+    for (int32_t f0 = fa; f0 < fb; f0 += kWave * kExpandUnroll) {
+        int32_t idx[kExpandUnroll], d[kExpandUnroll];
         int32_t sl = WIDE ? run_of(pre, k, f0) : 0;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kExpandUnroll; ++u) {
             const int32_t fs = f0 + u * kWave;
             const int32_t f = fs + lane;
             const bool valid = f < fb;
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_push_expand(const uint16_t *_
             idx[u] = valid ? i : -1;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < kExpandUnroll; ++u)
             if (idx[u] >= 0) vals[idx[u]] = xs[d[u]];
     }
 }
