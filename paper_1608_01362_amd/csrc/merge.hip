@@ -67,6 +67,40 @@ __device__ __forceinline__ void ord_apply(typename Op::T *acc, typename Op::T *c
     }
 }
 
+// Applies the entries of one loaded batch (lane entries lo + j * 64 + lane
+// below hi). A range's entries have distinct destinations, so every
+// accumulator of the batch is read before any is written: one LDS round trip
+// per batch instead of one per entry (R-MAT 25 FP32 sum: 1.80 -> 1.70 ms).
+// Entries past the range read the destination of the range's first entry and
+// write nothing.
+template <class Op, bool COMP>
+__device__ __forceinline__ void ord_apply_batch(typename Op::T *acc, typename Op::T *cmp,
+                                                const OrdBatch<typename Op::T> &q, int32_t lo, int32_t hi,
+                                                int lane) {
+    using T = typename Op::T;
+    T a[kOrdLoads], cm[kOrdLoads];
+#pragma unroll
+    for (int j = 0; j < kOrdLoads; ++j) {
+        a[j] = acc[q.d[j]];
+        if (COMP) cm[j] = cmp[q.d[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kOrdLoads; ++j) {
+        if (lo + j * kWave + lane >= hi) continue;
+        const T x = q.x[j];
+        if (COMP) {
+            // the Neumaier step of ord_apply on the values read above
+            const float sacc = a[j];
+            const float tsum = sacc + x;
+            if (fabsf(sacc) >= fabsf(x)) cmp[q.d[j]] = cm[j] + ((sacc - tsum) + x);
+            else cmp[q.d[j]] = cm[j] + ((x - tsum) + sacc);
+            acc[q.d[j]] = tsum;
+        } else {
+            acc[q.d[j]] = Op::apply(a[j], x);
+        }
+    }
+}
+
 template <class Op, bool COMP, bool STAGED>
 __global__ __launch_bounds__(64) void k_merge_ordered(const uint16_t *__restrict__ row_dst_lo,
                                                       const int32_t *__restrict__ block_ptr,
@@ -159,9 +193,7 @@ __global__ __launch_bounds__(64) void k_merge_ordered(const uint16_t *__restrict
                     more = false;
                     break;
                 }
-#pragma unroll
-                for (int j = 0; j < kOrdLoads; ++j)
-                    if (qlo[c] + j * kWave + lane < qhi[c]) ord_apply<Op, COMP>(acc, cmp, q[c].d[j], q[c].x[j]);
+                ord_apply_batch<Op, COMP>(acc, cmp, q[c], qlo[c], qhi[c], lane);
                 // the rest of a long range, still before the next subgraph
                 for (int32_t i = qlo[c] + kOrdBatch + lane; i < qhi[c]; i += 64)
                     ord_apply<Op, COMP>(acc, cmp, row_dst_lo[i], partial[i]);
